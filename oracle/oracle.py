@@ -1,0 +1,435 @@
+"""Plain FP64 CPU oracle of the Directional TSDF hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may import this
+module.  It shares no code with the HIP library; both sides only consume the seeded inputs of
+``synth``.
+
+* Integration and rendering (Sec. 3, Sec. 4) live in ``dtsdf_oracle.cpp`` (plain C++ in
+  double precision) and are wrapped here through ctypes.
+* Registration (Sec. 5 and Sec. 6) is written here with numpy in float64: projective data
+  association, the point-to-plane residual (eq. geometric_ICP), its Jacobian
+  (eq. ICP_geometric_dx; Sim(3): eq. sim3_derivative), the normal equations
+  (eq. ICP_Hessian), the Cholesky solve (eq. ICP_solution) and the left-multiplied update
+  (eq. deltaT_update).  The exponential maps are the matrix exponential of the 4x4 generator
+  (scipy.linalg.expm), the plain definition of exp on se(3) and sim(3).
+
+Parameters are passed as float32-representable values (``f32``) so that both implementations
+compare against exactly the same thresholds.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+import scipy.linalg
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "dtsdf_oracle.cpp")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C++ oracle (g++, OpenMP) next to its source."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c++17",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+def f32(x: float) -> float:
+    return float(np.float32(x))
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("voxel", ctypes.c_double), ("tau", ctypes.c_double),
+                ("theta", ctypes.c_double), ("w_carve", ctypes.c_double),
+                ("w_max", ctypes.c_double), ("w_min", ctypes.c_double),
+                ("step", ctypes.c_double), ("dense", ctypes.c_int32),
+                ("dense_lo", ctypes.c_int32 * 3), ("dense_hi", ctypes.c_int32 * 3),
+                ("with_color", ctypes.c_int32), ("single_direction", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("borderline_req", ctypes.c_int64),
+                ("new_bricks", ctypes.c_int64), ("updated", ctypes.c_int64),
+                ("carved", ctypes.c_int64)]
+
+
+class _RenderCfg(ctypes.Structure):
+    _fields_ = [("z_near", ctypes.c_double), ("z_far", ctypes.c_double),
+                ("eps_f", ctypes.c_double), ("eps_x", ctypes.c_double),
+                ("eps_s", ctypes.c_double), ("eps_root", ctypes.c_double),
+                ("classify", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+
+
+def _declare(L):
+    L.orc_create.restype = _P
+    L.orc_create.argtypes = [ctypes.POINTER(_Params)]
+    L.orc_destroy.argtypes = [_P]
+    L.orc_num_bricks.restype = ctypes.c_int64
+    L.orc_num_bricks.argtypes = [_P]
+    L.orc_integrate.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                                ctypes.c_double, ctypes.POINTER(_Stats)]
+    L.orc_requests.restype = ctypes.c_int64
+    L.orc_requests.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                               ctypes.c_double, _P, _P, _P, ctypes.c_int64]
+    L.orc_export.restype = ctypes.c_int64
+    L.orc_export.argtypes = [_P] * 7
+    L.orc_import.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
+    L.orc_render.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(_RenderCfg),
+                             _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_eval.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
+    L.orc_brick_key.argtypes = [_P, ctypes.c_int64, _P]
+    L.orc_w_dir.restype = ctypes.c_double
+    L.orc_w_dir.argtypes = [ctypes.POINTER(_Params), _P, ctypes.c_int]
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"], "arrays passed to the oracle must be contiguous"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------------------
+# Map parameters.  Values the paper does not give are proposals (see the design notes).
+# ----------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class MapParams:
+    voxel: float
+    tau: float
+    theta: float = math.pi / 3.0
+    w_carve: float = 0.1
+    w_max: float = 63.75
+    w_min: float = 1e-4
+    step: Optional[float] = None            # default: half a voxel
+    dense_lo: Optional[Sequence[int]] = None
+    dense_hi: Optional[Sequence[int]] = None
+    with_color: bool = True
+    single_direction: bool = False
+
+    def c_struct(self) -> _Params:
+        p = _Params()
+        p.voxel = f32(self.voxel)
+        p.tau = f32(self.tau)
+        p.theta = f32(self.theta)
+        p.w_carve = f32(self.w_carve)
+        p.w_max = f32(self.w_max)
+        p.w_min = f32(self.w_min)
+        p.step = f32(self.step if self.step is not None else 0.5 * self.voxel)
+        p.dense = 1 if self.dense_lo is not None else 0
+        for k in range(3):
+            p.dense_lo[k] = int(self.dense_lo[k]) if self.dense_lo is not None else 0
+            p.dense_hi[k] = int(self.dense_hi[k]) if self.dense_hi is not None else 0
+        p.with_color = int(self.with_color)
+        p.single_direction = int(self.single_direction)
+        return p
+
+
+def w_dir(params: MapParams, n: Sequence[float], d: int) -> float:
+    """Direction membership weight of unit normal ``n`` for direction ``d`` (X+,X-,Y+,...)."""
+    cp = params.c_struct()
+    nn = np.ascontiguousarray(n, np.float64)
+    return lib().orc_w_dir(ctypes.byref(cp), _ptr(nn), int(d))
+
+
+@dataclasses.dataclass
+class RenderOut:
+    depth: np.ndarray
+    vertex: np.ndarray
+    normal: np.ndarray
+    rgba: np.ndarray
+    mask: np.ndarray
+    flags: np.ndarray
+    khit: np.ndarray
+    thit: np.ndarray
+    touched: Optional[np.ndarray] = None
+
+
+# Grazing flag bits returned by render()
+NEAR_ZERO, NEAR_FACE, BRANCH, AMBIGUOUS, ROOT_FACE = 1, 2, 4, 8, 16
+
+
+class OracleMap:
+    """A DTSDF map held by the C++ oracle."""
+
+    def __init__(self, params: MapParams):
+        self.params = params
+        self._cp = params.c_struct()
+        self._h = lib().orc_create(ctypes.byref(self._cp))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    @property
+    def num_bricks(self) -> int:
+        return int(lib().orc_num_bricks(self._h))
+
+    def integrate(self, depth: np.ndarray, rgb: Optional[np.ndarray], cam, T_wc: np.ndarray,
+                  depth_scale: float = 1.0) -> dict:
+        d = np.ascontiguousarray(depth, np.float32)
+        c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        T = np.ascontiguousarray(T_wc, np.float64)
+        st = _Stats()
+        lib().orc_integrate(self._h, _ptr(d), _ptr(c), d.shape[1], d.shape[0], cam.fx, cam.fy,
+                            cam.cx, cam.cy, _ptr(T), f32(depth_scale), ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+    def requests(self, depth: np.ndarray, cam, T_wc: np.ndarray, depth_scale: float = 1.0):
+        """(keys n x 4, borderline flags, allocating flags) of one frame's block requests."""
+        d = np.ascontiguousarray(depth, np.float32)
+        T = np.ascontiguousarray(T_wc, np.float64)
+        cap = d.size * 6 * 64
+        keys = np.zeros((cap, 4), np.int32)
+        border = np.zeros(cap, np.uint8)
+        alloc = np.zeros(cap, np.uint8)
+        n = lib().orc_requests(self._h, _ptr(d), d.shape[1], d.shape[0], cam.fx, cam.fy, cam.cx,
+                               cam.cy, _ptr(T), f32(depth_scale), _ptr(keys), _ptr(border),
+                               _ptr(alloc), cap)
+        assert n <= cap
+        return keys[:n], border[:n], alloc[:n]
+
+    def export(self) -> dict:
+        n = self.num_bricks
+        out = dict(keys=np.zeros((n, 4), np.int32), sdf=np.zeros((n, 512), np.float32),
+                   w=np.zeros((n, 512), np.float32), rgb=np.zeros((n, 512, 3), np.uint8),
+                   wc=np.zeros((n, 512), np.float32), border=np.zeros((n, 512), np.uint8))
+        lib().orc_export(self._h, _ptr(out["keys"]), _ptr(out["sdf"]), _ptr(out["w"]),
+                         _ptr(out["rgb"]), _ptr(out["wc"]), _ptr(out["border"]))
+        return out
+
+    def load(self, blob: dict) -> None:
+        keys = np.ascontiguousarray(blob["keys"], np.int32)
+        sdf = np.ascontiguousarray(blob["sdf"], np.float32)
+        w = np.ascontiguousarray(blob["w"], np.float32)
+        rgb = blob.get("rgb")
+        wc = blob.get("wc")
+        rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        wc = None if wc is None else np.ascontiguousarray(wc, np.float32)
+        lib().orc_import(self._h, keys.shape[0], _ptr(keys), _ptr(sdf), _ptr(w), _ptr(rgb),
+                         _ptr(wc))
+
+    def render(self, cam, T_wc: np.ndarray, *, pixels: Optional[np.ndarray] = None,
+               z_near: float = 0.2, z_far: float = 10.0, eps_f: float = 1e-5,
+               eps_x: float = 1e-6, eps_s: float = 1e-5, eps_root: float = 2e-6,
+               classify: bool = True, touched: bool = False) -> RenderOut:
+        """Render all pixels (or the (n,2) array of (u, v) ``pixels``).
+
+        With ``classify`` the grazing flags are computed (eps_f: |f| near zero; eps_x: voxel
+        distance to a cell face; eps_s: margin on thresholded weight factors; eps_root: metres
+        between the root and a cell face); without it only the plain render runs."""
+        if pixels is None:
+            vv, uu = np.mgrid[0:cam.height, 0:cam.width]
+            pixels = np.stack([uu.ravel(), vv.ravel()], axis=1)
+        pixels = np.asarray(pixels)
+        us = np.ascontiguousarray(pixels[:, 0], np.int32)
+        vs = np.ascontiguousarray(pixels[:, 1], np.int32)
+        n = us.shape[0]
+        o = RenderOut(depth=np.zeros(n), vertex=np.zeros((n, 3)), normal=np.zeros((n, 3)),
+                      rgba=np.zeros((n, 4), np.uint8), mask=np.zeros(n, np.uint8),
+                      flags=np.zeros(n, np.uint8), khit=np.zeros(n, np.int64),
+                      thit=np.zeros(n))
+        if touched:
+            o.touched = np.zeros(self.num_bricks, np.uint8)
+        cfg = _RenderCfg(f32(z_near), f32(z_far), eps_f, eps_x, eps_s, eps_root, int(classify))
+        T = np.ascontiguousarray(T_wc, np.float64)
+        lib().orc_render(self._h, n, _ptr(us), _ptr(vs), cam.fx, cam.fy, cam.cx, cam.cy,
+                         _ptr(T), ctypes.byref(cfg), _ptr(o.depth), _ptr(o.vertex),
+                         _ptr(o.normal), _ptr(o.rgba), _ptr(o.mask), _ptr(o.flags),
+                         _ptr(o.khit), _ptr(o.thit), _ptr(o.touched))
+        return o
+
+    def eval(self, xs: np.ndarray, rs: np.ndarray):
+        """Combined SDF f at world points xs (n,3) for unit rays rs (n,3): (f, defined, fallback)."""
+        xs = np.ascontiguousarray(xs, np.float64)
+        rs = np.ascontiguousarray(np.broadcast_to(rs, xs.shape), np.float64)
+        n = xs.shape[0]
+        f = np.zeros(n)
+        d = np.zeros(n, np.uint8)
+        fb = np.zeros(n, np.uint8)
+        lib().orc_eval(self._h, n, _ptr(xs), _ptr(rs), _ptr(f), _ptr(d), _ptr(fb))
+        return f, d.astype(bool), fb.astype(bool)
+
+    def brick_key(self, i: int) -> np.ndarray:
+        k = np.zeros(4, np.int32)
+        lib().orc_brick_key(self._h, int(i), _ptr(k))
+        return k
+
+
+# ----------------------------------------------------------------------------------------
+# Registration: point-to-plane ICP in SE(3) and Sim(3) (Sec. 5, Sec. 6), numpy float64
+# ----------------------------------------------------------------------------------------
+
+def hat(w: np.ndarray) -> np.ndarray:
+    """The wedge operator of Sec. 5.3 (eq. wedge_operator)."""
+    return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+
+
+def generator(xi: np.ndarray) -> np.ndarray:
+    """4x4 Lie-algebra matrix of xi = (nu, omega) in se(3) or (nu, omega, sigma) in sim(3)."""
+    G = np.zeros((4, 4))
+    G[:3, :3] = hat(xi[3:6])
+    if len(xi) == 7:
+        G[:3, :3] += xi[6] * np.eye(3)
+    G[:3, 3] = xi[:3]
+    return G
+
+
+def exp_map(xi: np.ndarray) -> np.ndarray:
+    """exp: se(3) -> SE(3) or sim(3) -> Sim(3) as the matrix exponential of the generator.
+
+    For sim(3) this yields [[e^sigma exp(omega^), V nu], [0, 1]] (Sec. 6) with
+    V = int_0^1 e^(sigma u) exp(u omega^) du, the matrix the paper leaves undefined."""
+    return scipy.linalg.expm(generator(np.asarray(xi, np.float64)))
+
+
+def depth_pyramid(depth: np.ndarray, levels: int):
+    """Level l+1 pixel = mean of the 2x2 block of level l if all four are valid, else 0."""
+    out = [np.asarray(depth, np.float64)]
+    for _ in range(1, levels):
+        d = out[-1]
+        h, w = d.shape[0] // 2, d.shape[1] // 2
+        b = d[:2 * h, :2 * w].reshape(h, 2, w, 2)
+        ok = (b > 0).all(axis=(1, 3))
+        out.append(np.where(ok, b.mean(axis=(1, 3)), 0.0))
+    return out
+
+
+def vertex_normal_map(depth: np.ndarray, cam, depth_scale: float = 1.0):
+    """Camera-frame points (eq. reprojection) and cross-product normals facing the camera.
+
+    Returns V (H,W,3), N (H,W,3), valid-normal mask (H,W)."""
+    z = np.asarray(depth, np.float64) * depth_scale
+    H, W = z.shape
+    vv, uu = np.mgrid[0:H, 0:W].astype(np.float64)
+    V = np.stack([z * (uu - cam.cx) / cam.fx, z * (vv - cam.cy) / cam.fy, z], axis=-1)
+    pv = z > 0
+    N = np.zeros_like(V)
+    ok = np.zeros_like(pv)
+    dx = V[1:-1, 2:] - V[1:-1, :-2]
+    dy = V[2:, 1:-1] - V[:-2, 1:-1]
+    n = np.cross(dx, dy)
+    ln = np.linalg.norm(n, axis=-1)
+    inner = pv[1:-1, 1:-1] & pv[1:-1, 2:] & pv[1:-1, :-2] & pv[2:, 1:-1] & pv[:-2, 1:-1] & (ln > 0)
+    n = n / np.where(ln > 0, ln, 1.0)[..., None]
+    flip = (n * V[1:-1, 1:-1]).sum(-1) > 0
+    n = np.where(flip[..., None], -n, n)
+    N[1:-1, 1:-1] = np.where(inner[..., None], n, 0.0)
+    ok[1:-1, 1:-1] = inner
+    return V, N, ok
+
+
+@dataclasses.dataclass
+class IcpParams:
+    dist: float = 0.10                     # reject ||q - y|| above this [m]
+    angle_deg: float = 20.0                # reject normal angle above this
+    weight: str = "const"                  # "const" or "icp" (eq. ICP_weight)
+    z_min: float = 0.1
+
+
+def associate_reduce(live_V, live_N, live_ok, model_V, model_N, model_mask, cam_model,
+                     dT: np.ndarray, dim: int, params: IcpParams = IcpParams()):
+    """One Gauss-Newton linearisation around xi = 0 (Sec. 5).
+
+    Returns H (dim x dim), g (dim), error sum, inlier count.  H = sum w J J^T and
+    g = sum w J r (the factor 2 of eq. ICP_Hessian cancels in eq. ICP_solution)."""
+    P = live_V[live_ok].reshape(-1, 3)
+    Nl = live_N[live_ok].reshape(-1, 3)
+    R, t = dT[:3, :3], dT[:3, 3]
+    y = P @ R.T + t
+    nl = Nl @ R.T
+    # scale-aware rotation of normals: normalise after applying R (a Sim(3) dT has sR)
+    nl = nl / np.linalg.norm(nl, axis=1, keepdims=True)
+    pos = y[:, 2] > 0
+    zz = np.where(pos, y[:, 2], 1.0)
+    uf = cam_model.fx * y[:, 0] / zz + cam_model.cx
+    vf = cam_model.fy * y[:, 1] / zz + cam_model.cy
+    u = np.floor(uf + 0.5).astype(np.int64)
+    v = np.floor(vf + 0.5).astype(np.int64)
+    H_, W_ = model_mask.shape
+    inb = pos & (u >= 0) & (v >= 0) & (u < W_) & (v < H_)
+    u = np.where(inb, u, 0)
+    v = np.where(inb, v, 0)
+    has = inb & (model_mask[v, u] > 0)
+    q = model_V[v, u]
+    n = model_N[v, u]
+    diff = q - y
+    ok = has & (np.linalg.norm(diff, axis=1) <= params.dist) & \
+        ((n * nl).sum(1) >= math.cos(math.radians(params.angle_deg)))
+    y, n, diff = y[ok], n[ok], diff[ok]
+    r = (diff * n).sum(1)
+    J = np.concatenate([-n, -np.cross(y, n)], axis=1)
+    if dim == 7:
+        J = np.concatenate([J, -(n * y).sum(1, keepdims=True)], axis=1)
+    if params.weight == "icp":
+        z = P[ok][:, 2]
+        w = 1.0 / (z + (1.0 - params.z_min)) ** 2           # eq. ICP_weight
+    else:
+        w = np.ones(len(r))
+    H = (J * w[:, None]).T @ J
+    g = (J * w[:, None]).T @ r
+    return H, g, float((w * r * r).sum()), int(ok.sum())
+
+
+def solve_step(H: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """xi = -H^{-1} g via Cholesky (eq. ICP_solution)."""
+    c = scipy.linalg.cho_factor(H, lower=True)
+    return -scipy.linalg.cho_solve(c, g)
+
+
+def icp(live_depth: np.ndarray, live_cam, model_levels, dT0: np.ndarray, dim: int = 6,
+        iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
+        depth_scale: float = 1.0, min_inliers_per_dim: int = 64):
+    """Coarse-to-fine point-to-plane ICP.
+
+    model_levels[l] = (V, N, mask, cam) rendered at level l (model camera frame).
+    ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine.
+    Returns the final live->model transform and a per-iteration log."""
+    L = len(model_levels)
+    pyr = depth_pyramid(live_depth, L)
+    dT = np.array(dT0, np.float64)
+    log = []
+    for l in reversed(range(L)):
+        V, N, ok = vertex_normal_map(pyr[l], live_cam.level(l), depth_scale)
+        mV, mN, mM, mcam = model_levels[l]
+        for _ in range(iters[l]):
+            H, g, err, cnt = associate_reduce(V, N, ok, mV, mN, mM, mcam, dT, dim, params)
+            if cnt < min_inliers_per_dim * dim:
+                log.append(dict(level=l, status="degenerate", inliers=cnt))
+                break
+            xi = solve_step(H, g)
+            dT = exp_map(xi) @ dT                              # eq. deltaT_update
+            log.append(dict(level=l, inliers=cnt, err=err, step=float(np.linalg.norm(xi)),
+                            xi=xi))
+            if np.linalg.norm(xi) < min_step:
+                break
+    return dT, log
