@@ -1,0 +1,280 @@
+"""Benchmark: Directional-TSDF render throughput at 640x480 on one MI355X.
+
+Workload (the room configuration): a 4 x 4 x 3 m room with seeded boxes, spheres and 5 mm
+plates; 300 synthetic 640x480 RGB-D frames (f = 525, depth noise 0.0012 z^2) along a seeded
+smooth trajectory are fused into a sparse map of 8^3 blocks at 5 mm voxels (tau = 2 cm, 8-bit
+colour per direction).  One step renders depth + normal + colour at all 300 trajectory poses;
+`value` is rays per second over the timed steps (map and poses resident in device memory).
+
+Printed as one JSON line, with the roofline of the render kernel (algorithmic bytes per
+launch from the traced brick / bucket sets, divided by the launch duration measured with HIP
+events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
+Separately timed and reported beside it: integration ms/frame and three-level ICP ms/frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DTSDF render rays/s at 640x480 (% HBM roofline); served p50/p99 render+ICP ms"
+HBM_PEAK_GBS = 8000.0
+OUT_BYTES_PER_RAY = 4 + 12 + 4 + 1          # depth + normal + rgba + mask
+BRICK_MARCH_BYTES = 512 * 8                 # (sdf, w) float32 per voxel
+BRICK_COLOR_BYTES = 512 * 8                 # rgb code + colour weight per voxel
+BUCKET_BYTES = 32
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(kernel_src):
+    """HBM traffic per launch from the committed rocprofv3 summary, if it was taken on the
+    current kernel source."""
+    p = os.path.join(ROOT, "profiles", "render_room_640x480_traffic.txt")
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != source_hash(kernel_src):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-icp", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2301_12796_amd import dtsdf
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    # ---- inputs: scene, frames, fused map (setup, not timed as render) -----------------
+    cam = synth.scenes.ROOM_CAMERA
+    sc = synth.room_scene()
+    n = args.frames
+    params = dtsdf.Params(voxel_size=0.005, truncation=0.02, brick_capacity=1 << 20,
+                          hash_buckets=1 << 21)
+    gm = dtsdf.Map(params)
+    t_gen = 0.0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    integ_ms = 0.0
+    for k in range(n):
+        t = time.time()
+        f = synth.scenes.render_frame(sc, cam, synth.room_pose(k, n), noise="quadratic",
+                                      sigma=0.0012, seed=2000 + k, z_max=10.0, device="cuda")
+        depth = torch.from_numpy(f["depth"]).to(dev)
+        rgb = torch.from_numpy(f["rgb"]).to(dev)
+        t_gen += time.time() - t
+        ev0.record(stream)
+        gm.integrate(depth, rgb, cam, synth.room_pose(k, n))
+        ev1.record(stream)
+        ev1.synchronize()
+        integ_ms += ev0.elapsed_time(ev1)
+        if k % 50 == 0:
+            log(f"fused frame {k}/{n}: {gm.info()['bricks']} bricks")
+    info = gm.info()
+    log(f"map: {info['bricks']} bricks, {info['blocks']} blocks, dropped {info['dropped']}")
+
+    poses = [synth.room_pose(k, n) for k in range(n)]
+    H, W = cam.height, cam.width
+    out = dict(depth=torch.empty((H, W), dtype=torch.float32, device=dev),
+               normal=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+               rgba=torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+               mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+
+    # ---- algorithmic bytes per launch from traced brick and bucket sets (untimed) ------
+    tb = torch.zeros(params.brick_capacity, dtype=torch.uint8, device=dev)
+    tc = torch.zeros(params.brick_capacity, dtype=torch.uint8, device=dev)
+    ts = torch.zeros(params.hash_buckets, dtype=torch.uint8, device=dev)
+    traced = dict(out, trace_bricks=tb, trace_color=tc, trace_slots=ts)
+    bytes_per_pose = []
+    n_bd, n_cd, n_sl = [], [], []
+    hits = []
+    for T in poses:
+        tb.zero_(); tc.zero_(); ts.zero_()
+        gm.render(cam, T, out=traced)
+        nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
+        n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
+        hits.append(int(out["mask"].sum()))
+        bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +
+                              ns * BUCKET_BYTES + H * W * OUT_BYTES_PER_RAY)
+    bytes_per_launch = float(np.mean(bytes_per_pose))
+    log(f"per pose: bricks {np.mean(n_bd):.0f}, colour bricks {np.mean(n_cd):.0f}, buckets "
+        f"{np.mean(n_sl):.0f}, hit rate {np.mean(hits) / (H * W):.3f}, "
+        f"{bytes_per_launch / 1e6:.2f} MB")
+
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {a.numel() * 4} bytes")
+
+    # ---- timed render steps ------------------------------------------------------------
+    def step(evs=None):
+        for j, T in enumerate(poses):
+            if evs is not None:
+                evs[j][0].record(stream)
+            gm.render(cam, T, out=out)
+            if evs is not None:
+                evs[j][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in poses] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+        log(f"render step {s + 1}/{args.steps} enqueued")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launch_ms = np.array([[a.elapsed_time(b) for (a, b) in e] for e in evs])
+    wall = t1 - t0
+    rays = args.steps * len(poses) * H * W
+    value = rays / wall
+    mean_launch_s = float(launch_ms.mean()) * 1e-3
+    achieved = bytes_per_launch / mean_launch_s / 1e9
+    traffic = read_traffic(os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip"))
+
+    # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
+    icp_ms = None
+    if not args.no_icp:
+        icp_frames = list(range(5, n, max(1, n // 10)))[:10]
+        tot = 0.0
+        errs = []
+        rng = np.random.default_rng(3)
+        for k in icp_frames:
+            T = poses[k]
+            f = synth.scenes.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012,
+                                          seed=9000 + k, device="cuda")
+            live = torch.from_numpy(f["depth"]).to(dev)
+            dT0 = synth.perturb_pose(0.02, math.radians(2.0), rng)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            levels = []
+            for l in range(3):
+                c = dtsdf.level_camera(cam, l)
+                o = gm.render(c, T, outputs=("vertex", "normal", "mask"))
+                levels.append((o["vertex"], o["normal"], o["mask"], c))
+            T_est, _ = dtsdf.icp(live, cam, levels, dT0)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - ta
+            errs.append(float(np.linalg.norm(T_est[:3, 3])))
+        icp_ms = 1e3 * tot / len(icp_frames)
+        log(f"icp: {icp_ms:.2f} ms/frame, residual translation median {np.median(errs):.2e} m")
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample -----------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        om = orc.OracleMap(orc.MapParams(voxel=0.005, tau=0.02))
+        sample_frames = list(range(0, n, max(1, n // 5)))[:5]
+        for k in sample_frames:
+            f = synth.scenes.render_frame(sc, cam, synth.room_pose(k, n), noise="quadratic",
+                                          sigma=0.0012, seed=2000 + k, z_max=10.0,
+                                          device="cuda")
+            om.integrate(f["depth"], f["rgb"], cam, synth.room_pose(k, n))
+        T = poses[30]
+        rows_done, t_cpu = 0, 0.0
+        while t_cpu < args.cpu_seconds and rows_done < H:
+            vv, uu = np.mgrid[rows_done:rows_done + 8, 0:W]
+            pix = np.stack([uu.ravel(), vv.ravel()], 1)
+            ta = time.perf_counter()
+            om.render(cam, T, pixels=pix, classify=False)
+            t_cpu += time.perf_counter() - ta
+            rows_done += 8
+        cpu = dict(value=rows_done * W / t_cpu, unit="rays/s", cores=orc.num_threads(),
+                   kind="oracle",
+                   sample=f"FP64 oracle render (depth+normal+colour) of the first {rows_done} "
+                          f"rows of trajectory pose 30 ({rows_done * W} rays, {t_cpu:.1f} s) "
+                          f"on an oracle map fused from frames {sample_frames}")
+        log(f"cpu baseline: {cpu['value']:.0f} rays/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "room 4x4x3 m, seeded boxes/spheres/5 mm plates, 300 frames 640x480 "
+                        "fused at 5 mm voxels, tau 2 cm; render depth+normal+colour at the "
+                        "300 trajectory poses per step",
+            "width": W, "height": H, "poses_per_step": len(poses), "voxel_m": 0.005,
+            "truncation_m": 0.02, "bricks": info["bricks"], "blocks": info["blocks"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "mean_launch_ms": float(launch_ms.mean()),
+            "bricks_per_launch": float(np.mean(n_bd)),
+            "color_bricks_per_launch": float(np.mean(n_cd)),
+            "buckets_per_launch": float(np.mean(n_sl)),
+        },
+        "cpu_baseline": cpu,
+        "integrate_ms_per_frame": integ_ms / n,
+        "icp_ms_per_frame": icp_ms,
+        "hit_rate": float(np.mean(hits) / (H * W)),
+        "input_generation_s": t_gen,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

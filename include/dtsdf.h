@@ -1,0 +1,231 @@
+/*
+ * dtsdf.h -- C ABI of the Directional-TSDF library for AMD Instinct MI355X (gfx950).
+ *
+ * The library fuses depth (+colour) frames into a Directional TSDF, renders depth, vertex,
+ * normal and colour images from it by ray marching, and registers depth frames against the
+ * rendered views with point-to-plane ICP in SE(3) or Sim(3).  Every step runs in the
+ * library's own HIP kernels; the caller provides device buffers and a HIP stream.
+ *
+ * References are to Splietker & Behnke, "Rendering the Directional TSDF for Tracking and
+ * Multi-Sensor Registration with Point-To-Plane Scale ICP" (RAS 2023).
+ *
+ * Conventions shared by every call
+ *   - Units are metres.  Cameras are pinhole with OpenCV axes (x right, y down, z forward);
+ *     pixel (u, v) has its centre at integer coordinates.
+ *   - Poses are host double[16], row-major 4x4; T_world_cam maps camera to world.
+ *   - Images are dense row-major device arrays of width x height.  Three-component images
+ *     (vertex, normal) are stored as three planes: x plane, then y plane, then z plane.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the default stream).  Calls enqueue
+ *     work on it and return; device buffers must stay alive until the stream has finished.
+ *     Calls that return host results (statistics, icp_step) synchronise the stream.
+ *   - Every call returns a dtsdf_status; nothing throws across the ABI.  Output parameters
+ *     are written only on DTSDF_OK unless stated otherwise.
+ *   - World voxel (i, j, k) sits at (i, j, k) * voxel_size; block (bx, by, bz) holds voxels
+ *     8 bx .. 8 bx + 7 per axis.  Directions are ordered X+, X-, Y+, Y-, Z+, Z- (Sec. 3).
+ */
+#ifndef DTSDF_H_
+#define DTSDF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dtsdf_map dtsdf_map; /* opaque, owned by the library */
+
+typedef enum {
+  DTSDF_OK = 0,
+  DTSDF_E_INVAL = 1,      /* bad argument: null pointer, size, format or parameter range */
+  DTSDF_E_NOMEM = 2,      /* device or host allocation failed */
+  DTSDF_E_CAPACITY = 3,   /* brick pool or hash table full; see dtsdf_integrate */
+  DTSDF_E_HIP = 4,        /* a HIP runtime call failed */
+  DTSDF_E_DEGENERATE = 5, /* icp_step: too few inliers or the normal matrix is not PD */
+  DTSDF_E_BUSY = 6        /* resource in use */
+} dtsdf_status;
+
+/* Storage of the per-voxel signed distance and weight (Sec. 3: voxel tuple (d, w_d, c, w_c)). */
+typedef enum {
+  DTSDF_SDF_F32 = 0, /* float32 normalised distance */
+  DTSDF_SDF_F16 = 1, /* float16, round to nearest even */
+  DTSDF_SDF_I16 = 2  /* int16 q = round(d * 32767), distance scaled by the truncation */
+} dtsdf_sdf_fmt;
+
+typedef enum {
+  DTSDF_W_F32 = 0, /* float32 weight */
+  DTSDF_W_U8 = 1   /* uint8 code q = round(4 w), weights capped at 63.75 */
+} dtsdf_w_fmt;
+
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+} dtsdf_intrinsics;
+
+/* Map parameters.  theta is the angular threshold of Sec. 3 (eq. angular_threshold), in
+ * (pi/4, pi/2].  Values the paper leaves open have these suggested defaults:
+ * theta = pi/3, w_carve = 0.1 (free-space weight, Sec. 3), w_max = 63.75 (weight cap),
+ * w_min = 1e-4 (updates with a smaller fusion weight are skipped), lattice_step =
+ * 0.5 * voxel_size (ray-march probing interval, Sec. 4). */
+typedef struct {
+  float voxel_size;        /* metres */
+  float truncation;        /* tau, metres */
+  float theta;             /* radians */
+  float w_carve, w_max, w_min;
+  float lattice_step;      /* metres */
+  int32_t sdf_fmt;         /* dtsdf_sdf_fmt */
+  int32_t w_fmt;           /* dtsdf_w_fmt */
+  int32_t with_color;      /* 1: keep per-direction rgb + colour weight */
+  uint32_t brick_capacity; /* number of 8^3 brick-directions the pool holds */
+  uint32_t hash_buckets;   /* power of two, at least 2 * number of blocks expected */
+  int32_t dense;           /* 1: allocate the block range below in all six directions and
+                              never allocate outside it */
+  int32_t dense_lo[3], dense_hi[3]; /* inclusive block range of a dense map */
+} dtsdf_params;
+
+typedef struct {
+  int64_t bricks;          /* brick-directions in use */
+  int64_t capacity;        /* brick_capacity */
+  int64_t blocks;          /* distinct blocks (hash entries) */
+  int64_t hash_buckets;
+  int64_t dropped;         /* brick requests refused for lack of capacity, cumulative */
+  int64_t device_bytes;    /* device memory held by the map */
+} dtsdf_info;
+
+/* Render outputs; every pointer is a device buffer or NULL (not produced).
+ * The trace_* arrays serve traffic accounting: when given, the caller zeroes them and the
+ * render sets to 1 the entry of every brick whose (sdf, w) a sample read (trace_bricks,
+ * brick_capacity bytes), every brick whose colour an output read (trace_color, same size)
+ * and every hash bucket a lookup probed (trace_slots, hash_buckets bytes). */
+typedef struct {
+  float* depth;   /* H*W camera-frame z of the hit, 0 where nothing was hit */
+  float* vertex;  /* 3*H*W planes, camera-frame hit point */
+  float* normal;  /* 3*H*W planes, camera-frame unit normal facing the camera */
+  uint8_t* rgba;  /* H*W*4, colour of the hit, alpha 255 where a colour is defined */
+  uint8_t* mask;  /* H*W, 1 where the ray hit a surface */
+  uint8_t* trace_bricks;
+  uint8_t* trace_color;
+  uint8_t* trace_slots;
+} dtsdf_render_out;
+
+/* Host-side map image used for checkpoints and exact map transfer.  Bricks are listed in
+ * ascending (bx, by, bz, D) order; voxel l of a brick has local coordinates
+ * (l % 8, (l / 8) % 8, l / 64).  Arrays are host memory owned by the caller. */
+typedef struct {
+  int64_t n_bricks; /* in/out: number of bricks (capacity of the arrays on export) */
+  int32_t* keys;    /* n_bricks x 4: bx, by, bz, D */
+  float* sdf;       /* n_bricks x 512 normalised distance */
+  float* w;         /* n_bricks x 512 weight */
+  uint8_t* rgb;     /* n_bricks x 512 x 3, or NULL */
+  float* wc;        /* n_bricks x 512 colour weight, or NULL */
+} dtsdf_blob;
+
+/* Create an empty map (dense maps start with their whole block range allocated).
+ * Errors: DTSDF_E_INVAL on a bad parameter (hash_buckets not a power of two, theta outside
+ * (pi/4, pi/2], non-positive sizes, unsupported format), DTSDF_E_NOMEM. */
+dtsdf_status dtsdf_create(const dtsdf_params* params, dtsdf_map** out);
+
+/* Free a map and its device memory (synchronises the device). NULL is accepted. */
+dtsdf_status dtsdf_destroy(dtsdf_map* map);
+
+dtsdf_status dtsdf_get_info(const dtsdf_map* map, dtsdf_info* out);
+
+typedef struct {
+  int64_t new_bricks;  /* brick-directions allocated by this call */
+  int64_t dropped;     /* requests refused for lack of capacity by this call */
+  int64_t bricks;      /* brick-directions in use after the call */
+} dtsdf_integrate_stats;
+
+/* Fuse one depth (+ colour) frame with known pose (Sec. 3).
+ *   depth: device H*W float32 metres (multiplied by depth_scale), 0 = no measurement.
+ *   rgb:   device H*W*3 uint8, or NULL.
+ * Steps: cross-product normals of the frame (Sec. 7); allocation of every block on the
+ * segment p +/- tau r for each direction D with w_dir(n) > 0 (Sec. 7: blocks keyed by
+ * (x, y, z, D)); voxel-projection fusion (Sec. 3) of every allocated voxel with the point-to-
+ * plane distance (eq. point-to-plane), fusion weight (eq. combined_fusion_weight), colour
+ * weight (eq. color_weight) and free-space carving.
+ * stats may be NULL (then the call does not synchronise).  When the pool is full the
+ * requests that fit are allocated, the others are dropped, every allocated voxel is still
+ * fused, and DTSDF_E_CAPACITY is returned with stats filled in; the map stays consistent. */
+dtsdf_status dtsdf_integrate(dtsdf_map* map, const float* depth, const uint8_t* rgb,
+                             const dtsdf_intrinsics* intr, const double T_world_cam[16],
+                             float depth_scale, void* stream, dtsdf_integrate_stats* stats);
+
+/* Render a view of the map (Sec. 4): per pixel, the combined SDF of the six directions
+ * (eq. combine_weight, fallback eq. combine_tsdf_weight) is probed at t0 + k * lattice_step
+ * from z_near to z_far along the ray; the first step from a positive to a non-positive value
+ * is refined inside its bracket and the outputs are written.  Read-only on the map:
+ * concurrent renders of one map are allowed. */
+dtsdf_status dtsdf_render(const dtsdf_map* map, const dtsdf_intrinsics* intr,
+                          const double T_world_cam[16], float z_near, float z_far,
+                          const dtsdf_render_out* out, void* stream);
+
+/* Copy the map to host arrays.  With blob->keys == NULL only blob->n_bricks is set.
+ * Otherwise blob->n_bricks must be at least the number of bricks (DTSDF_E_INVAL if not);
+ * it is set to the number written.  Synchronises. */
+dtsdf_status dtsdf_export(const dtsdf_map* map, dtsdf_blob* blob);
+
+/* Replace the map contents with a blob (keys in any order, no duplicates).  rgb and wc may
+ * be NULL (colour cleared).  DTSDF_E_CAPACITY if the blob does not fit.  Synchronises. */
+dtsdf_status dtsdf_import(dtsdf_map* map, const dtsdf_blob* blob);
+
+/* Camera-frame points (Sec. 6, eq. reprojection) and cross-product normals (Sec. 7) of a
+ * depth image: vertex/normal are 3*H*W planes; the normal of a pixel without depth in
+ * itself or one of its four neighbours is written as (0, 0, 0), as is its vertex when the
+ * pixel has no depth.  Normals face the camera. */
+dtsdf_status dtsdf_vertex_normal(const float* depth, const dtsdf_intrinsics* intr,
+                                 float depth_scale, float* vertex, float* normal,
+                                 void* stream);
+
+/* Halve a depth image: output pixel = mean of its 2x2 input block if all four are valid,
+ * else 0.  Output size (width / 2) x (height / 2). */
+dtsdf_status dtsdf_depth_downsample(const float* depth_in, int32_t width, int32_t height,
+                                    float* depth_out, void* stream);
+
+/* One frame of a registration problem at one pyramid level. */
+typedef struct {
+  const float* vertex;   /* 3*H*W planes, camera frame */
+  const float* normal;   /* 3*H*W planes; (0,0,0) marks an invalid pixel */
+  const uint8_t* mask;   /* H*W hit mask of a rendered model image, or NULL */
+  dtsdf_intrinsics intr;
+} dtsdf_image;
+
+typedef enum { DTSDF_ICP_W_CONST = 0, DTSDF_ICP_W_DEPTH = 1 } dtsdf_icp_weight;
+
+typedef struct {
+  float max_dist;          /* reject ||q - y|| above this [m] (0.10) */
+  float max_angle_deg;     /* reject normal angle above this (20) */
+  int32_t weight;          /* dtsdf_icp_weight; DEPTH is eq. ICP_weight with z_min */
+  float z_min;
+  int32_t min_inliers_per_dim; /* fewer than this * dim inliers -> DTSDF_E_DEGENERATE (64) */
+} dtsdf_icp_params;
+
+typedef struct {
+  double xi[7];        /* solved increment (nu, omega[, sigma]) */
+  double H[49];        /* dim x dim normal matrix, row-major (sum w J J^T) */
+  double g[7];         /* sum w J r */
+  double error;        /* sum w r^2 */
+  int64_t inliers;
+  double step_norm;    /* ||xi||_2 */
+} dtsdf_icp_result;
+
+/* One Gauss-Newton step of point-to-plane ICP (Sec. 5, eq. geometric_ICP .. deltaT_update;
+ * Sim(3): Sec. 6, eq. sim3_derivative).  dim = 6 (SE(3)) or 7 (Sim(3)).
+ * T_model_live (host, in/out) maps live camera coordinates to model camera coordinates.
+ * Every live pixel with a valid normal is transformed by T_model_live, projected into the
+ * model image (nearest pixel, must be a hit), and rejected beyond max_dist or
+ * max_angle_deg; the residuals r = <q - y, n> and Jacobians J = (-n, -(y x n)[, -<n, y>])
+ * are reduced in a fixed order (bitwise run-to-run reproducible), the system H xi = -g is
+ * solved by Cholesky in float64 on the device and T_model_live <- exp(xi) T_model_live.
+ * DTSDF_E_DEGENERATE (T unchanged, result filled in) if there are too few inliers or H is
+ * not positive definite.  Synchronises the stream. */
+dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
+                      const dtsdf_icp_params* params, double T_model_live[16],
+                      dtsdf_icp_result* result, void* stream);
+
+const char* dtsdf_status_string(dtsdf_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTSDF_H_ */

@@ -25,6 +25,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <omp.h>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -87,7 +89,7 @@ struct Map {
   std::unordered_map<Key, int, KeyHash> index;   // (block, D) -> brick ordinal
   std::unordered_set<BKey, BKeyHash> blocks;     // blocks with at least one direction
   std::vector<Key> keys;
-  std::vector<Brick> bricks;
+  std::deque<Brick> bricks;    // stable addresses, no reallocation copies
 };
 
 inline int64_t floor_div(int64_t a, int64_t b) {
@@ -418,7 +420,8 @@ void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H
                         (pw[2] - t[2]) * nw[2]) / rl;
       double w_angle = std::max(0.0, cosang);
       double wd = w_angle * wd_dir;
-      if (std::fabs(wd - p.w_min) < 1e-6 * p.w_min) bl = true;
+      // float32 implementations carry ~5e-7 absolute error in w_dir near the blend-zone edge
+      if (std::fabs(wd - p.w_min) < 1e-6) bl = true;
       if (wd < p.w_min) {
         if (bl) B.border[l] = 1;
         continue;
@@ -495,7 +498,6 @@ void orc_import(void* h, int64_t n, const int32_t* keys, const float* sdf, const
   m.blocks.clear();
   m.keys.clear();
   m.bricks.clear();
-  m.bricks.reserve((size_t)n);
   for (int64_t j = 0; j < n; ++j) {
     int id = add_brick(m, Key{keys[4 * j], keys[4 * j + 1], keys[4 * j + 2], keys[4 * j + 3]});
     Brick& B = m.bricks[id];
@@ -952,5 +954,8 @@ void orc_brick_key(void* h, int64_t id, int32_t* key4) {
 }
 
 double orc_w_dir(const Params* p, const double n[3], int d) { return w_dir(*p, n, d); }
+
+// Threads an OpenMP region of the oracle uses.
+int orc_num_threads() { return omp_get_max_threads(); }
 
 }  // extern "C"

@@ -105,6 +105,7 @@ def _declare(L):
                              _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_eval.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
     L.orc_brick_key.argtypes = [_P, ctypes.c_int64, _P]
+    L.orc_num_threads.restype = ctypes.c_int
     L.orc_w_dir.restype = ctypes.c_double
     L.orc_w_dir.argtypes = [ctypes.POINTER(_Params), _P, ctypes.c_int]
 
@@ -150,6 +151,10 @@ class MapParams:
         p.with_color = int(self.with_color)
         p.single_direction = int(self.single_direction)
         return p
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def w_dir(params: MapParams, n: Sequence[float], d: int) -> float:

@@ -1,0 +1,141 @@
+// Internal definitions of the Directional-TSDF library (device layout, hash, helpers).
+//
+// Device layout of a map
+//   entries  HashEntry[buckets]     open-addressing spatial hash, linear probing; one entry per
+//                                   8^3 block holds the pool index of the block's brick in each
+//                                   of the six directions (-1: not allocated).  Sec. 7 keys
+//                                   bricks by (x, y, z, D); grouping the six D of a block in one
+//                                   32-byte entry lets one probe serve every direction a ray
+//                                   sample reads.
+//   req      uint32[buckets]        per-entry bit mask of directions requested by the frame
+//                                   being integrated (cleared when bricks are assigned)
+//   bkey     int4[capacity]         (bx, by, bz, D) of every pool brick
+//   sw       float2[capacity*512]   (sdf, w) of every voxel, brick-major, voxel l at local
+//                                   (l % 8, l / 8 % 8, l / 64); the march reads only these
+//   rgb      uint32[capacity*512]   r | g << 8 | b << 16 colour code per voxel
+//   wc       float[capacity*512]    colour weight per voxel
+//   counters int32[4]               [0] bricks handed out (may overshoot the capacity while a
+//                                   frame allocates), [1] dropped requests, [2] hash overflow,
+//                                   [3] occupied hash entries
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dtsdf.h"
+
+namespace dtsdf {
+
+constexpr int kB = 8;
+constexpr int kVox = 512;
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int kKeyBias = 1 << 19;   // block coordinates must lie in [-2^19, 2^19)
+
+struct alignas(32) HashEntry {
+  uint64_t key;
+  int32_t brick[6];
+};
+static_assert(sizeof(HashEntry) == 32, "hash entries are 32 bytes");
+
+__host__ __device__ inline bool key_in_range(int bx, int by, int bz) {
+  return bx >= -kKeyBias && bx < kKeyBias && by >= -kKeyBias && by < kKeyBias &&
+         bz >= -kKeyBias && bz < kKeyBias;
+}
+
+__host__ __device__ inline uint64_t pack_key(int bx, int by, int bz) {
+  return (uint64_t)(uint32_t)(bx + kKeyBias) | ((uint64_t)(uint32_t)(by + kKeyBias) << 20) |
+         ((uint64_t)(uint32_t)(bz + kKeyBias) << 40);
+}
+
+__host__ __device__ inline void unpack_key(uint64_t k, int& bx, int& by, int& bz) {
+  bx = (int)(k & 0xFFFFF) - kKeyBias;
+  by = (int)((k >> 20) & 0xFFFFF) - kKeyBias;
+  bz = (int)((k >> 40) & 0xFFFFF) - kKeyBias;
+}
+
+__host__ __device__ inline uint32_t hash_key(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+
+// Read-only view of a map, passed by value to kernels.
+struct MapView {
+  const HashEntry* entries;
+  uint32_t mask;            // buckets - 1
+  float2* sw;
+  uint32_t* rgb;
+  float* wc;
+  const int4* bkey;
+  uint32_t capacity;
+  double voxel, inv_voxel;
+  float tau, theta, w_carve, w_max, w_min;
+  double step;
+  int with_color;
+};
+
+// Slot of a block key, -1 if absent.  At most `mask + 1` probes.
+__device__ inline int find_slot(const HashEntry* __restrict__ e, uint32_t mask, uint64_t key) {
+  uint32_t s = hash_key(key) & mask;
+  for (uint32_t i = 0; i <= mask; ++i) {
+    uint64_t k = e[s].key;
+    if (k == key) return (int)s;
+    if (k == kEmptyKey) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+__device__ inline double floor_d(double x) { return floor(x); }
+
+// Direction membership weight of Sec. 3 (eq. direction_weight), read as the clamped-linear
+// function that is 1 for angles up to pi/2 - theta, 0 from theta on and linear in between.
+// `c` is the cosine <n, v^D>.
+__device__ inline float w_dir_cos(float c, float theta) {
+  c = fminf(1.0f, fmaxf(-1.0f, c));
+  float a = acosf(c);
+  float v = (theta - a) / (2.0f * theta - 1.5707963267948966f);
+  return fminf(1.0f, fmaxf(0.0f, v));
+}
+
+// <n, v^D> for direction D (X+, X-, Y+, Y-, Z+, Z-).
+__device__ __host__ inline float axis_dot(float nx, float ny, float nz, int d) {
+  float c = (d < 2) ? nx : (d < 4 ? ny : nz);
+  return (d & 1) ? -c : c;
+}
+
+#define DTSDF_HIP(x)                                  \
+  do {                                                \
+    hipError_t e__ = (x);                             \
+    if (e__ != hipSuccess) return DTSDF_E_HIP;        \
+  } while (0)
+
+}  // namespace dtsdf
+
+// Host-side state of a map.
+struct dtsdf_map {
+  dtsdf_params p;
+  int device;
+  uint32_t buckets;
+  dtsdf::HashEntry* entries;
+  uint32_t* req;
+  int4* bkey;
+  float2* sw;
+  uint32_t* rgb;
+  float* wc;
+  int32_t* counters;
+  int64_t n_bricks;     // host mirror of the bricks in use
+  int64_t n_blocks;     // host mirror of occupied entries (updated on sync points)
+  int64_t dropped;
+  // integration scratch, grown on demand
+  int64_t img_cap;
+  float* vmap;
+  float* nmap;
+};
+
+namespace dtsdf {
+MapView make_view(const dtsdf_map* m);
+}

@@ -1,0 +1,393 @@
+// Integration of depth (+colour) frames into the Directional TSDF (Sec. 3 and Sec. 7).
+//
+// Per frame:
+//   1. vertex_normal_k   back-projection (eq. reprojection) and cross-product normals of the
+//                        depth image, one thread per pixel, float64 arithmetic
+//   2. request_k         (sparse maps) block requests along p +/- tau r for every direction
+//                        with w_dir > 0, inserted into the spatial hash by CAS
+//   3. assign_k          pool indices for newly requested (block, D) bricks
+//   4. fuse_k            voxel-projection fusion of every allocated brick, one workgroup per
+//                        brick, 256 threads x 2 voxels: HBM streaming of (sdf, w) (+ colour)
+// Geometry (projection, point-to-plane distance) is evaluated in float64 so that the
+// discrete decisions (pixel association, band tests) match an exact evaluation except on
+// measure-zero ties; the running averages are float32, as stored.
+#include <cmath>
+#include <vector>
+
+#include "dtsdf_internal.hpp"
+
+using namespace dtsdf;
+
+namespace {
+
+struct Intr {
+  int W, H;
+  double fx, fy, cx, cy;
+};
+
+__global__ __launch_bounds__(256) void vertex_normal_k(const float* __restrict__ depth, Intr in,
+                                                       double scale, float* __restrict__ vmap,
+                                                       float* __restrict__ nmap) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y * blockDim.y + threadIdx.y;
+  if (u >= in.W || v >= in.H) return;
+  const size_t HW = (size_t)in.W * in.H;
+  const size_t i = (size_t)v * in.W + u;
+  auto point = [&](int uu, int vv, double* P) -> bool {
+    double z = (double)depth[(size_t)vv * in.W + uu] * scale;
+    if (!(z > 0.0) || !isfinite(z)) return false;
+    P[0] = z * ((double)uu - in.cx) / in.fx;
+    P[1] = z * ((double)vv - in.cy) / in.fy;
+    P[2] = z;
+    return true;
+  };
+  double P[3] = {0, 0, 0};
+  bool pv = point(u, v, P);
+  vmap[i] = pv ? (float)P[0] : 0.f;
+  vmap[HW + i] = pv ? (float)P[1] : 0.f;
+  vmap[2 * HW + i] = pv ? (float)P[2] : 0.f;
+  float n_out[3] = {0.f, 0.f, 0.f};
+  if (pv && u > 0 && v > 0 && u + 1 < in.W && v + 1 < in.H) {
+    double L[3], Rr[3], T[3], B[3];
+    if (point(u - 1, v, L) && point(u + 1, v, Rr) && point(u, v - 1, T) && point(u, v + 1, B)) {
+      double dx[3] = {Rr[0] - L[0], Rr[1] - L[1], Rr[2] - L[2]};
+      double dy[3] = {B[0] - T[0], B[1] - T[1], B[2] - T[2]};
+      double n[3] = {dx[1] * dy[2] - dx[2] * dy[1], dx[2] * dy[0] - dx[0] * dy[2],
+                     dx[0] * dy[1] - dx[1] * dy[0]};
+      double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      if (len > 0.0) {
+        double s = (n[0] * P[0] + n[1] * P[1] + n[2] * P[2] > 0.0) ? -1.0 / len : 1.0 / len;
+        for (int k = 0; k < 3; ++k) n_out[k] = (float)(n[k] * s);
+      }
+    }
+  }
+  nmap[i] = n_out[0];
+  nmap[HW + i] = n_out[1];
+  nmap[2 * HW + i] = n_out[2];
+}
+
+__global__ __launch_bounds__(256) void downsample_k(const float* __restrict__ in, int W, int H,
+                                                    float* __restrict__ out) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y * blockDim.y + threadIdx.y;
+  int Wo = W / 2, Ho = H / 2;
+  if (u >= Wo || v >= Ho) return;
+  const float* r0 = in + (size_t)(2 * v) * W + 2 * u;
+  const float* r1 = r0 + W;
+  float a = r0[0], b = r0[1], c = r1[0], d = r1[1];
+  out[(size_t)v * Wo + u] = (a > 0.f && b > 0.f && c > 0.f && d > 0.f) ? (a + b + c + d) * 0.25f : 0.f;
+}
+
+struct Pose {
+  double R[9];
+  double t[3];
+};
+
+// Inserts (key, D) into the hash: the key by CAS on an empty slot, D as a request bit.
+// New keys are refused (and counted as dropped requests) once `max_entries` slots are
+// occupied, so that probe sequences of absent keys stay short.
+__device__ void insert_request(HashEntry* e, uint32_t* req, uint32_t mask, uint64_t key, int d,
+                               int32_t* counters, int32_t max_entries) {
+  uint32_t s = hash_key(key) & mask;
+  for (uint32_t i = 0; i <= mask; ++i) {
+    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&e[s].key);
+    uint64_t k = __atomic_load_n(kp, __ATOMIC_RELAXED);
+    if (k == kEmptyKey) {
+      if (__atomic_load_n(&counters[3], __ATOMIC_RELAXED) >= max_entries) {
+        atomicAdd(&counters[1], 1);
+        return;
+      }
+      uint64_t prev = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
+      if (prev == kEmptyKey) atomicAdd(&counters[3], 1);
+      if (prev == kEmptyKey || prev == key) {
+        atomicOr(&req[s], 1u << d);
+        return;
+      }
+      k = prev;
+    }
+    if (k == key) {
+      atomicOr(&req[s], 1u << d);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+  atomicExch(&counters[2], 1);
+}
+
+// Allocation requests (Sec. 7: blocks are allocated for every point with a valid normal):
+// for each direction D with w_dir(n) > 0, the blocks containing the J + 1 evenly spaced
+// points p + s r, s in [-tau, tau] (r: unit ray through the pixel).
+__global__ __launch_bounds__(256) void request_k(const float* __restrict__ depth,
+                                                 const float* __restrict__ nmap, Intr in,
+                                                 double scale, Pose T, double voxel, double tau,
+                                                 int J, float theta, HashEntry* entries,
+                                                 uint32_t* req, uint32_t mask,
+                                                 int32_t* counters, int32_t max_entries) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y * blockDim.y + threadIdx.y;
+  if (u >= in.W || v >= in.H) return;
+  const size_t HW = (size_t)in.W * in.H;
+  const size_t i = (size_t)v * in.W + u;
+  float nx = nmap[i], ny = nmap[HW + i], nz = nmap[2 * HW + i];
+  if (nx == 0.f && ny == 0.f && nz == 0.f) return;
+  double z = (double)depth[i] * scale;
+  double pc[3] = {z * ((double)u - in.cx) / in.fx, z * ((double)v - in.cy) / in.fy, z};
+  double len = sqrt(pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]);
+  double pw[3], rw[3];
+  float nw[3];
+  for (int k = 0; k < 3; ++k) {
+    double rp = T.R[3 * k] * pc[0] + T.R[3 * k + 1] * pc[1] + T.R[3 * k + 2] * pc[2];
+    pw[k] = rp + T.t[k];
+    rw[k] = rp / len;
+    nw[k] = (float)(T.R[3 * k] * nx + T.R[3 * k + 1] * ny + T.R[3 * k + 2] * nz);
+  }
+  for (int d = 0; d < 6; ++d) {
+    if (!(w_dir_cos(axis_dot(nw[0], nw[1], nw[2], d), theta) > 0.f)) continue;
+    uint64_t prev = kEmptyKey;
+    for (int j = 0; j <= J; ++j) {
+      double s = -tau + 2.0 * tau * j / J;
+      int b[3];
+      for (int k = 0; k < 3; ++k) b[k] = (int)floor((pw[k] + s * rw[k]) / voxel / kB);
+      if (!key_in_range(b[0], b[1], b[2])) continue;
+      uint64_t key = pack_key(b[0], b[1], b[2]);
+      if (key == prev) continue;
+      prev = key;
+      insert_request(entries, req, mask, key, d, counters, max_entries);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* req, int4* bkey,
+                                                uint32_t buckets, uint32_t capacity,
+                                                int32_t* counters) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= buckets) return;
+  uint32_t r = req[s];
+  if (!r) return;
+  req[s] = 0;
+  int bx, by, bz;
+  unpack_key(entries[s].key, bx, by, bz);
+  for (int d = 0; d < 6; ++d) {
+    if (!((r >> d) & 1u) || entries[s].brick[d] >= 0) continue;
+    int idx = atomicAdd(&counters[0], 1);
+    if (idx < (int)capacity) {
+      entries[s].brick[d] = idx;
+      bkey[idx] = make_int4(bx, by, bz, d);
+    } else {
+      atomicAdd(&counters[1], 1);
+    }
+  }
+}
+
+struct FuseArgs {
+  const float* depth;
+  const uint8_t* rgb;
+  const float* nmap;
+  Intr in;
+  double scale;
+  Pose T;
+};
+
+// Voxel-projection fusion (Sec. 3) of one brick per workgroup.
+__global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a) {
+  const int4 key = m.bkey[blockIdx.x];
+  const int D = key.w;
+  const size_t HW = (size_t)a.in.W * a.in.H;
+  const double tau = (double)m.tau;
+  for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
+    const int lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
+    double x[3] = {(double)(key.x * kB + lx) * m.voxel, (double)(key.y * kB + ly) * m.voxel,
+                   (double)(key.z * kB + lz) * m.voxel};
+    double xr[3] = {x[0] - a.T.t[0], x[1] - a.T.t[1], x[2] - a.T.t[2]};
+    double xc[3];
+    for (int k = 0; k < 3; ++k)
+      xc[k] = a.T.R[k] * xr[0] + a.T.R[3 + k] * xr[1] + a.T.R[6 + k] * xr[2];
+    if (!(xc[2] > 0.0)) continue;
+    double uf = a.in.fx * xc[0] / xc[2] + a.in.cx;
+    double vf = a.in.fy * xc[1] / xc[2] + a.in.cy;
+    double ur = floor(uf + 0.5), vr = floor(vf + 0.5);
+    if (ur < 0.0 || vr < 0.0 || ur >= (double)a.in.W || vr >= (double)a.in.H) continue;
+    const int u = (int)ur, v = (int)vr;
+    const size_t pi = (size_t)v * a.in.W + u;
+    const float nx = a.nmap[pi], ny = a.nmap[HW + pi], nz = a.nmap[2 * HW + pi];
+    if (nx == 0.f && ny == 0.f && nz == 0.f) continue;
+    const double z = (double)a.depth[pi] * a.scale;
+    const double pc[3] = {z * ((double)u - a.in.cx) / a.in.fx, z * ((double)v - a.in.cy) / a.in.fy, z};
+    // point-to-plane distance (eq. point-to-plane) with the normal facing the camera, so that
+    // positive values lie in front of the surface
+    const double dd = ((xc[0] - pc[0]) * nx + (xc[1] - pc[1]) * ny + (xc[2] - pc[2]) * nz) / tau;
+    float2* swp = &m.sw[(size_t)blockIdx.x * kVox + l];
+    if (dd > 1.0) {
+      // free space: value 1 with a constant weight unless a depth jump above tau lies within
+      // two pixels (Sec. 3)
+      bool ok = m.w_carve > 0.f;
+      for (int dv = -2; dv <= 2 && ok; ++dv)
+        for (int du = -2; du <= 2; ++du) {
+          int uu = u + du, vv = v + dv;
+          if (uu < 0 || vv < 0 || uu >= a.in.W || vv >= a.in.H) continue;
+          double z1 = (double)a.depth[(size_t)vv * a.in.W + uu] * a.scale;
+          if (!(z1 > 0.0)) continue;
+          if (fabs(z1 - z) > tau) {
+            ok = false;
+            break;
+          }
+        }
+      if (ok) {
+        float2 s = *swp;
+        float nw = s.y + m.w_carve;
+        s.x = (s.x * s.y + 1.0f * m.w_carve) / nw;
+        s.y = fminf(nw, m.w_max);
+        *swp = s;
+      }
+      continue;
+    }
+    if (dd < -1.0) continue;
+    float nwx = (float)(a.T.R[0] * nx + a.T.R[1] * ny + a.T.R[2] * nz);
+    float nwy = (float)(a.T.R[3] * nx + a.T.R[4] * ny + a.T.R[5] * nz);
+    float nwz = (float)(a.T.R[6] * nx + a.T.R[7] * ny + a.T.R[8] * nz);
+    const float wdir = w_dir_cos(axis_dot(nwx, nwy, nwz, D), m.theta);
+    if (!(wdir > 0.f)) continue;
+    // w_d = w_depth * w_angle * w_dir (eq. combined_fusion_weight), w_depth = 1,
+    // w_angle = max(0, <n, -r>) for the unit ray r through the pixel
+    const double plen = sqrt(pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]);
+    const float w_angle = fmaxf(0.f, (float)(-(pc[0] * nx + pc[1] * ny + pc[2] * nz) / plen));
+    const float wd = w_angle * wdir;
+    if (wd < m.w_min) continue;
+    float2 s = *swp;
+    float nw = s.y + wd;
+    s.x = (s.x * s.y + (float)dd * wd) / nw;
+    s.y = fminf(nw, m.w_max);
+    *swp = s;
+    if (m.with_color && a.rgb) {
+      // colour weight w_c = w_d (1 - min(1, |p - x| / tau)) (eq. color_weight)
+      const double dist = sqrt((pc[0] - xc[0]) * (pc[0] - xc[0]) + (pc[1] - xc[1]) * (pc[1] - xc[1]) +
+                               (pc[2] - xc[2]) * (pc[2] - xc[2]));
+      const float wc = wd * (1.0f - fminf(1.0f, (float)(dist / tau)));
+      if (wc > 0.f) {
+        const size_t vi = (size_t)blockIdx.x * kVox + l;
+        float Wc = m.wc[vi];
+        uint32_t c = m.rgb[vi];
+        const float inv = 1.0f / (Wc + wc);
+        uint32_t outc = 0;
+        for (int ch = 0; ch < 3; ++ch) {
+          float old = (float)((c >> (8 * ch)) & 0xFFu);
+          float px = (float)a.rgb[3 * pi + ch];
+          float val = rintf((old * Wc + px * wc) * inv);
+          val = fminf(255.f, fmaxf(0.f, val));
+          outc |= (uint32_t)val << (8 * ch);
+        }
+        m.rgb[vi] = outc;
+        m.wc[vi] = fminf(Wc + wc, m.w_max);
+      }
+    }
+  }
+}
+
+Intr make_intr(const dtsdf_intrinsics* i) {
+  return Intr{i->width, i->height, (double)i->fx, (double)i->fy, (double)i->cx, (double)i->cy};
+}
+
+Pose make_pose(const double T[16]) {
+  Pose p;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) p.R[3 * r + c] = T[4 * r + c];
+    p.t[r] = T[4 * r + 3];
+  }
+  return p;
+}
+
+bool valid_intr(const dtsdf_intrinsics* i) {
+  return i && i->width > 2 && i->height > 2 && i->width <= 16384 && i->height <= 16384 &&
+         i->fx > 0 && i->fy > 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+dtsdf_status dtsdf_vertex_normal(const float* depth, const dtsdf_intrinsics* intr,
+                                 float depth_scale, float* vertex, float* normal,
+                                 void* stream) {
+  if (!depth || !vertex || !normal || !valid_intr(intr) || !(depth_scale > 0))
+    return DTSDF_E_INVAL;
+  Intr in = make_intr(intr);
+  dim3 blk(16, 16), grd((in.W + 15) / 16, (in.H + 15) / 16);
+  hipLaunchKernelGGL(vertex_normal_k, grd, blk, 0, (hipStream_t)stream, depth, in,
+                     (double)depth_scale, vertex, normal);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+dtsdf_status dtsdf_depth_downsample(const float* depth_in, int32_t width, int32_t height,
+                                    float* depth_out, void* stream) {
+  if (!depth_in || !depth_out || width < 2 || height < 2) return DTSDF_E_INVAL;
+  dim3 blk(16, 16), grd((width / 2 + 15) / 16, (height / 2 + 15) / 16);
+  hipLaunchKernelGGL(downsample_k, grd, blk, 0, (hipStream_t)stream, depth_in, width, height,
+                     depth_out);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rgb,
+                             const dtsdf_intrinsics* intr, const double T_world_cam[16],
+                             float depth_scale, void* stream, dtsdf_integrate_stats* stats) {
+  if (!m || !depth || !valid_intr(intr) || !T_world_cam || !(depth_scale > 0))
+    return DTSDF_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Intr in = make_intr(intr);
+  const int64_t HW = (int64_t)in.W * in.H;
+  if (HW > m->img_cap) {
+    DTSDF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(m->vmap);
+    (void)hipFree(m->nmap);
+    m->vmap = m->nmap = nullptr;
+    m->img_cap = 0;
+    if (hipMalloc(&m->vmap, sizeof(float) * 3 * HW) != hipSuccess ||
+        hipMalloc(&m->nmap, sizeof(float) * 3 * HW) != hipSuccess)
+      return DTSDF_E_NOMEM;
+    m->img_cap = HW;
+  }
+  Pose T = make_pose(T_world_cam);
+  dim3 blk(16, 16), grd((in.W + 15) / 16, (in.H + 15) / 16);
+  hipLaunchKernelGGL(vertex_normal_k, grd, blk, 0, st, depth, in, (double)depth_scale, m->vmap,
+                     m->nmap);
+  int64_t before = m->n_bricks;
+  int64_t dropped_now = 0;
+  if (!m->p.dense) {
+    const double voxel = (double)m->p.voxel_size, tau = (double)m->p.truncation;
+    const int J = (int)std::ceil(2.0 * tau / voxel - 1e-9);
+    const int32_t max_entries = (int32_t)((uint64_t)m->buckets * 3 / 4);
+    hipLaunchKernelGGL(request_k, grd, blk, 0, st, depth, m->nmap, in, (double)depth_scale, T,
+                       voxel, tau, J, m->p.theta, m->entries, m->req, m->buckets - 1,
+                       m->counters, max_entries);
+    hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
+                       m->req, m->bkey, m->buckets, m->p.brick_capacity, m->counters);
+    int32_t c[4];
+    DTSDF_HIP(hipMemcpyAsync(c, m->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    DTSDF_HIP(hipStreamSynchronize(st));
+    int64_t handed = c[0];
+    if (handed > (int64_t)m->p.brick_capacity) {
+      int32_t cap = (int32_t)m->p.brick_capacity;
+      DTSDF_HIP(hipMemcpyAsync(m->counters, &cap, sizeof(cap), hipMemcpyHostToDevice, st));
+      handed = cap;
+    }
+    dropped_now = (int64_t)c[1] - m->dropped;
+    m->dropped = c[1];
+    m->n_bricks = handed;
+    m->n_blocks = c[3];
+  }
+  if (m->n_bricks > 0) {
+    FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
+    hipLaunchKernelGGL(fuse_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, make_view(m), fa);
+  }
+  DTSDF_HIP(hipGetLastError());
+  if (stats) {
+    stats->new_bricks = m->n_bricks - before;
+    stats->dropped = dropped_now;
+    stats->bricks = m->n_bricks;
+    DTSDF_HIP(hipStreamSynchronize(st));
+  }
+  return dropped_now > 0 ? DTSDF_E_CAPACITY : DTSDF_OK;
+}
+
+}  // extern "C"

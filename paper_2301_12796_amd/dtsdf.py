@@ -1,0 +1,393 @@
+"""ctypes binding of libdtsdf.so (the C ABI declared in include/dtsdf.h).
+
+Argument marshalling only: device buffers are torch tensors on the HIP device, passed by
+pointer together with torch's current stream; every step of the computation runs in the
+library's HIP kernels.  There is no fallback: if the library is missing, importing this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdtsdf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c \"import "
+                      "__graft_entry__ as g; g.build()\"` (hipcc, gfx950)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY = range(7)
+SDF_F32, SDF_F16, SDF_I16 = 0, 1, 2
+W_F32, W_U8 = 0, 1
+ICP_W_CONST, ICP_W_DEPTH = 0, 1
+
+
+class DtsdfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_lib.dtsdf_status_string(status).decode()} ({status})")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("truncation", ctypes.c_float),
+                ("theta", ctypes.c_float), ("w_carve", ctypes.c_float),
+                ("w_max", ctypes.c_float), ("w_min", ctypes.c_float),
+                ("lattice_step", ctypes.c_float), ("sdf_fmt", ctypes.c_int32),
+                ("w_fmt", ctypes.c_int32), ("with_color", ctypes.c_int32),
+                ("brick_capacity", ctypes.c_uint32), ("hash_buckets", ctypes.c_uint32),
+                ("dense", ctypes.c_int32), ("dense_lo", ctypes.c_int32 * 3),
+                ("dense_hi", ctypes.c_int32 * 3)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("bricks", ctypes.c_int64), ("capacity", ctypes.c_int64),
+                ("blocks", ctypes.c_int64), ("hash_buckets", ctypes.c_int64),
+                ("dropped", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class _Intr(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class _RenderOut(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
+                ("normal", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("trace_bricks", ctypes.c_void_p),
+                ("trace_color", ctypes.c_void_p), ("trace_slots", ctypes.c_void_p)]
+
+
+class _Blob(ctypes.Structure):
+    _fields_ = [("n_bricks", ctypes.c_int64), ("keys", ctypes.c_void_p), ("sdf", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("rgb", ctypes.c_void_p), ("wc", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("new_bricks", ctypes.c_int64), ("dropped", ctypes.c_int64),
+                ("bricks", ctypes.c_int64)]
+
+
+class _Image(ctypes.Structure):
+    _fields_ = [("vertex", ctypes.c_void_p), ("normal", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("intr", _Intr)]
+
+
+class _IcpParams(ctypes.Structure):
+    _fields_ = [("max_dist", ctypes.c_float), ("max_angle_deg", ctypes.c_float),
+                ("weight", ctypes.c_int32), ("z_min", ctypes.c_float),
+                ("min_inliers_per_dim", ctypes.c_int32)]
+
+
+class _IcpResult(ctypes.Structure):
+    _fields_ = [("xi", ctypes.c_double * 7), ("H", ctypes.c_double * 49),
+                ("g", ctypes.c_double * 7), ("error", ctypes.c_double),
+                ("inliers", ctypes.c_int64), ("step_norm", ctypes.c_double)]
+
+
+_V = ctypes.c_void_p
+_D16 = ctypes.POINTER(ctypes.c_double)
+
+EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate",
+            "dtsdf_render", "dtsdf_export", "dtsdf_import", "dtsdf_vertex_normal",
+            "dtsdf_depth_downsample", "icp_step", "dtsdf_status_string"]
+
+_lib.dtsdf_status_string.restype = ctypes.c_char_p
+_lib.dtsdf_status_string.argtypes = [ctypes.c_int]
+_lib.dtsdf_create.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_V)]
+_lib.dtsdf_destroy.argtypes = [_V]
+_lib.dtsdf_get_info.argtypes = [_V, ctypes.POINTER(_Info)]
+_lib.dtsdf_integrate.argtypes = [_V, _V, _V, ctypes.POINTER(_Intr), _D16, ctypes.c_float, _V,
+                                 ctypes.POINTER(_Stats)]
+_lib.dtsdf_render.argtypes = [_V, ctypes.POINTER(_Intr), _D16, ctypes.c_float, ctypes.c_float,
+                              ctypes.POINTER(_RenderOut), _V]
+_lib.dtsdf_export.argtypes = [_V, ctypes.POINTER(_Blob)]
+_lib.dtsdf_import.argtypes = [_V, ctypes.POINTER(_Blob)]
+_lib.dtsdf_vertex_normal.argtypes = [_V, ctypes.POINTER(_Intr), ctypes.c_float, _V, _V, _V]
+_lib.dtsdf_depth_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
+_lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes.c_int32,
+                          ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
+for _f in EXPORTED:
+    if _f != "dtsdf_status_string":
+        getattr(_lib, _f).restype = ctypes.c_int
+
+
+def _check(status: int, what: str, allow=()):
+    if status != OK and status not in allow:
+        raise DtsdfError(status, what)
+    return status
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype, numel=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device buffers must be HIP tensors")
+    if t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _intr(cam) -> _Intr:
+    return _Intr(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
+                 float(cam.cy))
+
+
+def _pose(T) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(T, np.float64).reshape(16))
+    return (ctypes.c_double * 16)(*a.tolist())
+
+
+@dataclasses.dataclass
+class Params:
+    voxel_size: float
+    truncation: float
+    theta: float = math.pi / 3.0
+    w_carve: float = 0.1
+    w_max: float = 63.75
+    w_min: float = 1e-4
+    lattice_step: Optional[float] = None
+    sdf_fmt: int = SDF_F32
+    w_fmt: int = W_F32
+    with_color: bool = True
+    brick_capacity: int = 1 << 16
+    hash_buckets: int = 1 << 17
+    dense_lo: Optional[Sequence[int]] = None
+    dense_hi: Optional[Sequence[int]] = None
+
+    def c_struct(self) -> _Params:
+        p = _Params()
+        p.voxel_size = self.voxel_size
+        p.truncation = self.truncation
+        p.theta = self.theta
+        p.w_carve = self.w_carve
+        p.w_max = self.w_max
+        p.w_min = self.w_min
+        p.lattice_step = self.lattice_step if self.lattice_step is not None else 0.5 * self.voxel_size
+        p.sdf_fmt = self.sdf_fmt
+        p.w_fmt = self.w_fmt
+        p.with_color = int(self.with_color)
+        p.brick_capacity = self.brick_capacity
+        p.hash_buckets = self.hash_buckets
+        p.dense = 1 if self.dense_lo is not None else 0
+        for k in range(3):
+            p.dense_lo[k] = int(self.dense_lo[k]) if self.dense_lo is not None else 0
+            p.dense_hi[k] = int(self.dense_hi[k]) if self.dense_hi is not None else 0
+        return p
+
+
+class Map:
+    """A Directional TSDF resident in device memory."""
+
+    def __init__(self, params: Params):
+        self.params = params
+        h = _V()
+        _check(_lib.dtsdf_create(ctypes.byref(params.c_struct()), ctypes.byref(h)), "dtsdf_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dtsdf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(_lib.dtsdf_get_info(self._h, ctypes.byref(i)), "dtsdf_get_info")
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def integrate(self, depth: torch.Tensor, rgb: Optional[torch.Tensor], cam, T_wc,
+                  depth_scale: float = 1.0, stats: bool = False, stream=None):
+        H, W = int(cam.height), int(cam.width)
+        st = _Stats() if stats else None
+        status = _lib.dtsdf_integrate(
+            self._h, _dev_ptr(depth, torch.float32, H * W),
+            _dev_ptr(rgb, torch.uint8, H * W * 3) if rgb is not None else None,
+            ctypes.byref(_intr(cam)), _pose(T_wc), depth_scale, _stream(stream),
+            ctypes.byref(st) if st is not None else None)
+        _check(status, "dtsdf_integrate", allow=(E_CAPACITY,))
+        if stats:
+            return dict(status=status, new_bricks=st.new_bricks, dropped=st.dropped,
+                        bricks=st.bricks)
+        return status
+
+    def render(self, cam, T_wc, z_near: float = 0.2, z_far: float = 10.0,
+               out: Optional[dict] = None, outputs=("depth", "vertex", "normal", "rgba", "mask"),
+               stream=None) -> dict:
+        H, W = int(cam.height), int(cam.width)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = {}
+            shapes = dict(depth=((H, W), torch.float32), vertex=((3, H, W), torch.float32),
+                          normal=((3, H, W), torch.float32), rgba=((H, W, 4), torch.uint8),
+                          mask=((H, W), torch.uint8))
+            for k in outputs:
+                shp, dt = shapes[k]
+                out[k] = torch.empty(shp, dtype=dt, device=dev)
+        cap, nb = self.params.brick_capacity, self.params.hash_buckets
+        ro = _RenderOut(_dev_ptr(out.get("depth"), torch.float32, H * W),
+                        _dev_ptr(out.get("vertex"), torch.float32, 3 * H * W),
+                        _dev_ptr(out.get("normal"), torch.float32, 3 * H * W),
+                        _dev_ptr(out.get("rgba"), torch.uint8, 4 * H * W),
+                        _dev_ptr(out.get("mask"), torch.uint8, H * W),
+                        _dev_ptr(out.get("trace_bricks"), torch.uint8, cap),
+                        _dev_ptr(out.get("trace_color"), torch.uint8, cap),
+                        _dev_ptr(out.get("trace_slots"), torch.uint8, nb))
+        _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
+                                 ctypes.byref(ro), _stream(stream)), "dtsdf_render")
+        return out
+
+    def export(self) -> dict:
+        b = _Blob()
+        _check(_lib.dtsdf_export(self._h, ctypes.byref(b)), "dtsdf_export")
+        n = b.n_bricks
+        out = dict(keys=np.zeros((n, 4), np.int32), sdf=np.zeros((n, 512), np.float32),
+                   w=np.zeros((n, 512), np.float32), rgb=np.zeros((n, 512, 3), np.uint8),
+                   wc=np.zeros((n, 512), np.float32))
+        b.keys = out["keys"].ctypes.data
+        b.sdf = out["sdf"].ctypes.data
+        b.w = out["w"].ctypes.data
+        b.rgb = out["rgb"].ctypes.data
+        b.wc = out["wc"].ctypes.data
+        _check(_lib.dtsdf_export(self._h, ctypes.byref(b)), "dtsdf_export")
+        return out
+
+    def load(self, blob: dict) -> None:
+        keys = np.ascontiguousarray(blob["keys"], np.int32)
+        sdf = np.ascontiguousarray(blob["sdf"], np.float32)
+        w = np.ascontiguousarray(blob["w"], np.float32)
+        rgb = blob.get("rgb")
+        wc = blob.get("wc")
+        rgb = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
+        wc = None if wc is None else np.ascontiguousarray(wc, np.float32)
+        b = _Blob(keys.shape[0], keys.ctypes.data, sdf.ctypes.data, w.ctypes.data,
+                  rgb.ctypes.data if rgb is not None else None,
+                  wc.ctypes.data if wc is not None else None)
+        _check(_lib.dtsdf_import(self._h, ctypes.byref(b)), "dtsdf_import")
+
+
+def vertex_normal(depth: torch.Tensor, cam, depth_scale: float = 1.0, stream=None):
+    """(vertex, normal) as (3, H, W) float32 device tensors."""
+    H, W = int(cam.height), int(cam.width)
+    v = torch.empty((3, H, W), dtype=torch.float32, device=depth.device)
+    n = torch.empty((3, H, W), dtype=torch.float32, device=depth.device)
+    _check(_lib.dtsdf_vertex_normal(_dev_ptr(depth, torch.float32, H * W),
+                                    ctypes.byref(_intr(cam)), depth_scale,
+                                    _dev_ptr(v, torch.float32), _dev_ptr(n, torch.float32),
+                                    _stream(stream)), "dtsdf_vertex_normal")
+    return v, n
+
+
+def depth_downsample(depth: torch.Tensor, stream=None) -> torch.Tensor:
+    H, W = depth.shape
+    out = torch.empty((H // 2, W // 2), dtype=torch.float32, device=depth.device)
+    _check(_lib.dtsdf_depth_downsample(_dev_ptr(depth, torch.float32), W, H,
+                                       _dev_ptr(out, torch.float32), _stream(stream)),
+           "dtsdf_depth_downsample")
+    return out
+
+
+@dataclasses.dataclass
+class IcpParams:
+    max_dist: float = 0.10
+    max_angle_deg: float = 20.0
+    weight: int = ICP_W_CONST
+    z_min: float = 0.1
+    min_inliers_per_dim: int = 64
+
+
+def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
+             model_vertex: torch.Tensor, model_normal: torch.Tensor,
+             model_mask: Optional[torch.Tensor], model_cam, T_model_live, dim: int = 6,
+             params: IcpParams = IcpParams(), stream=None):
+    """One ICP Gauss-Newton step; returns (status, updated T (4x4), result dict)."""
+    Hl, Wl = int(live_cam.height), int(live_cam.width)
+    Hm, Wm = int(model_cam.height), int(model_cam.width)
+    live = _Image(_dev_ptr(live_vertex, torch.float32, 3 * Hl * Wl),
+                  _dev_ptr(live_normal, torch.float32, 3 * Hl * Wl), None, _intr(live_cam))
+    model = _Image(_dev_ptr(model_vertex, torch.float32, 3 * Hm * Wm),
+                   _dev_ptr(model_normal, torch.float32, 3 * Hm * Wm),
+                   _dev_ptr(model_mask, torch.uint8, Hm * Wm) if model_mask is not None else None,
+                   _intr(model_cam))
+    p = _IcpParams(params.max_dist, params.max_angle_deg, params.weight, params.z_min,
+                   params.min_inliers_per_dim)
+    T = _pose(T_model_live)
+    r = _IcpResult()
+    status = _lib.icp_step(ctypes.byref(live), ctypes.byref(model), dim, ctypes.byref(p), T,
+                           ctypes.byref(r), _stream(stream))
+    _check(status, "icp_step", allow=(E_DEGENERATE,))
+    res = dict(xi=np.array(r.xi[:dim]), H=np.array(r.H[:dim * dim]).reshape(dim, dim),
+               g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm)
+    return status, np.array(T[:]).reshape(4, 4), res
+
+
+def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
+        iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
+        depth_scale: float = 1.0, stream=None):
+    """Coarse-to-fine ICP: model_levels[l] = (vertex, normal, mask, cam) at level l.
+    ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine."""
+    L = len(model_levels)
+    pyr = [live_depth]
+    for _ in range(1, L):
+        pyr.append(depth_downsample(pyr[-1], stream=stream))
+    T = np.array(T0, np.float64)
+    log = []
+    for l in reversed(range(L)):
+        cam_l = level_camera(live_cam, l)
+        v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
+        mv, mn, mm, mcam = model_levels[l]
+        for _ in range(iters[l]):
+            status, T_new, res = icp_step(v, n, cam_l, mv, mn, mm, mcam, T, dim, params, stream)
+            if status != OK:
+                log.append(dict(level=l, status="degenerate", inliers=res["inliers"]))
+                break
+            T = T_new
+            log.append(dict(level=l, inliers=res["inliers"], err=res["error"],
+                            step=res["step_norm"]))
+            if res["step_norm"] < min_step:
+                break
+    return T, log
+
+
+@dataclasses.dataclass(frozen=True)
+class LevelCamera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+
+def level_camera(cam, l: int):
+    """Intrinsics of pyramid level l: f / 2^l, c_l = (c + 0.5) / 2^l - 0.5."""
+    if l == 0:
+        return cam
+    s = float(2 ** l)
+    return LevelCamera(int(cam.width) >> l, int(cam.height) >> l, cam.fx / s, cam.fy / s,
+                       (cam.cx + 0.5) / s - 0.5, (cam.cy + 0.5) / s - 0.5)

@@ -1,0 +1,303 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests import parity as P
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dtsdf():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2301_12796_amd import dtsdf as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def tiny_oracle():
+    m = O.OracleMap(P.tiny_oracle_params())
+    frames = synth.tiny_frames(10)
+    for f in frames:
+        m.integrate(f["depth"], f["rgb"], P.TINY_CAM, f["T_wc"])
+    return m, frames
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def test_render_tiny_identical_map(dtsdf, tiny_oracle):
+    """Config-1 map fused by the oracle, imported into the GPU map; one 160x120 view."""
+    om, _ = tiny_oracle
+    blob = om.export()
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    gm.load(blob)
+    ref_map = O.OracleMap(P.tiny_oracle_params())
+    ref_map.load(blob)                               # the oracle renders the same float32 map
+    T = synth.tiny_render_pose()
+    print("case: tiny render phi=0.3, 160x120", flush=True)
+    out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
+    ref = ref_map.render(P.TINY_CAM, T, z_far=2.5)
+    st = P.compare_render(out, ref, name="tiny")
+    assert st["compared"] > 5000
+
+
+@pytest.mark.parametrize("phi", [0.0, 1.3, 2.9, 4.4])
+def test_render_tiny_other_views(dtsdf, tiny_oracle, phi):
+    om, _ = tiny_oracle
+    blob = om.export()
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    gm.load(blob)
+    ref_map = O.OracleMap(P.tiny_oracle_params())
+    ref_map.load(blob)
+    T = synth.tiny_render_pose(phi)
+    print(f"case: tiny render phi={phi}", flush=True)
+    out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
+    ref = ref_map.render(P.TINY_CAM, T, z_far=2.5)
+    P.compare_render(out, ref, name=f"tiny phi={phi}")
+
+
+def test_render_is_bitwise_deterministic(dtsdf, tiny_oracle):
+    om, _ = tiny_oracle
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    gm.load(om.export())
+    T = synth.tiny_render_pose()
+    a = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
+    b = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_integrate_tiny_voxelwise(dtsdf, tiny_oracle):
+    """The GPU fuses the same ten frames into a dense map; voxel values match the oracle."""
+    om, frames = tiny_oracle
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    print("case: tiny integrate 10 frames", flush=True)
+    for f in frames:
+        gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.TINY_CAM, f["T_wc"])
+    torch.cuda.synchronize()
+    st = P.compare_maps(gm.export(), om.export(), n_frames=len(frames), name="tiny")
+    assert st["only_gpu"] == 0 and st["only_oracle"] == 0
+    assert st["ok"], st
+
+
+def test_end_to_end_tiny(dtsdf, tiny_oracle):
+    """Each side fuses its own map and renders it: reported with the same bars."""
+    om, frames = tiny_oracle
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    for f in frames:
+        gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.TINY_CAM, f["T_wc"])
+    T = synth.tiny_render_pose()
+    out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
+    ref = om.render(P.TINY_CAM, T, z_far=2.5)
+    st = P.compare_render(out, ref, name="tiny end-to-end")
+    assert st["compared"] > 5000
+
+
+@pytest.fixture(scope="module")
+def room_oracle():
+    """Room map fused by the oracle from 3 frames spread over the trajectory (640x480)."""
+    sc = synth.room_scene()
+    idx = [0, 100, 200]
+    frames = synth.room_frames(idx, scene=sc)
+    m = O.OracleMap(P.room_oracle_params())
+    for f in frames:
+        m.integrate(f["depth"], f["rgb"], P.ROOM_CAM, f["T_wc"])
+    return m, frames
+
+
+def test_integrate_room_sparse_allocation_and_values(dtsdf, room_oracle):
+    om, frames = room_oracle
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf))
+    print("case: room integrate 3 frames 640x480", flush=True)
+    # required / allowed allocation sets from the oracle's request lists
+    probe = O.OracleMap(P.room_oracle_params())
+    required, allowed = set(), set()
+    for f in frames:
+        keys, border, alloc = probe.requests(f["depth"], P.ROOM_CAM, f["T_wc"])
+        for k, b, a in zip(map(tuple, keys), border, alloc):
+            allowed.add(k)
+            if a and not b:
+                required.add(k)
+        st = gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.ROOM_CAM, f["T_wc"], stats=True)
+        assert st["dropped"] == 0
+    gb = gm.export()
+    gset = set(map(tuple, gb["keys"]))
+    assert required <= gset, len(required - gset)
+    assert gset <= allowed, len(gset - allowed)
+    st = P.compare_maps(gb, om.export(), n_frames=len(frames), name="room")
+    assert st["ok"], st
+
+
+def test_render_room_full_size_sampled(dtsdf, room_oracle):
+    """640x480 render of the oracle's room map in the benchmark's launch configuration;
+    the oracle renders 3000 sampled pixels plus two full rows."""
+    om, _ = room_oracle
+    blob = om.export()
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf))
+    gm.load(blob)
+    ref_map = O.OracleMap(P.room_oracle_params())
+    ref_map.load(blob)
+    for k in (0, 37, 120):
+        T = synth.room_pose(k)
+        print(f"case: room render pose {k}", flush=True)
+        out = P.to_numpy_out(gm.render(P.ROOM_CAM, T))
+        pix = P.random_pixels(P.ROOM_CAM, 3000, seed=k)
+        rows = np.stack(np.meshgrid(np.arange(640), [100, 333]), -1).reshape(-1, 2)
+        pix = np.concatenate([pix, rows])
+        ref = ref_map.render(P.ROOM_CAM, T, pixels=pix)
+        st = P.compare_render(out, ref, pixels=pix, name=f"room pose {k}")
+        assert st["hits"] > 500
+
+
+def test_empty_map_renders_nothing(dtsdf):
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf, capacity=64, buckets=256))
+    out = P.to_numpy_out(gm.render(P.ROOM_CAM, synth.room_pose(3)))
+    assert out["mask"].sum() == 0 and np.all(out["depth"] == 0)
+
+
+def test_vertex_normal_matches_oracle(dtsdf):
+    f = synth.room_frames([10])[0]
+    v, n = dtsdf.vertex_normal(_dev(f["depth"]), P.ROOM_CAM)
+    V, N, ok = O.vertex_normal_map(f["depth"], P.ROOM_CAM)
+    v = v.cpu().numpy().transpose(1, 2, 0)
+    n = n.cpu().numpy().transpose(1, 2, 0)
+    gok = np.any(n != 0, axis=-1)
+    assert np.array_equal(gok, ok)
+    assert np.max(np.abs(v - V)) < 1e-6
+    assert np.max(np.abs(n[ok] - N[ok])) < 1e-6
+
+
+def test_depth_downsample_matches_oracle(dtsdf):
+    f = synth.room_frames([10])[0]
+    d = dtsdf.depth_downsample(_dev(f["depth"])).cpu().numpy()
+    ref = O.depth_pyramid(f["depth"], 2)[1]
+    assert np.array_equal(d > 0, ref > 0)
+    assert np.max(np.abs(d - ref)) < 1e-6
+
+
+def _analytic_model(sc, cam, T):
+    f = synth.render_frame(sc, cam, T)
+    V = cam.pixel_rays() * f["true_depth"][..., None]
+    return V, f["normal"], f["hit"].astype(np.uint8)
+
+
+@pytest.mark.parametrize("dim", [6, 7])
+def test_icp_step_normal_equations(dtsdf, dim):
+    """One associate+reduce+solve step: H, g, inliers and the updated pose vs the oracle."""
+    sc = synth.room_scene()
+    cam = P.ROOM_CAM
+    T = synth.room_pose(40)
+    live = synth.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012, seed=5)["depth"]
+    V, N, M = _analytic_model(sc, cam, T)
+    rng = np.random.default_rng(7)
+    dT = synth.perturb_pose(0.02, math.radians(2.0), rng)
+    lv, ln = dtsdf.vertex_normal(_dev(live), cam)
+    mv = _dev(V.transpose(2, 0, 1).astype(np.float32))
+    mn = _dev(N.transpose(2, 0, 1).astype(np.float32))
+    mm = _dev(M)
+    status, T_new, res = dtsdf.icp_step(lv, ln, cam, mv, mn, mm, cam, dT, dim=dim)
+    assert status == dtsdf.OK
+    LV, LN, LOK = O.vertex_normal_map(live, cam)
+    Href, gref, err, cnt = O.associate_reduce(LV, LN, LOK, V.astype(np.float32).astype(np.float64),
+                                              N.astype(np.float32).astype(np.float64), M, cam,
+                                              dT, dim)
+    print(f"[icp step dim={dim}] inliers gpu {res['inliers']} oracle {cnt}", flush=True)
+    assert abs(res["inliers"] - cnt) <= max(5, 1e-4 * cnt)
+    np.testing.assert_allclose(res["H"], Href, rtol=2e-3, atol=1e-3 * np.abs(Href).max())
+    xi_ref = O.solve_step(Href, gref)
+    T_ref = O.exp_map(xi_ref) @ dT
+    assert np.max(np.abs(T_new - T_ref)) < 1e-5
+
+
+@pytest.mark.parametrize("dim", [6, 7])
+def test_icp_converges_like_oracle(dtsdf, dim):
+    """Three-level ICP (10/5/4 iterations) on the same live frame and model maps: final
+    poses agree within 1e-5 rad / 1e-5 m."""
+    sc = synth.room_scene()
+    cam = P.ROOM_CAM
+    T = synth.room_pose(70)
+    s = 1.0 if dim == 6 else synth.precision_scale()
+    live = synth.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012, seed=9,
+                              depth_scale=s)["depth"]
+    rng = np.random.default_rng(11)
+    dT0 = synth.perturb_pose(0.02, math.radians(2.0), rng)
+    if dim == 7:
+        dT0[:3, :3] *= 1.01 / s
+    levels_o, levels_g = [], []
+    for l in range(3):
+        c = cam.level(l)
+        V, N, M = _analytic_model(sc, c, T)
+        V = V.astype(np.float32).astype(np.float64)
+        N = N.astype(np.float32).astype(np.float64)
+        levels_o.append((V, N, M, c))
+        levels_g.append((_dev(V.transpose(2, 0, 1).astype(np.float32)),
+                         _dev(N.transpose(2, 0, 1).astype(np.float32)), _dev(M), c))
+    T_o, _ = O.icp(live, cam, levels_o, dT0, dim=dim)
+    T_g, log = dtsdf.icp(_dev(live), cam, levels_g, dT0, dim=dim)
+    dR = T_g[:3, :3] @ np.linalg.inv(T_o[:3, :3])
+    sc_g = np.cbrt(np.linalg.det(T_g[:3, :3]))
+    sc_o = np.cbrt(np.linalg.det(T_o[:3, :3]))
+    ang = P.rotation_angle(dR / np.cbrt(np.linalg.det(dR)))
+    dt = np.linalg.norm(T_g[:3, 3] - T_o[:3, 3])
+    print(f"[icp dim={dim}] rot {ang:.2e} rad trans {dt:.2e} m scale {sc_g:.8f} vs {sc_o:.8f}",
+          flush=True)
+    assert ang < 1e-5 and dt < 1e-5 and abs(sc_g - sc_o) < 1e-5
+
+
+def test_icp_is_bitwise_deterministic(dtsdf):
+    sc = synth.room_scene()
+    cam = P.ROOM_CAM
+    T = synth.room_pose(40)
+    live = synth.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012, seed=5)["depth"]
+    V, N, M = _analytic_model(sc, cam, T)
+    lv, ln = dtsdf.vertex_normal(_dev(live), cam)
+    mv = _dev(V.transpose(2, 0, 1).astype(np.float32))
+    mn = _dev(N.transpose(2, 0, 1).astype(np.float32))
+    dT = synth.perturb_pose(0.02, math.radians(2.0), np.random.default_rng(7))
+    r1 = dtsdf.icp_step(lv, ln, cam, mv, mn, _dev(M), cam, dT)
+    r2 = dtsdf.icp_step(lv, ln, cam, mv, mn, _dev(M), cam, dT)
+    assert np.array_equal(r1[1], r2[1])
+    assert np.array_equal(r1[2]["H"], r2[2]["H"])
+
+
+def test_icp_degenerate_on_empty_frame(dtsdf):
+    cam = P.ROOM_CAM
+    z = torch.zeros((cam.height, cam.width), dtype=torch.float32, device="cuda")
+    lv, ln = dtsdf.vertex_normal(z, cam)
+    mv = torch.zeros((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+    status, T, res = dtsdf.icp_step(lv, ln, cam, mv, mv, None, cam, np.eye(4))
+    assert status == dtsdf.E_DEGENERATE and res["inliers"] == 0
+    assert np.array_equal(T, np.eye(4))
+
+
+def test_capacity_overflow_is_reported_and_consistent(dtsdf, room_oracle):
+    _, frames = room_oracle
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf, capacity=500, buckets=1 << 14))
+    st = gm.integrate(_dev(frames[0]["depth"]), None, P.ROOM_CAM, frames[0]["T_wc"], stats=True)
+    assert st["status"] == dtsdf.E_CAPACITY and st["dropped"] > 0 and st["bricks"] == 500
+    info = gm.info()
+    assert info["bricks"] == 500
+    blob = gm.export()
+    assert len(set(map(tuple, blob["keys"]))) == 500
+    out = P.to_numpy_out(gm.render(P.ROOM_CAM, frames[0]["T_wc"]))
+    assert np.isfinite(out["depth"]).all()
+
+
+def test_invalid_arguments_are_rejected(dtsdf):
+    with pytest.raises(dtsdf.DtsdfError) as e:
+        dtsdf.Map(dtsdf.Params(voxel_size=0.01, truncation=0.04, hash_buckets=1000))
+    assert e.value.status == dtsdf.E_INVAL
+    with pytest.raises(dtsdf.DtsdfError):
+        dtsdf.Map(dtsdf.Params(voxel_size=0.01, truncation=0.04, theta=0.5))
