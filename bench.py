@@ -126,30 +126,39 @@ def main():
     tb = torch.zeros(params.brick_capacity, dtype=torch.uint8, device=dev)
     tc = torch.zeros(params.brick_capacity, dtype=torch.uint8, device=dev)
     ts = torch.zeros(params.hash_buckets, dtype=torch.uint8, device=dev)
-    traced = dict(out, trace_bricks=tb, trace_color=tc, trace_slots=ts)
+    tcnt = torch.zeros((H, W, 4), dtype=torch.int32, device=dev)
+    traced = dict(out, trace_bricks=tb, trace_color=tc, trace_slots=ts, trace_counts=tcnt)
     bytes_per_pose = []
     n_bd, n_cd, n_sl = [], [], []
     hits = []
+    counts = []
     for T in poses:
         tb.zero_(); tc.zero_(); ts.zero_()
         gm.render(cam, T, out=traced)
         nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
         n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
         hits.append(int(out["mask"].sum()))
+        c = tcnt.view(H // 8, 8, W // 8, 8, 4).permute(0, 2, 1, 3, 4).reshape(-1, 64, 4).float()
+        counts.append(torch.stack([c.mean((0, 1)), c.amax(1).mean(0)]).cpu().numpy())
         bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +
                               ns * BUCKET_BYTES + H * W * OUT_BYTES_PER_RAY)
     bytes_per_launch = float(np.mean(bytes_per_pose))
-    log(f"per pose: bricks {np.mean(n_bd):.0f}, colour bricks {np.mean(n_cd):.0f}, buckets "
+    log(f"per pose: bricks {np.mean(n_bd):.0f}, colour bricks {np.mean(n_cd):.0f}, entries "
         f"{np.mean(n_sl):.0f}, hit rate {np.mean(hits) / (H * W):.3f}, "
         f"{bytes_per_launch / 1e6:.2f} MB")
+    cnt = np.mean(counts, 0)
+    per_ray = dict(zip(["eval", "skip", "absent", "refine"], cnt[0].round(2).tolist()))
+    per_wave_max = dict(zip(["eval", "skip", "absent", "refine"], cnt[1].round(2).tolist()))
+    log(f"per ray mean {per_ray}; per 8x8 wave, mean of the lane maximum {per_wave_max}")
 
     if args.copy_probe:
+        # a plain elementwise kernel reading and writing 256 MiB each (counter calibration)
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
-        log(f"copy probe: 3 copies of {a.numel() * 4} bytes")
+        log(f"copy probe: 3 x (read {a.numel() * 4} B, write {b.numel() * 4} B)")
 
     # ---- timed render steps ------------------------------------------------------------
     def step(evs=None):
@@ -271,6 +280,8 @@ def main():
         "integrate_ms_per_frame": integ_ms / n,
         "icp_ms_per_frame": icp_ms,
         "hit_rate": float(np.mean(hits) / (H * W)),
+        "samples_per_ray": per_ray,
+        "samples_per_wave_max": per_wave_max,
         "input_generation_s": t_gen,
     }
     print(json.dumps(line), flush=True)

@@ -95,7 +95,10 @@ typedef struct {
  * The trace_* arrays serve traffic accounting: when given, the caller zeroes them and the
  * render sets to 1 the entry of every brick whose (sdf, w) a sample read (trace_bricks,
  * brick_capacity bytes), every brick whose colour an output read (trace_color, same size)
- * and every hash bucket a lookup probed (trace_slots, hash_buckets bytes). */
+ * and every hash entry whose brick indices a lookup read (trace_slots, hash_buckets bytes);
+ * trace_counts (4 int32 per pixel) receives the number of full evaluations in blocks that
+ * may hold a crossing, evaluations at the end of skipped positive blocks, jumps over absent
+ * blocks, and refinement evaluations. */
 typedef struct {
   float* depth;   /* H*W camera-frame z of the hit, 0 where nothing was hit */
   float* vertex;  /* 3*H*W planes, camera-frame hit point */
@@ -105,6 +108,7 @@ typedef struct {
   uint8_t* trace_bricks;
   uint8_t* trace_color;
   uint8_t* trace_slots;
+  int32_t* trace_counts;
 } dtsdf_render_out;
 
 /* Host-side map image used for checkpoints and exact map transfer.  Bricks are listed in

@@ -14,9 +14,26 @@
 //                                   (l % 8, l / 8 % 8, l / 64); the march reads only these
 //   rgb      uint32[capacity*512]   r | g << 8 | b << 16 colour code per voxel
 //   wc       float[capacity*512]    colour weight per voxel
-//   counters int32[4]               [0] bricks handed out (may overshoot the capacity while a
+//   counters int32[16]              [0] bricks handed out (may overshoot the capacity while a
 //                                   frame allocates), [1] dropped requests, [2] hash overflow,
-//                                   [3] occupied hash entries
+//                                   [3] occupied hash entries, [4..9] bounding box of the
+//                                   occupied blocks (min x, y, z, max x, y, z)
+//   sub_min  float[capacity*8]      per 4^3 sub-block of a brick: min sdf over its voxels with
+//                                   w > 0 (+inf if none); sub-block s = sx | sy << 1 | sz << 2
+//   slot_min float[buckets*8]       per hash entry and sub-block: min of sub_min over the
+//                                   block's directions
+//
+// Render index (updated after every integrate / import): a dense grid over the bounding box
+// of the occupied blocks.  288 GB of HBM make a dense block grid affordable for room- and
+// building-scale maps (~6 bytes per 4 cm block), and it replaces hash probing in the ray
+// march by direct loads:
+//   grid_slot int32[gx*gy*gz]       hash slot of the block, -1 if absent
+//   grid_mask uint8[gx*gy*gz]       bit s set: every cell based in sub-block s has all corner
+//                                   values > kSkipMin in every direction, so the combined SDF
+//                                   is positive wherever defined there and no crossing can end
+//                                   in that sub-block
+//   macro1   uint8[ceil(g/4)^3]     1 if any block of the 4^3-block cell is present
+//   macro2   uint8[ceil(g/16)^3]    1 if any block of the 16^3-block cell is present
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +47,8 @@ constexpr int kB = 8;
 constexpr int kVox = 512;
 constexpr uint64_t kEmptyKey = ~0ull;
 constexpr int kKeyBias = 1 << 19;   // block coordinates must lie in [-2^19, 2^19)
+constexpr float kSkipMin = 1e-6f;   // margin keeping interpolated values strictly positive
+constexpr int64_t kMaxGridBlocks = 1ll << 31;
 
 struct alignas(32) HashEntry {
   uint64_t key;
@@ -71,6 +90,12 @@ struct MapView {
   float* wc;
   const int4* bkey;
   uint32_t capacity;
+  const int32_t* grid_slot;
+  const uint8_t* grid_mask;
+  const uint8_t* macro1;
+  const uint8_t* macro2;
+  int gx0, gy0, gz0;        // grid origin (block coordinates)
+  int gx, gy, gz;           // grid dimensions (blocks)
   double voxel, inv_voxel;
   float tau, theta, w_carve, w_max, w_min;
   double step;
@@ -130,6 +155,15 @@ struct dtsdf_map {
   int64_t n_bricks;     // host mirror of the bricks in use
   int64_t n_blocks;     // host mirror of occupied entries (updated on sync points)
   int64_t dropped;
+  float* sub_min;
+  float* slot_min;
+  int32_t* grid_slot;
+  uint8_t* grid_mask;
+  uint8_t* macro1;
+  uint8_t* macro2;
+  int32_t grid_lo[3], grid_dim[3];
+  int64_t grid_cap;     // allocated grid cells
+  int64_t macro_cap;    // allocated bytes of each macro grid
   // integration scratch, grown on demand
   int64_t img_cap;
   float* vmap;
@@ -138,4 +172,38 @@ struct dtsdf_map {
 
 namespace dtsdf {
 MapView make_view(const dtsdf_map* m);
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Minima of the eight 4^3 sub-blocks of brick `b` over voxels with w > 0 (+inf if none),
+// written to out8[0..7]; called by every thread of a 256-thread workgroup.
+__device__ inline void brick_sub_min(const float2* __restrict__ sw, size_t b, float* out8) {
+  __shared__ float vals[kVox];
+  for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
+    const float2 s = sw[b * kVox + l];
+    vals[l] = s.y > 0.f ? s.x : INFINITY;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < 2; ++q) {
+    const int sb = 2 * wave + q;
+    const int lx = (lane & 3) + 4 * (sb & 1), ly = ((lane >> 2) & 3) + 4 * ((sb >> 1) & 1),
+              lz = (lane >> 4) + 4 * (sb >> 2);
+    float v = vals[lx + 8 * ly + 64 * lz];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    if (lane == 0) out8[sb] = v;
+  }
+  __syncthreads();
+}
+// Recomputes sub_min of every brick in use.
+dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st);
+// Enqueues the bounding-box reduction into counters[4..9].
+void launch_bbox(dtsdf_map* m, hipStream_t st);
+// Makes the grid cover the bounding box `hb` (host copy); reallocates and clears on growth.
+dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st);
+// Enqueues the slot scatter and the skip codes.
+dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st);
+// All of the above (synchronises `st`).
+dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st);
 }

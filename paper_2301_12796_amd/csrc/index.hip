@@ -1,0 +1,257 @@
+// Per-brick summaries and the dense render index (see dtsdf_internal.hpp).
+#include <climits>
+#include <cmath>
+
+#include "dtsdf_internal.hpp"
+
+using namespace dtsdf;
+
+namespace {
+
+// Sub-block minima of every brick in use; one workgroup per brick.
+__global__ __launch_bounds__(256) void brick_stats_k(const float2* __restrict__ sw, float* sub_min) {
+  brick_sub_min(sw, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
+}
+
+__device__ inline bool slot_present(const HashEntry& e) {
+  if (e.key == kEmptyKey) return false;
+  for (int d = 0; d < 6; ++d)
+    if (e.brick[d] >= 0) return true;
+  return false;
+}
+
+// Bounding box of the occupied blocks: min/max folded across the wave with xor shuffles and
+// across the workgroup in LDS, so each workgroup issues six atomics.
+__global__ __launch_bounds__(256) void bbox_k(const HashEntry* __restrict__ e, uint32_t buckets,
+                                              int32_t* bbox) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  int v[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  if (s < buckets) {
+    const HashEntry ent = e[s];
+    if (slot_present(ent)) {
+      int b[3];
+      unpack_key(ent.key, b[0], b[1], b[2]);
+      for (int k = 0; k < 3; ++k) v[k] = v[3 + k] = b[k];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[k] = min(v[k], __shfl_xor(v[k], off, 64));
+      v[3 + k] = max(v[3 + k], __shfl_xor(v[3 + k], off, 64));
+    }
+  __shared__ int part[4][6];
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; ++k) part[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    int r = part[0][k];
+    for (int w = 1; w < 4; ++w) r = k < 3 ? min(r, part[w][k]) : max(r, part[w][k]);
+    if (k < 3 && r != INT_MAX) atomicMin(&bbox[k], r);
+    if (k >= 3 && r != INT_MIN) atomicMax(&bbox[k], r);
+  }
+}
+
+__global__ __launch_bounds__(256) void grid_clear_k(int32_t* slot, uint8_t* mask, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  slot[i] = -1;
+  mask[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void bytes_clear_k(uint8_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+struct Grid {
+  int x0, y0, z0, nx, ny, nz;
+  int m1x, m1y, m2x, m2y;   // macro grid dimensions (x, y)
+  __device__ int64_t index(int bx, int by, int bz) const {
+    int ix = bx - x0, iy = by - y0, iz = bz - z0;
+    if (ix < 0 || iy < 0 || iz < 0 || ix >= nx || iy >= ny || iz >= nz) return -1;
+    return ((int64_t)iz * ny + iy) * nx + ix;
+  }
+};
+
+__global__ __launch_bounds__(256) void grid_scatter_k(const HashEntry* __restrict__ e,
+                                                      uint32_t buckets, Grid g, int32_t* slot,
+                                                      uint8_t* macro1, uint8_t* macro2) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  int b[3];
+  unpack_key(ent.key, b[0], b[1], b[2]);
+  int64_t i = g.index(b[0], b[1], b[2]);
+  if (i < 0) return;
+  slot[i] = (int32_t)s;
+  const int ix = b[0] - g.x0, iy = b[1] - g.y0, iz = b[2] - g.z0;
+  macro1[((int64_t)(iz >> 2) * g.m1y + (iy >> 2)) * g.m1x + (ix >> 2)] = 1;
+  macro2[((int64_t)(iz >> 4) * g.m2y + (iy >> 4)) * g.m2x + (ix >> 4)] = 1;
+}
+
+// Per entry and sub-block: min over the block's directions of the sub-block minima.
+__global__ __launch_bounds__(256) void slot_min_k(const HashEntry* __restrict__ e,
+                                                  uint32_t buckets,
+                                                  const float* __restrict__ sub_min,
+                                                  float* slot_min) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  float mn[8];
+  for (int q = 0; q < 8; ++q) mn[q] = INFINITY;
+  for (int d = 0; d < 6; ++d) {
+    const int br = ent.brick[d];
+    if (br < 0) continue;
+    for (int q = 0; q < 8; ++q) mn[q] = fminf(mn[q], sub_min[(size_t)br * 8 + q]);
+  }
+  for (int q = 0; q < 8; ++q) slot_min[(size_t)s * 8 + q] = mn[q];
+}
+
+// Skip mask of every present block: bit q is set if the minima of the 2x2x2 sub-blocks
+// starting at sub-block q (possibly in the +x/+y/+z neighbour blocks) all exceed kSkipMin;
+// those sub-blocks hold every corner a cell based in sub-block q can reach.  Absent
+// neighbours make the cells that need them undefined and do not constrain the mask.
+__global__ __launch_bounds__(256) void grid_mask_k(const HashEntry* __restrict__ e,
+                                                   uint32_t buckets, Grid g,
+                                                   const int32_t* __restrict__ slot,
+                                                   const float* __restrict__ slot_min,
+                                                   uint8_t* mask) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  int b[3];
+  unpack_key(ent.key, b[0], b[1], b[2]);
+  int64_t i = g.index(b[0], b[1], b[2]);
+  if (i < 0) return;
+  int nslot[8];
+  for (int o = 0; o < 8; ++o) {
+    int64_t j = o == 0 ? i : g.index(b[0] + (o & 1), b[1] + ((o >> 1) & 1), b[2] + ((o >> 2) & 1));
+    nslot[o] = j < 0 ? -1 : slot[j];
+  }
+  uint8_t bits = 0;
+  for (int q = 0; q < 8; ++q) {
+    const int qs[3] = {q & 1, (q >> 1) & 1, q >> 2};
+    float mn = INFINITY;
+    for (int dd = 0; dd < 8; ++dd) {
+      const int t[3] = {qs[0] + (dd & 1), qs[1] + ((dd >> 1) & 1), qs[2] + (dd >> 2)};
+      const int o = (t[0] >> 1) | ((t[1] >> 1) << 1) | ((t[2] >> 1) << 2);
+      const int sub = (t[0] & 1) | ((t[1] & 1) << 1) | ((t[2] & 1) << 2);
+      const int sl = nslot[o];
+      if (sl >= 0) mn = fminf(mn, slot_min[(size_t)sl * 8 + sub]);
+    }
+    if (mn > kSkipMin) bits |= (uint8_t)(1u << q);
+  }
+  mask[i] = bits;
+}
+
+__global__ void bbox_reset_k(int32_t* bbox) {
+  if (threadIdx.x < 3) bbox[threadIdx.x] = INT_MAX;
+  else if (threadIdx.x < 6) bbox[threadIdx.x] = INT_MIN;
+}
+
+}  // namespace
+
+namespace dtsdf {
+
+dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st) {
+  if (m->n_bricks > 0)
+    hipLaunchKernelGGL(brick_stats_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, m->sw,
+                       m->sub_min);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+void launch_bbox(dtsdf_map* m, hipStream_t st) {
+  int32_t* bbox = m->counters + 4;
+  hipLaunchKernelGGL(bbox_reset_k, dim3(1), dim3(64), 0, st, bbox);
+  hipLaunchKernelGGL(bbox_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
+                     m->buckets, bbox);
+}
+
+dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st) {
+  const bool empty = hb[0] > hb[3];
+  if (empty) {
+    for (int k = 0; k < 3; ++k) m->grid_dim[k] = 0;
+    return DTSDF_OK;
+  }
+  bool inside = m->grid_dim[0] > 0;
+  for (int k = 0; k < 3 && inside; ++k)
+    inside = hb[k] >= m->grid_lo[k] && hb[3 + k] < m->grid_lo[k] + m->grid_dim[k];
+  if (inside) return DTSDF_OK;
+  // new grid: bounding box padded by 8 blocks per side so that growth is rare
+  const int pad = m->p.dense ? 1 : 8;
+  int lo[3], dim[3];
+  int64_t cells = 1;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = hb[k] - pad;
+    dim[k] = hb[3 + k] - hb[k] + 1 + 2 * pad;
+    cells *= dim[k];
+  }
+  if (cells > kMaxGridBlocks) return DTSDF_E_CAPACITY;
+  const int64_t c1 = (int64_t)ceil_div(dim[0], 4) * ceil_div(dim[1], 4) * ceil_div(dim[2], 4);
+  const int64_t c2 = (int64_t)ceil_div(dim[0], 16) * ceil_div(dim[1], 16) * ceil_div(dim[2], 16);
+  if (cells > m->grid_cap || c1 > m->macro_cap) {
+    DTSDF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(m->grid_slot);
+    (void)hipFree(m->grid_mask);
+    (void)hipFree(m->macro1);
+    (void)hipFree(m->macro2);
+    m->grid_slot = nullptr;
+    m->grid_mask = m->macro1 = m->macro2 = nullptr;
+    m->grid_cap = 0;
+    m->macro_cap = 0;
+    for (int k = 0; k < 3; ++k) m->grid_dim[k] = 0;
+    const int64_t want = cells + cells / 4;
+    const int64_t want1 = c1 + c1 / 4;   // c2 <= c1
+    if (hipMalloc(&m->grid_slot, sizeof(int32_t) * want) != hipSuccess ||
+        hipMalloc(&m->grid_mask, want) != hipSuccess ||
+        hipMalloc(&m->macro1, want1) != hipSuccess || hipMalloc(&m->macro2, want1) != hipSuccess)
+      return DTSDF_E_NOMEM;
+    m->grid_cap = want;
+    m->macro_cap = want1;
+  }
+  for (int k = 0; k < 3; ++k) {
+    m->grid_lo[k] = lo[k];
+    m->grid_dim[k] = dim[k];
+  }
+  hipLaunchKernelGGL(grid_clear_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st,
+                     m->grid_slot, m->grid_mask, cells);
+  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c1 + 255) / 256)), dim3(256), 0, st, m->macro1, c1);
+  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c2 + 255) / 256)), dim3(256), 0, st, m->macro2, c2);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st) {
+  if (m->grid_dim[0] == 0) return DTSDF_OK;
+  Grid g{m->grid_lo[0], m->grid_lo[1], m->grid_lo[2], m->grid_dim[0], m->grid_dim[1], m->grid_dim[2],
+         ceil_div(m->grid_dim[0], 4), ceil_div(m->grid_dim[1], 4),
+         ceil_div(m->grid_dim[0], 16), ceil_div(m->grid_dim[1], 16)};
+  const dim3 grd((m->buckets + 255) / 256);
+  hipLaunchKernelGGL(grid_scatter_k, grd, dim3(256), 0, st, m->entries, m->buckets, g,
+                     m->grid_slot, m->macro1, m->macro2);
+  hipLaunchKernelGGL(slot_min_k, grd, dim3(256), 0, st, m->entries, m->buckets, m->sub_min,
+                     m->slot_min);
+  hipLaunchKernelGGL(grid_mask_k, grd, dim3(256), 0, st, m->entries, m->buckets, g,
+                     m->grid_slot, m->slot_min, m->grid_mask);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st) {
+  launch_bbox(m, st);
+  int32_t hb[6];
+  DTSDF_HIP(hipMemcpyAsync(hb, m->counters + 4, sizeof(hb), hipMemcpyDeviceToHost, st));
+  DTSDF_HIP(hipStreamSynchronize(st));
+  dtsdf_status s = ensure_grid(m, hb, st);
+  if (s != DTSDF_OK) return s;
+  return launch_index_update(m, st);
+}
+
+}  // namespace dtsdf

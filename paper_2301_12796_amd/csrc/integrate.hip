@@ -188,12 +188,14 @@ struct FuseArgs {
   Pose T;
 };
 
-// Voxel-projection fusion (Sec. 3) of one brick per workgroup.
-__global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a) {
+// Voxel-projection fusion (Sec. 3) of one brick per workgroup.  A brick with any updated
+// voxel refreshes its sub-block minima (sdf over voxels with w > 0) for the render index.
+__global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min) {
   const int4 key = m.bkey[blockIdx.x];
   const int D = key.w;
   const size_t HW = (size_t)a.in.W * a.in.H;
   const double tau = (double)m.tau;
+  bool upd = false;
   for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
     const int lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
     double x[3] = {(double)(key.x * kB + lx) * m.voxel, (double)(key.y * kB + ly) * m.voxel,
@@ -238,6 +240,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a) {
         s.x = (s.x * s.y + 1.0f * m.w_carve) / nw;
         s.y = fminf(nw, m.w_max);
         *swp = s;
+        upd = true;
       }
       continue;
     }
@@ -258,6 +261,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a) {
     s.x = (s.x * s.y + (float)dd * wd) / nw;
     s.y = fminf(nw, m.w_max);
     *swp = s;
+    upd = true;
     if (m.with_color && a.rgb) {
       // colour weight w_c = w_d (1 - min(1, |p - x| / tau)) (eq. color_weight)
       const double dist = sqrt((pc[0] - xc[0]) * (pc[0] - xc[0]) + (pc[1] - xc[1]) * (pc[1] - xc[1]) +
@@ -281,6 +285,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a) {
       }
     }
   }
+  if (__syncthreads_or(upd)) brick_sub_min(m.sw, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
 }
 
 Intr make_intr(const dtsdf_intrinsics* i) {
@@ -362,9 +367,12 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
                        m->counters, max_entries);
     hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
                        m->req, m->bkey, m->buckets, m->p.brick_capacity, m->counters);
-    int32_t c[4];
+    launch_bbox(m, st);
+    int32_t c[10];
     DTSDF_HIP(hipMemcpyAsync(c, m->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     DTSDF_HIP(hipStreamSynchronize(st));
+    dtsdf_status gs = ensure_grid(m, c + 4, st);
+    if (gs != DTSDF_OK) return gs;
     int64_t handed = c[0];
     if (handed > (int64_t)m->p.brick_capacity) {
       int32_t cap = (int32_t)m->p.brick_capacity;
@@ -378,9 +386,12 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
   }
   if (m->n_bricks > 0) {
     FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
-    hipLaunchKernelGGL(fuse_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, make_view(m), fa);
+    hipLaunchKernelGGL(fuse_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, make_view(m), fa,
+                       m->sub_min);
   }
   DTSDF_HIP(hipGetLastError());
+  dtsdf_status is = launch_index_update(m, st);
+  if (is != DTSDF_OK) return is;
   if (stats) {
     stats->new_bricks = m->n_bricks - before;
     stats->dropped = dropped_now;

@@ -20,6 +20,16 @@ MapView make_view(const dtsdf_map* m) {
   v.wc = m->wc;
   v.bkey = m->bkey;
   v.capacity = m->p.brick_capacity;
+  v.grid_slot = m->grid_slot;
+  v.grid_mask = m->grid_mask;
+  v.macro1 = m->macro1;
+  v.macro2 = m->macro2;
+  v.gx0 = m->grid_lo[0];
+  v.gy0 = m->grid_lo[1];
+  v.gz0 = m->grid_lo[2];
+  v.gx = m->grid_dim[0];
+  v.gy = m->grid_dim[1];
+  v.gz = m->grid_dim[2];
   v.voxel = (double)m->p.voxel_size;
   v.inv_voxel = 1.0 / (double)m->p.voxel_size;
   v.tau = m->p.truncation;
@@ -85,7 +95,7 @@ dtsdf_status upload_table(dtsdf_map* m, const std::vector<HostKey>& keys) {
                       hipMemcpyHostToDevice));
   if (!bk.empty())
     DTSDF_HIP(hipMemcpy(m->bkey, bk.data(), sizeof(int4) * bk.size(), hipMemcpyHostToDevice));
-  int32_t counters[4] = {(int32_t)keys.size(), 0, 0, (int32_t)blocks};
+  int32_t counters[16] = {(int32_t)keys.size(), 0, 0, (int32_t)blocks};
   DTSDF_HIP(hipMemcpy(m->counters, counters, sizeof(counters), hipMemcpyHostToDevice));
   m->n_bricks = (int64_t)keys.size();
   m->n_blocks = blocks;
@@ -104,12 +114,20 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->counters);
   (void)hipFree(m->vmap);
   (void)hipFree(m->nmap);
+  (void)hipFree(m->sub_min);
+  (void)hipFree(m->slot_min);
+  (void)hipFree(m->grid_slot);
+  (void)hipFree(m->grid_mask);
+  (void)hipFree(m->macro1);
+  (void)hipFree(m->macro2);
   delete m;
 }
 
 dtsdf_status zero_pool(dtsdf_map* m) {
   size_t nv = (size_t)m->p.brick_capacity * kVox;
   DTSDF_HIP(hipMemset(m->sw, 0, nv * sizeof(float2)));
+  // 0x7f7f7f7f = 3.4e38: a brick without observed voxels bounds nothing
+  DTSDF_HIP(hipMemset(m->sub_min, 0x7f, sizeof(float) * 8 * m->p.brick_capacity));
   if (m->rgb) DTSDF_HIP(hipMemset(m->rgb, 0, nv * sizeof(uint32_t)));
   if (m->wc) DTSDF_HIP(hipMemset(m->wc, 0, nv * sizeof(float)));
   return DTSDF_OK;
@@ -156,7 +174,9 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
             hipMalloc(&m->req, sizeof(uint32_t) * m->buckets) == hipSuccess &&
             hipMalloc(&m->bkey, sizeof(int4) * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->sw, sizeof(float2) * nv) == hipSuccess &&
-            hipMalloc(&m->counters, sizeof(int32_t) * 4) == hipSuccess;
+            hipMalloc(&m->counters, sizeof(int32_t) * 16) == hipSuccess &&
+            hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
+            hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess;
   if (ok && p->with_color)
     ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess &&
          hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
@@ -176,6 +196,7 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
     if (keys.size() > p->brick_capacity || keys.empty()) st = DTSDF_E_INVAL;
   }
   if (st == DTSDF_OK) st = upload_table(m, keys);
+  if (st == DTSDF_OK) st = rebuild_index(m, nullptr);
   if (st == DTSDF_OK && hipDeviceSynchronize() != hipSuccess) st = DTSDF_E_HIP;
   if (st != DTSDF_OK) {
     free_map(m);
@@ -201,8 +222,11 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   out->dropped = m->dropped;
   size_t nv = (size_t)m->p.brick_capacity * kVox;
   out->device_bytes = (int64_t)(sizeof(HashEntry) * m->buckets + sizeof(uint32_t) * m->buckets +
-                                sizeof(int4) * m->p.brick_capacity + sizeof(float2) * nv +
-                                (m->p.with_color ? (sizeof(uint32_t) + sizeof(float)) * nv : 0));
+                                (sizeof(int4) + 8 * sizeof(float)) * m->p.brick_capacity +
+                                8 * sizeof(float) * m->buckets +
+                                sizeof(float2) * nv +
+                                (m->p.with_color ? (sizeof(uint32_t) + sizeof(float)) * nv : 0) +
+                                (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap);
   return DTSDF_OK;
 }
 
@@ -304,6 +328,9 @@ dtsdf_status dtsdf_import(dtsdf_map* m, const dtsdf_blob* b) {
     }
   }
   DTSDF_HIP(hipMemset(m->req, 0, sizeof(uint32_t) * m->buckets));
+  st = brick_stats(m, nullptr);
+  if (st == DTSDF_OK) st = rebuild_index(m, nullptr);
+  if (st != DTSDF_OK) return st;
   DTSDF_HIP(hipDeviceSynchronize());
   return DTSDF_OK;
 }

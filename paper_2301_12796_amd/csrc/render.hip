@@ -1,16 +1,24 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
-// One thread per pixel, 8x8 pixel tiles per wave so that the rays of a wave traverse the same
-// bricks.  Per ray:
+// One thread per pixel; a workgroup is one wave covering an 8x8 pixel tile so that its rays
+// traverse the same bricks.  Tiles are numbered so that the workgroups the dispatcher sends to
+// one XCD (workgroup id mod 8) cover one contiguous band of the image, keeping each band's
+// bricks in that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
 //     sample positions are float64 so that the cell a sample falls in is the exact one,
 //     interpolation and combination are float32;
-//   * a sample whose base voxel lies in a block absent from the hash is undefined in every
-//     direction, so the march jumps to the last lattice point before the block exit (exact);
+//   * blocks are found through the dense render index.  A sample whose base voxel lies in an
+//     absent block is undefined in every direction, so the march jumps to the first lattice
+//     point past the largest empty cell (64, 16 or 4 cm at 5 mm voxels) of the occupancy
+//     hierarchy that contains the block.  In a sub-block whose skip bit is set every value a
+//     cell based there can interpolate is positive, so the combined SDF is positive wherever
+//     defined and no crossing can end there: only its last lattice point is evaluated (it may
+//     start a crossing in what follows).  Both jumps are exact;
 //   * per present direction: trilinear Phi^D, W^D and the analytic gradient of the interpolant
 //     over the 8 corners (all corners allocated with W > 0, else the direction is undefined);
 //     combination weight w_dir(n^D) max(0, <n^D, -r>) W^D (eq. combine_weight) and the
-//     gradient-free fallback W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight);
+//     gradient-free fallback W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight), both summed in
+//     one pass over the directions;
 //   * hit: first k >= 1 with f(t_{k-1}) > 0 >= f(t_k), both defined; the bracket is refined
 //     with the Illinois variant of regula falsi (every fourth step a bisection), undefined
 //     points counting as free space; outputs are evaluated at the bracket end inside the
@@ -25,6 +33,7 @@ namespace {
 
 struct RenderArgs {
   int W, H;
+  int tiles_x, tiles;
   double fx, fy, cx, cy;
   double R[9], t[3];
   double z_near, z_far;
@@ -36,6 +45,7 @@ struct RenderArgs {
   uint8_t* trace_bricks;
   uint8_t* trace_color;
   uint8_t* trace_slots;
+  int32_t* trace_counts;
 };
 
 struct Trace {
@@ -44,26 +54,68 @@ struct Trace {
   uint8_t* slots;
 };
 
-struct BlockCache {
-  int bx, by, bz;
-  int slot;
+// Ray parameter at which the ray leaves the box [lo, hi) (world units).
+__device__ inline double box_exit(const double o[3], const double r[3], const double ir[3],
+                                  const double lo[3], const double hi[3]) {
+  double t = 1e300;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (r[ax] > 0.0) t = fmin(t, (hi[ax] - o[ax]) * ir[ax]);
+    else if (r[ax] < 0.0) t = fmin(t, (lo[ax] - o[ax]) * ir[ax]);
+  }
+  return t;
+}
+
+__device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
+  const int ix = bx - m.gx0, iy = by - m.gy0, iz = bz - m.gz0;
+  if (ix < 0 || iy < 0 || iz < 0 || ix >= m.gx || iy >= m.gy || iz >= m.gz) return -1;
+  return ((int64_t)iz * m.gy + iy) * m.gx + ix;
+}
+
+// Hash slot of a block via the render index, -1 if absent.
+__device__ inline int block_slot(const MapView& m, int bx, int by, int bz, const Trace& tr) {
+  const int64_t i = grid_index(m, bx, by, bz);
+  const int s = i < 0 ? -1 : m.grid_slot[i];
+  if (tr.slots && s >= 0) tr.slots[s] = 1;
+  return s;
+}
+
+struct CellPos {
+  int bl[3], lo[3];
+  float a[3];
 };
 
-__device__ inline int lookup_block(const MapView& m, int bx, int by, int bz, const Trace& tr) {
-  if (!key_in_range(bx, by, bz)) return -1;
-  const uint64_t key = pack_key(bx, by, bz);
-  if (tr.slots) {   // traffic accounting: mark every probed bucket
-    uint32_t s = hash_key(key) & m.mask;
-    for (uint32_t i = 0; i <= m.mask; ++i) {
-      tr.slots[s] = 1;
-      uint64_t k = m.entries[s].key;
-      if (k == key) return (int)s;
-      if (k == kEmptyKey) return -1;
-      s = (s + 1) & m.mask;
-    }
-    return -1;
+__device__ inline void locate(const MapView& m, const double x[3], CellPos& c) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vx = x[k] * m.inv_voxel;
+    const double fl = floor(vx);
+    const int ix = (int)fl;
+    c.a[k] = (float)(vx - fl);
+    c.bl[k] = ix >> 3;
+    c.lo[k] = ix & 7;
   }
-  return find_slot(m.entries, m.mask, key);
+}
+
+// arccos by the polynomial of Abramowitz & Stegun 4.4.46 (|error| <= 2e-8 on [0, 1]),
+// extended to [-1, 0) by acos(x) = pi - acos(-x).
+__device__ inline float acos_as(float x) {
+  const float ax = fminf(fabsf(x), 1.0f);
+  float p = -0.0012624911f;
+  p = fmaf(p, ax, 0.0066700901f);
+  p = fmaf(p, ax, -0.0170881256f);
+  p = fmaf(p, ax, 0.0308918810f);
+  p = fmaf(p, ax, -0.0501743046f);
+  p = fmaf(p, ax, 0.0889789874f);
+  p = fmaf(p, ax, -0.2145988016f);
+  p = fmaf(p, ax, 1.5707963050f);
+  const float r = sqrtf(1.0f - ax) * p;
+  return x < 0.f ? 3.14159265358979f - r : r;
+}
+
+// Direction weight of Sec. 3 (clamped-linear reading), from the cosine <n, v^D>.
+__device__ inline float w_dir_fast(float c, float theta, float inv_band) {
+  return fminf(1.0f, fmaxf(0.0f, (theta - acos_as(c)) * inv_band));
 }
 
 struct Eval {
@@ -75,94 +127,81 @@ struct Eval {
   bool color_ok;
 };
 
-// Evaluates the combined SDF at world point x for unit ray direction r.
-// Returns false if the block of the base voxel is absent (the sample is undefined and so
-// is every sample in that block); `bc` caches the base block's hash slot.
 template <bool FULL>
-__device__ bool eval_at(const MapView& m, const double x[3], const float r[3], BlockCache& bc,
-                        Eval& e, const Trace& tr) {
+__device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, const float r[3],
+                          float inv_band, Eval& e, const Trace& tr) {
   e.defined = false;
   e.fallback = false;
   e.f = 0.f;
-  int ix[3], bl[3], lo[3];
-  float a[3];
-  for (int k = 0; k < 3; ++k) {
-    double vx = x[k] * m.inv_voxel;
-    double fl = floor(vx);
-    ix[k] = (int)fl;
-    a[k] = (float)(vx - fl);
-    bl[k] = ix[k] >> 3;
-    lo[k] = ix[k] & 7;
+  if (FULL) {
+    e.n[0] = e.n[1] = e.n[2] = 0.f;
+    e.rgb[0] = e.rgb[1] = e.rgb[2] = 0.f;
+    e.color_ok = false;
   }
-  if (bl[0] != bc.bx || bl[1] != bc.by || bl[2] != bc.bz) {
-    bc.bx = bl[0];
-    bc.by = bl[1];
-    bc.bz = bl[2];
-    bc.slot = lookup_block(m, bl[0], bl[1], bl[2], tr);
-  }
-  if (bc.slot < 0) return false;
+  if (base_slot < 0) return;
+  const int lx = cp.lo[0], ly = cp.lo[1], lz = cp.lo[2];
   // hash slots of the blocks the eight corners fall in, indexed by block offset bits
-  const int need = (lo[0] == 7 ? 1 : 0) | (lo[1] == 7 ? 2 : 0) | (lo[2] == 7 ? 4 : 0);
+  const int need = (lx == 7 ? 1 : 0) | (ly == 7 ? 2 : 0) | (lz == 7 ? 4 : 0);
   int nb[8];
-  nb[0] = bc.slot;
+  nb[0] = base_slot;
 #pragma unroll
   for (int o = 1; o < 8; ++o) {
     nb[o] = -1;
     if ((o & need) == o)
-      nb[o] = lookup_block(m, bl[0] + (o & 1), bl[1] + ((o >> 1) & 1), bl[2] + ((o >> 2) & 1), tr);
+      nb[o] = block_slot(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1), cp.bl[2] + ((o >> 2) & 1), tr);
   }
-  int loc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    int cx = lo[0] + (c & 1), cy = lo[1] + ((c >> 1) & 1), cz = lo[2] + ((c >> 2) & 1);
-    loc[c] = (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
-  }
-  const HashEntry& base = m.entries[bc.slot];
+  const float ax = cp.a[0], ay = cp.a[1], az = cp.a[2];
+  const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
+  const float tw[8] = {bx * by * bz, ax * by * bz, bx * ay * bz, ax * ay * bz,
+                       bx * by * az, ax * by * az, bx * ay * az, ax * ay * az};
   const float mr[3] = {-r[0], -r[1], -r[2]};
-  float phi[6], W[6], om[6], nn[6][3];
-  bool def[6], gok[6];
-  int brick_of[6][8];
+  const int32_t* base_br = m.entries[base_slot].brick;
+  float so = 0.f, sop = 0.f;   // gradient combination weights
+  float fo = 0.f, fop = 0.f;   // fallback weights
   bool any = false;
-  float sum_o = 0.f, sum_op = 0.f;
-#pragma unroll
+  // FULL accumulators: normals and colours for both branches
+  float ng0 = 0.f, ng1 = 0.f, ng2 = 0.f, nf0 = 0.f, nf1 = 0.f, nf2 = 0.f;
+  float cg0 = 0.f, cg1 = 0.f, cg2 = 0.f, cgo = 0.f;     // colour weights of the colour blend
+  float cgg0 = 0.f, cgg1 = 0.f, cgg2 = 0.f, cggo = 0.f; // geometric weights, gradient branch
+  float cgf0 = 0.f, cgf1 = 0.f, cgf2 = 0.f, cgfo = 0.f; // geometric weights, fallback branch
+#pragma unroll 1
   for (int d = 0; d < 6; ++d) {
-    def[d] = false;
-    gok[d] = false;
-    om[d] = 0.f;
-    int b0 = base.brick[d];
+    const int b0 = base_br[d];
     if (b0 < 0) continue;
-    float sv[8], wv[8];
+    int br[8];
     bool ok = true;
-    for (int c = 0; c < 8 && ok; ++c) {
-      int o = c & need;
-      int br = b0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int o = c & need;
+      br[c] = b0;
       if (o) {
-        int s = nb[o];
-        br = s < 0 ? -1 : m.entries[s].brick[d];
+        const int s = nb[o];
+        br[c] = s < 0 ? -1 : m.entries[s].brick[d];
+        ok = ok && br[c] >= 0;
       }
-      if (br < 0) {
-        ok = false;
-        break;
-      }
-      brick_of[d][c] = br;
-      if (tr.bricks) tr.bricks[br] = 1;
-      float2 v = m.sw[(size_t)br * kVox + loc[c]];
-      sv[c] = v.x;
-      wv[c] = v.y;
-      if (!(v.y > 0.f)) ok = false;
     }
     if (!ok) continue;
-    def[d] = true;
+    float sv[8], wv[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
+                      64 * ((lz + ((c >> 2) & 1)) & 7);
+      const float2 v = m.sw[(size_t)br[c] * kVox + loc];
+      sv[c] = v.x;
+      wv[c] = v.y;
+      if (tr.bricks) tr.bricks[br[c]] = 1;
+    }
+    bool wok = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) wok = wok && (wv[c] > 0.f);
+    if (!wok) continue;
     any = true;
-    const float ax = a[0], ay = a[1], az = a[2];
-    const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
-    // trilinear weights of corners c = (cx, cy, cz)
-    const float t0 = bx * by * bz, t1 = ax * by * bz, t2 = bx * ay * bz, t3 = ax * ay * bz;
-    const float t4 = bx * by * az, t5 = ax * by * az, t6 = bx * ay * az, t7 = ax * ay * az;
-    phi[d] = t0 * sv[0] + t1 * sv[1] + t2 * sv[2] + t3 * sv[3] + t4 * sv[4] + t5 * sv[5] +
-             t6 * sv[6] + t7 * sv[7];
-    W[d] = t0 * wv[0] + t1 * wv[1] + t2 * wv[2] + t3 * wv[3] + t4 * wv[4] + t5 * wv[5] +
-           t6 * wv[6] + t7 * wv[7];
+    float phi = 0.f, W = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      phi = fmaf(tw[c], sv[c], phi);
+      W = fmaf(tw[c], wv[c], W);
+    }
     // analytic gradient of the interpolant (per voxel)
     const float gx = (sv[1] - sv[0]) * by * bz + (sv[3] - sv[2]) * ay * bz +
                      (sv[5] - sv[4]) * by * az + (sv[7] - sv[6]) * ay * az;
@@ -171,117 +210,118 @@ __device__ bool eval_at(const MapView& m, const double x[3], const float r[3], B
     const float gz = (sv[4] - sv[0]) * bx * by + (sv[5] - sv[1]) * ax * by +
                      (sv[6] - sv[2]) * bx * ay + (sv[7] - sv[3]) * ax * ay;
     const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
+    float om = 0.f, wdc = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
     if (gl >= 1e-6f) {
-      gok[d] = true;
       const float il = 1.f / gl;
-      nn[d][0] = gx * il;
-      nn[d][1] = gy * il;
-      nn[d][2] = gz * il;
-      const float wd = w_dir_cos(axis_dot(nn[d][0], nn[d][1], nn[d][2], d), m.theta);
-      const float cs = nn[d][0] * mr[0] + nn[d][1] * mr[1] + nn[d][2] * mr[2];
-      om[d] = wd * fmaxf(0.f, cs) * W[d];
+      n0 = gx * il;
+      n1 = gy * il;
+      n2 = gz * il;
+      const float wd = w_dir_fast(axis_dot(n0, n1, n2, d), m.theta, inv_band);
+      wdc = wd * fmaxf(0.f, n0 * mr[0] + n1 * mr[1] + n2 * mr[2]);
+      om = wdc * W;
     }
-    sum_o += om[d];
-    sum_op += om[d] * phi[d];
+    so += om;
+    sop += om * phi;
+    const float fb = W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d));
+    fo += fb;
+    fop += fb * phi;
+    if (FULL) {
+      ng0 += om * n0;
+      ng1 += om * n1;
+      ng2 += om * n2;
+      const float sfb = (d & 1) ? -fb : fb;
+      nf0 += d < 2 ? sfb : 0.f;
+      nf1 += (d >> 1) == 1 ? sfb : 0.f;
+      nf2 += d >= 4 ? sfb : 0.f;
+      if (m.with_color) {
+        float wsum = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+        bool cok = true;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
+                          64 * ((lz + ((c >> 2) & 1)) & 7);
+          const size_t vi = (size_t)br[c] * kVox + loc;
+          if (tr.color) tr.color[br[c]] = 1;
+          const float w = m.wc[vi];
+          const uint32_t code = m.rgb[vi];
+          cok = cok && (w > 0.f);
+          wsum = fmaf(tw[c], w, wsum);
+          c0 = fmaf(tw[c], (float)(code & 0xFFu), c0);
+          c1 = fmaf(tw[c], (float)((code >> 8) & 0xFFu), c1);
+          c2 = fmaf(tw[c], (float)((code >> 16) & 0xFFu), c2);
+        }
+        if (cok) {
+          const float oc = wdc * wsum;   // w_dir(n^D) max(0, <n^D, -r>) W_c^D
+          cg0 += oc * c0;
+          cg1 += oc * c1;
+          cg2 += oc * c2;
+          cgg0 += om * c0;
+          cgg1 += om * c1;
+          cgg2 += om * c2;
+          cgf0 += fb * c0;
+          cgf1 += fb * c1;
+          cgf2 += fb * c2;
+          cgo += oc;
+          cggo += om;
+          cgfo += fb;
+        }
+      }
+    }
   }
-  if (!any) return true;
-  if (sum_o > 0.f) {
+  if (!any) return;
+  if (so > 0.f) {
     e.defined = true;
-    e.f = sum_op / sum_o;
+    e.f = sop / so;
   } else {
     // no usable gradient weight in any direction: eq. combine_tsdf_weight
     e.fallback = true;
-    sum_o = 0.f;
-    sum_op = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      om[d] = 0.f;
-      if (!def[d]) continue;
-      om[d] = W[d] * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d));
-      sum_o += om[d];
-      sum_op += om[d] * phi[d];
-    }
-    if (sum_o > 0.f) {
+    if (fo > 0.f) {
       e.defined = true;
-      e.f = sum_op / sum_o;
+      e.f = fop / fo;
     }
   }
   if (FULL) {
-    e.n[0] = e.n[1] = e.n[2] = 0.f;
-    e.color_ok = false;
-    e.rgb[0] = e.rgb[1] = e.rgb[2] = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if (!def[d] || !(om[d] > 0.f)) continue;
-      for (int k = 0; k < 3; ++k) {
-        float comp = e.fallback ? ((k == (d >> 1)) ? ((d & 1) ? -1.f : 1.f) : 0.f) : nn[d][k];
-        e.n[k] += om[d] * comp;
-      }
-    }
+    e.n[0] = e.fallback ? nf0 : ng0;
+    e.n[1] = e.fallback ? nf1 : ng1;
+    e.n[2] = e.fallback ? nf2 : ng2;
     if (m.with_color) {
-      // colour: per direction trilinear colour over corners with w_c > 0, blended with
-      // w_dir(n^D) max(0, <n^D, -r>) W_c^D; if those sum to zero, with the geometric weights
-      float cw[6], col[6][3];
-      bool cok[6];
-      const float ax = a[0], ay = a[1], az = a[2];
-      const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
-      const float tw[8] = {bx * by * bz, ax * by * bz, bx * ay * bz, ax * ay * bz,
-                           bx * by * az, ax * by * az, bx * ay * az, ax * ay * az};
-      for (int d = 0; d < 6; ++d) {
-        cok[d] = false;
-        if (!def[d]) continue;
-        float wsum = 0.f, c3[3] = {0.f, 0.f, 0.f};
-        bool ok = true;
-        for (int c = 0; c < 8; ++c) {
-          size_t vi = (size_t)brick_of[d][c] * kVox + loc[c];
-          if (tr.color) tr.color[brick_of[d][c]] = 1;
-          float w = m.wc[vi];
-          if (!(w > 0.f)) {
-            ok = false;
-            break;
-          }
-          uint32_t code = m.rgb[vi];
-          wsum += tw[c] * w;
-          for (int ch = 0; ch < 3; ++ch) c3[ch] += tw[c] * (float)((code >> (8 * ch)) & 0xFFu);
-        }
-        if (!ok) continue;
-        cok[d] = true;
-        cw[d] = wsum;
-        for (int ch = 0; ch < 3; ++ch) col[d][ch] = c3[ch];
+      float s0 = cg0, s1 = cg1, s2 = cg2, sw = cgo;
+      if (e.fallback) {
+        s0 = cgf0; s1 = cgf1; s2 = cgf2; sw = cgfo;
+      } else if (!(cgo > 0.f)) {
+        s0 = cgg0; s1 = cgg1; s2 = cgg2; sw = cggo;
       }
-      float so = 0.f, sc[3] = {0.f, 0.f, 0.f};
-      if (!e.fallback)
-        for (int d = 0; d < 6; ++d) {
-          if (!cok[d] || !gok[d]) continue;
-          float oc = w_dir_cos(axis_dot(nn[d][0], nn[d][1], nn[d][2], d), m.theta) *
-                     fmaxf(0.f, nn[d][0] * mr[0] + nn[d][1] * mr[1] + nn[d][2] * mr[2]) * cw[d];
-          so += oc;
-          for (int ch = 0; ch < 3; ++ch) sc[ch] += oc * col[d][ch];
-        }
-      if (!(so > 0.f)) {
-        so = 0.f;
-        sc[0] = sc[1] = sc[2] = 0.f;
-        for (int d = 0; d < 6; ++d) {
-          if (!cok[d]) continue;
-          so += om[d];
-          for (int ch = 0; ch < 3; ++ch) sc[ch] += om[d] * col[d][ch];
-        }
-      }
-      if (so > 0.f) {
+      if (sw > 0.f) {
         e.color_ok = true;
-        for (int ch = 0; ch < 3; ++ch) e.rgb[ch] = sc[ch] / so;
+        const float isw = 1.f / sw;
+        e.rgb[0] = s0 * isw;
+        e.rgb[1] = s1 * isw;
+        e.rgb[2] = s2 * isw;
       }
     }
   }
-  return true;
+}
+
+// Evaluates the combined SDF at an arbitrary point (refinement, outputs).
+template <bool FULL>
+__device__ void eval_at(const MapView& m, const double x[3], const float r[3], float inv_band,
+                        Eval& e, const Trace& tr) {
+  CellPos cp;
+  locate(m, x, cp);
+  eval_cell<FULL>(m, cp, block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), r, inv_band, e, tr);
 }
 
 __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
-  const int u = blockIdx.x * 8 + (threadIdx.x & 7);
-  const int v = blockIdx.y * 8 + (threadIdx.x >> 3);
+  // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
+  const int per = (a.tiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= a.tiles) return;
+  const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
+  const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
   if (u >= a.W || v >= a.H) return;
   const size_t i = (size_t)v * a.W + u;
   const size_t HW = (size_t)a.W * a.H;
+  const float inv_band = 1.0f / (2.0f * m.theta - 1.5707963267948966f);
   double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
   const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
   const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
@@ -291,69 +331,143 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
   const double* o = a.t;
   const double t0 = a.z_near / rc[2], tmax = a.z_far / rc[2];
   const double step = m.step;
-  BlockCache bc{0x7fffffff, 0, 0, -1};
   const Trace tr{a.trace_bricks, a.trace_color, a.trace_slots};
-  bool prev_def = false, hit = false;
+  int n_eval = 0, n_skip = 0, n_absent = 0, n_refine = 0;
+  const double ir[3] = {r[0] != 0.0 ? 1.0 / r[0] : 0.0, r[1] != 0.0 ? 1.0 / r[1] : 0.0,
+                        r[2] != 0.0 ? 1.0 / r[2] : 0.0};
+  const double inv_step = 1.0 / step;
+  const double bw = kB * m.voxel;          // block edge [m]
+  int cb[3] = {0x7fffffff, 0, 0};   // block of the previous lattice sample
+  int cslot = -1;
+  uint8_t cmask = 0;
+  bool prev_def = false, hit = false, refining = false;
   float prev_f = 0.f, fa = 0.f, fb = 0.f;
   double ta = 0.0, tb = 0.0;
-  for (long long k = 0;;) {
-    const double tk = t0 + (double)k * step;
-    if (tk > tmax) break;
-    const double x[3] = {o[0] + tk * r[0], o[1] + tk * r[1], o[2] + tk * r[2]};
-    Eval e;
-    if (!eval_at<false>(m, x, rf, bc, e, tr)) {
-      // every lattice point before the exit of this absent block is undefined
-      double texit = 1e300;
-      for (int ax = 0; ax < 3; ++ax) {
-        int b = ax == 0 ? bc.bx : (ax == 1 ? bc.by : bc.bz);
-        if (r[ax] > 0.0) texit = fmin(texit, ((double)(b + 1) * kB * m.voxel - o[ax]) / r[ax]);
-        else if (r[ax] < 0.0) texit = fmin(texit, ((double)b * kB * m.voxel - o[ax]) / r[ax]);
+  long long k = 0, next_k = 0;
+  int it = 0, side = 0;
+  // One loop serves the march and the refinement so that the evaluation is inlined once.
+  for (;;) {
+    double te;            // parameter of the point to evaluate
+    bool lattice = false; // a lattice point of a sub-block that may hold a crossing
+    int eslot;
+    if (!refining) {
+      const double tk = t0 + (double)k * step;
+      if (tk > tmax) break;
+      const double x[3] = {o[0] + tk * r[0], o[1] + tk * r[1], o[2] + tk * r[2]};
+      CellPos cp;
+      locate(m, x, cp);
+      if (cp.bl[0] != cb[0] || cp.bl[1] != cb[1] || cp.bl[2] != cb[2]) {
+        cb[0] = cp.bl[0];
+        cb[1] = cp.bl[1];
+        cb[2] = cp.bl[2];
+        const int64_t gi = grid_index(m, cb[0], cb[1], cb[2]);
+        cslot = gi < 0 ? -1 : m.grid_slot[gi];
+        cmask = gi < 0 ? 0 : m.grid_mask[gi];
+        if (tr.slots && cslot >= 0) tr.slots[cslot] = 1;
       }
-      const double jn = ceil((texit - 1e-6 - t0) / step);
-      long long j0 = jn > 9e15 ? (long long)9e15 : (long long)jn;
-      k = j0 > k + 1 ? j0 : k + 1;
-      prev_def = false;
-      continue;
+      if (cslot < 0) {
+        // absent block: leave the largest empty cell of the hierarchy that contains it
+        const int g[3] = {cb[0] - m.gx0, cb[1] - m.gy0, cb[2] - m.gz0};
+        const bool inside = g[0] >= 0 && g[1] >= 0 && g[2] >= 0 && g[0] < m.gx && g[1] < m.gy &&
+                            g[2] < m.gz;
+        int sh = 4;   // log2 of the cell edge in blocks
+        if (inside) {
+          const int m1x = (m.gx + 3) >> 2, m1y = (m.gy + 3) >> 2;
+          const int m2x = (m.gx + 15) >> 4, m2y = (m.gy + 15) >> 4;
+          if (m.macro2[((int64_t)(g[2] >> 4) * m2y + (g[1] >> 4)) * m2x + (g[0] >> 4)])
+            sh = m.macro1[((int64_t)(g[2] >> 2) * m1y + (g[1] >> 2)) * m1x + (g[0] >> 2)] ? 0 : 2;
+        }
+        double lo[3], hi[3];
+        const int gg[3] = {m.gx0, m.gy0, m.gz0};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int c0 = gg[ax] + ((g[ax] >> sh) << sh);
+          lo[ax] = (double)c0 * bw;
+          hi[ax] = (double)(c0 + (1 << sh)) * bw;
+        }
+        const double texit = box_exit(o, r, ir, lo, hi);
+        const double jn = ceil((texit - 1e-6 - t0) * inv_step);
+        const long long j0 = jn > 9e15 ? (long long)9e15 : (long long)jn;
+        ++n_absent;
+        prev_def = false;
+        k = j0 > k + 1 ? j0 : k + 1;
+        continue;
+      }
+      const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
+      if ((cmask >> sub) & 1) {
+        // positive sub-block: evaluate only its last lattice point
+        double lo[3], hi[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int v0 = cb[ax] * kB + ((sub >> ax) & 1) * 4;
+          lo[ax] = (double)v0 * m.voxel;
+          hi[ax] = (double)(v0 + 4) * m.voxel;
+        }
+        const double texit = box_exit(o, r, ir, lo, hi);
+        const double jn = ceil((texit - 1e-6 - t0) * inv_step);
+        const long long j0 = jn > 9e15 ? (long long)9e15 : (long long)jn;
+        ++n_skip;
+        const long long last = j0 - 1 > k ? j0 - 1 : k;
+        te = t0 + (double)last * step;
+        if (te > tmax) break;
+        next_k = last + 1;
+      } else {
+        te = tk;
+        lattice = true;
+        next_k = k + 1;
+        ++n_eval;
+      }
+      eslot = cslot;
+    } else {
+      if (it >= 24 || !((tb - ta) > 1e-6)) break;
+      te = (it & 3) == 3 ? 0.5 * (ta + tb)
+                         : ta + (tb - ta) * ((double)fa / ((double)fa - (double)fb));
+      if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
+      eslot = -2;
+      ++n_refine;
     }
-    if (k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
-      hit = true;
-      ta = t0 + (double)(k - 1) * step;
-      tb = tk;
-      fa = prev_f;
-      fb = e.f;
-      break;
-    }
-    prev_def = e.defined;
-    prev_f = e.f;
-    ++k;
-  }
-  float out_depth = 0.f, out_v[3] = {0.f, 0.f, 0.f}, out_n[3] = {0.f, 0.f, 0.f};
-  uint32_t out_c = 0;
-  if (hit) {
-    int side = 0;
-    for (int it = 0; it < 40 && (tb - ta) > 1e-7; ++it) {
-      double c = (it & 3) == 3 ? 0.5 * (ta + tb)
-                               : ta + (tb - ta) * ((double)fa / ((double)fa - (double)fb));
-      if (!(c > ta && c < tb)) c = 0.5 * (ta + tb);
-      const double x[3] = {o[0] + c * r[0], o[1] + c * r[1], o[2] + c * r[2]};
-      Eval e;
-      bool present = eval_at<false>(m, x, rf, bc, e, tr);
-      if (!present || !e.defined || e.f > 0.f) {
-        ta = c;
-        if (present && e.defined) fa = e.f;
+    const double x[3] = {o[0] + te * r[0], o[1] + te * r[1], o[2] + te * r[2]};
+    CellPos cp;
+    locate(m, x, cp);
+    if (eslot == -2 || cp.bl[0] != cb[0] || cp.bl[1] != cb[1] || cp.bl[2] != cb[2])
+      eslot = block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr);
+    Eval e;
+    eval_cell<false>(m, cp, eslot, rf, inv_band, e, tr);
+    if (refining) {
+      ++it;
+      if (!e.defined || e.f > 0.f) {
+        ta = te;
+        if (e.defined) fa = e.f;
         if (side == 1) fb *= 0.5f;
         side = 1;
       } else {
-        tb = c;
+        tb = te;
         fb = e.f;
         if (side == -1) fa *= 0.5f;
         side = -1;
       }
+      continue;
     }
+    if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
+      hit = true;
+      refining = true;
+      ta = t0 + (double)(k - 1) * step;
+      tb = te;
+      fa = prev_f;
+      fb = e.f;
+      continue;
+    }
+    prev_def = e.defined;
+    prev_f = e.f;
+    k = next_k;
+  }
+  float out_depth = 0.f, out_v[3] = {0.f, 0.f, 0.f}, out_n[3] = {0.f, 0.f, 0.f};
+  uint32_t out_c = 0;
+  if (hit) {
     const double ts = 0.5 * (ta + tb);
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
     Eval e;
-    eval_at<true>(m, x, rf, bc, e, tr);
+    eval_at<true>(m, x, rf, inv_band, e, tr);
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
@@ -382,6 +496,12 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
   }
   if (a.rgba) reinterpret_cast<uint32_t*>(a.rgba)[i] = out_c;
   if (a.mask) a.mask[i] = hit ? 1 : 0;
+  if (a.trace_counts) {
+    a.trace_counts[4 * i + 0] = n_eval;
+    a.trace_counts[4 * i + 1] = n_skip;
+    a.trace_counts[4 * i + 2] = n_absent;
+    a.trace_counts[4 * i + 3] = n_refine;
+  }
 }
 
 }  // namespace
@@ -397,6 +517,8 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
   RenderArgs a;
   a.W = intr->width;
   a.H = intr->height;
+  a.tiles_x = (a.W + 7) / 8;
+  a.tiles = a.tiles_x * ((a.H + 7) / 8);
   a.fx = intr->fx;
   a.fy = intr->fy;
   a.cx = intr->cx;
@@ -415,8 +537,9 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
   a.trace_bricks = out->trace_bricks;
   a.trace_color = out->trace_color;
   a.trace_slots = out->trace_slots;
-  dim3 grd((a.W + 7) / 8, (a.H + 7) / 8);
-  hipLaunchKernelGGL(render_k, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
+  a.trace_counts = out->trace_counts;
+  const int per = (a.tiles + 7) / 8;
+  hipLaunchKernelGGL(render_k, dim3(per * 8), dim3(64), 0, (hipStream_t)stream, make_view(m), a);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

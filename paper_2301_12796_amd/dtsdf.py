@@ -62,7 +62,8 @@ class _RenderOut(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
                 ("normal", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
                 ("mask", ctypes.c_void_p), ("trace_bricks", ctypes.c_void_p),
-                ("trace_color", ctypes.c_void_p), ("trace_slots", ctypes.c_void_p)]
+                ("trace_color", ctypes.c_void_p), ("trace_slots", ctypes.c_void_p),
+                ("trace_counts", ctypes.c_void_p)]
 
 
 class _Blob(ctypes.Structure):
@@ -257,7 +258,8 @@ class Map:
                         _dev_ptr(out.get("mask"), torch.uint8, H * W),
                         _dev_ptr(out.get("trace_bricks"), torch.uint8, cap),
                         _dev_ptr(out.get("trace_color"), torch.uint8, cap),
-                        _dev_ptr(out.get("trace_slots"), torch.uint8, nb))
+                        _dev_ptr(out.get("trace_slots"), torch.uint8, nb),
+                        _dev_ptr(out.get("trace_counts"), torch.int32, 4 * H * W))
         _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
                                  ctypes.byref(ro), _stream(stream)), "dtsdf_render")
         return out
