@@ -163,6 +163,21 @@ dtsdf_status dtsdf_render(const dtsdf_map* map, const dtsdf_intrinsics* intr,
                           const double T_world_cam[16], float z_near, float z_far,
                           const dtsdf_render_out* out, void* stream);
 
+/* One view of a batched render. */
+typedef struct {
+  dtsdf_intrinsics intr;
+  double T_world_cam[16];
+  float z_near, z_far;
+  dtsdf_render_out out;
+} dtsdf_render_req;
+
+/* Render n views (any sizes, any poses) of one map in a single persistent launch that hands
+ * (view, 8x8 tile) work items to waves as they free up.  Every pixel is computed exactly as
+ * by dtsdf_render, so each view is bitwise identical to rendering it alone.  Serves many
+ * sensors at once (continuous batching of render requests).  Enqueues on `stream`. */
+dtsdf_status dtsdf_render_batch(const dtsdf_map* map, int32_t n, const dtsdf_render_req* reqs,
+                                void* stream);
+
 /* Copy the map to host arrays.  With blob->keys == NULL only blob->n_bricks is set.
  * Otherwise blob->n_bricks must be at least the number of bricks (DTSDF_E_INVAL if not);
  * it is set to the number written.  Synchronises. */
@@ -201,6 +216,8 @@ typedef struct {
   int32_t weight;          /* dtsdf_icp_weight; DEPTH is eq. ICP_weight with z_min */
   float z_min;
   int32_t min_inliers_per_dim; /* fewer than this * dim inliers -> DTSDF_E_DEGENERATE (64) */
+  int32_t compensated;     /* 1: float32 sums with Neumaier compensation per thread and
+                              TwoSum merges across the reduction tree */
 } dtsdf_icp_params;
 
 typedef struct {
@@ -210,6 +227,8 @@ typedef struct {
   double error;        /* sum w r^2 */
   int64_t inliers;
   double step_norm;    /* ||xi||_2 */
+  int32_t status;      /* DTSDF_OK or DTSDF_E_DEGENERATE */
+  int32_t reserved;
 } dtsdf_icp_result;
 
 /* One Gauss-Newton step of point-to-plane ICP (Sec. 5, eq. geometric_ICP .. deltaT_update;
@@ -225,6 +244,26 @@ typedef struct {
 dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
                       const dtsdf_icp_params* params, double T_model_live[16],
                       dtsdf_icp_result* result, void* stream);
+
+/* One registration request of a batch; pose, flag and result live in device memory so that
+ * a serving loop can run many iterations without host round-trips. */
+typedef struct {
+  dtsdf_image live, model;
+  int32_t dim;                 /* 6 or 7 */
+  dtsdf_icp_params params;
+  double* pose;                /* device double[16], T_model_live, updated in place */
+  int32_t* active;             /* device flag or NULL: the step runs only while *active != 0,
+                                  and clears it when ||xi|| < min_step or the system is
+                                  degenerate (then the pose is left unchanged) */
+  double min_step;
+  dtsdf_icp_result* result;    /* device or NULL */
+} dtsdf_icp_req;
+
+/* One Gauss-Newton step for each of n requests (any sizes, SE(3) or Sim(3)) in two launches
+ * (reduction over (request, chunk) workgroups, then one solve workgroup per request).  The
+ * per-request reduction order is the same as icp_step's, so every request's pose is bitwise
+ * identical to stepping it alone.  Enqueues on `stream`; does not synchronise. */
+dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream);
 
 const char* dtsdf_status_string(dtsdf_status status);
 

@@ -53,6 +53,8 @@ struct Params {
   int32_t dense_hi[3];
   int32_t with_color;
   int32_t single_direction;  // control: one direction with w_dir = 1 (a regular TSDF)
+  int32_t sdf_fmt;           // 0 float, 1 float16 code, 2 int16 code scaled by the truncation
+  int32_t w_fmt;             // 0 float, 1 uint8 code of 4 w
 };
 
 struct Key {
@@ -203,6 +205,38 @@ Frame make_frame(const float* depth, int W, int H, double fx, double fy, double 
 void running_average(double& val, double& w, double x, double wx, double w_max) {
   val = (val * w + x * wx) / (w + wx);
   w = std::min(w + wx, w_max);
+}
+
+// Round half to even to a multiple of `quantum`; `tie` is set when x lies within `tol`
+// quanta of a rounding boundary (a float32 implementation, whose running averages carry a
+// few float32 ulps of error, may round the other way there).
+double round_to(double x, double quantum, double tol, bool* tie) {
+  const double y = x / quantum;
+  if (std::fabs(y - std::floor(y) - 0.5) < tol) *tie = true;
+  return std::nearbyint(y) * quantum;
+}
+
+// Stored form of a distance: float16 keeps 10 fraction bits in the binade of x (spacing
+// 2^-24 below the smallest normal); int16 keeps q / 32767 with q = round(32767 d).
+double store_sdf(const Params& p, double d, bool* tie) {
+  if (p.sdf_fmt == 1) {
+    const double ax = std::fabs(d);
+    if (ax == 0.0) return d;
+    int e;
+    std::frexp(ax, &e);
+    return round_to(d, std::ldexp(1.0, std::max(e - 11, -24)), 1e-3, tie);
+  }
+  if (p.sdf_fmt == 2) {
+    const double q = std::min(32767.0, std::max(-32767.0, round_to(d * 32767.0, 1.0, 5e-2, tie)));
+    return q / 32767.0;
+  }
+  return d;
+}
+
+// Stored form of a weight: the uint8 code q = round(4 w) (capped at 255 by w_max = 63.75).
+double store_w(const Params& p, double w, bool* tie) {
+  if (p.w_fmt == 1) return std::min(255.0, round_to(4.0 * w, 1.0, 1e-3, tie)) / 4.0;
+  return w;
 }
 
 }  // namespace
@@ -396,6 +430,8 @@ void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H
           }
         if (ok && p.w_carve > 0.0) {
           running_average(B.sdf[l], B.w[l], 1.0, p.w_carve, p.w_max);
+          B.sdf[l] = store_sdf(p, B.sdf[l], &bl);
+          B.w[l] = store_w(p, B.w[l], &bl);
           n_carve++;
         }
         if (bl) B.border[l] = 1;
@@ -427,6 +463,8 @@ void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H
         continue;
       }
       running_average(B.sdf[l], B.w[l], dd, wd, p.w_max);
+      B.sdf[l] = store_sdf(p, B.sdf[l], &bl);
+      B.w[l] = store_w(p, B.w[l], &bl);
       n_upd++;
       if (p.with_color && rgb) {
         double dist = std::sqrt((pw[0] - x[0]) * (pw[0] - x[0]) + (pw[1] - x[1]) * (pw[1] - x[1]) +
@@ -443,7 +481,7 @@ void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H
             double q = std::nearbyint(val);
             B.rgb[l][c] = (uint8_t)std::min(255.0, std::max(0.0, q));
           }
-          B.wc[l] = std::min(B.wc[l] + wc, p.w_max);
+          B.wc[l] = store_w(p, std::min(B.wc[l] + wc, p.w_max), &bl);
         }
       }
       if (bl) B.border[l] = 1;

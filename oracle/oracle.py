@@ -65,7 +65,8 @@ class _Params(ctypes.Structure):
                 ("w_max", ctypes.c_double), ("w_min", ctypes.c_double),
                 ("step", ctypes.c_double), ("dense", ctypes.c_int32),
                 ("dense_lo", ctypes.c_int32 * 3), ("dense_hi", ctypes.c_int32 * 3),
-                ("with_color", ctypes.c_int32), ("single_direction", ctypes.c_int32)]
+                ("with_color", ctypes.c_int32), ("single_direction", ctypes.c_int32),
+                ("sdf_fmt", ctypes.c_int32), ("w_fmt", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -134,6 +135,8 @@ class MapParams:
     dense_hi: Optional[Sequence[int]] = None
     with_color: bool = True
     single_direction: bool = False
+    sdf_fmt: int = 0            # 0 float, 1 float16, 2 int16 scaled by the truncation
+    w_fmt: int = 0              # 0 float, 1 uint8 code of 4 w
 
     def c_struct(self) -> _Params:
         p = _Params()
@@ -150,6 +153,8 @@ class MapParams:
             p.dense_hi[k] = int(self.dense_hi[k]) if self.dense_hi is not None else 0
         p.with_color = int(self.with_color)
         p.single_direction = int(self.single_direction)
+        p.sdf_fmt = int(self.sdf_fmt)
+        p.w_fmt = int(self.w_fmt)
         return p
 
 

@@ -10,10 +10,15 @@
 //   req      uint32[buckets]        per-entry bit mask of directions requested by the frame
 //                                   being integrated (cleared when bricks are assigned)
 //   bkey     int4[capacity]         (bx, by, bz, D) of every pool brick
-//   sw       float2[capacity*512]   (sdf, w) of every voxel, brick-major, voxel l at local
-//                                   (l % 8, l / 8 % 8, l / 64); the march reads only these
-//   rgb      uint32[capacity*512]   r | g << 8 | b << 16 colour code per voxel
-//   wc       float[capacity*512]    colour weight per voxel
+//   geo      [capacity*512]         distance and weight of every voxel, brick-major, voxel l at
+//                                   local (l % 8, l / 8 % 8, l / 64); the march reads only
+//                                   these.  Plain format: float2 (sdf, w), 8 bytes.  Packed
+//                                   formats: one 32-bit word, sdf code in bits 0-15 (float16,
+//                                   or int16 q with sdf = q / 32767) and the weight code
+//                                   q = round(4 w) in bits 16-23, 4 bytes.
+//   rgb      uint32[capacity*512]   r | g << 8 | b << 16 colour code per voxel; in the packed
+//                                   formats the colour-weight code sits in bits 24-31
+//   wc       float[capacity*512]    colour weight per voxel (plain format only)
 //   counters int32[16]              [0] bricks handed out (may overshoot the capacity while a
 //                                   frame allocates), [1] dropped requests, [2] hash overflow,
 //                                   [3] occupied hash entries, [4..9] bounding box of the
@@ -36,6 +41,7 @@
 //   macro2   uint8[ceil(g/16)^3]    1 if any block of the 16^3-block cell is present
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -82,10 +88,91 @@ __host__ __device__ inline uint32_t hash_key(uint64_t k) {
 }
 
 // Read-only view of a map, passed by value to kernels.
+// Storage formats: 0 plain float, 1 float16 distance + uint8 weights, 2 int16 distance
+// (scaled by the truncation) + uint8 weights.  Codes are rounded half to even.
+__host__ __device__ inline uint32_t weight_code(float w) {
+  return (uint32_t)fminf(255.f, rintf(4.f * fmaxf(0.f, w)));
+}
+
+template <int F>
+struct Vox;
+
+template <>
+struct Vox<0> {
+  static constexpr int kGeoBytes = 8;
+  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
+    const float2 v = static_cast<const float2*>(g)[i];
+    s = v.x;
+    w = v.y;
+  }
+  __host__ __device__ static void store(void* g, size_t i, float s, float w) {
+    static_cast<float2*>(g)[i] = make_float2(s, w);
+  }
+  __host__ __device__ static void load_color(const uint32_t* rgb, const float* wc, size_t i,
+                                             uint32_t& code, float& w) {
+    code = rgb[i];
+    w = wc[i];
+  }
+  __host__ __device__ static void store_color(uint32_t* rgb, float* wc, size_t i, uint32_t code,
+                                              float w) {
+    rgb[i] = code;
+    wc[i] = w;
+  }
+};
+
+struct VoxPacked {
+  static constexpr int kGeoBytes = 4;
+  __host__ __device__ static float weight(uint32_t v) { return (float)((v >> 16) & 0xFFu) * 0.25f; }
+  __host__ __device__ static void load_color(const uint32_t* rgb, const float*, size_t i,
+                                             uint32_t& code, float& w) {
+    const uint32_t v = rgb[i];
+    code = v & 0xFFFFFFu;
+    w = (float)(v >> 24) * 0.25f;
+  }
+  __host__ __device__ static void store_color(uint32_t* rgb, float*, size_t i, uint32_t code,
+                                              float w) {
+    rgb[i] = (code & 0xFFFFFFu) | (weight_code(w) << 24);
+  }
+};
+
+template <>
+struct Vox<1> : VoxPacked {
+  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
+    const uint32_t v = static_cast<const uint32_t*>(g)[i];
+    s = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu)));
+    w = weight(v);
+  }
+  __host__ __device__ static void store(void* g, size_t i, float s, float w) {
+    static_cast<uint32_t*>(g)[i] =
+        (uint32_t)__half_as_ushort(__float2half_rn(s)) | (weight_code(w) << 16);
+  }
+};
+
+template <>
+struct Vox<2> : VoxPacked {
+  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
+    const uint32_t v = static_cast<const uint32_t*>(g)[i];
+    s = (float)(int16_t)(v & 0xFFFFu) * (1.0f / 32767.0f);
+    w = weight(v);
+  }
+  __host__ __device__ static void store(void* g, size_t i, float s, float w) {
+    const float q = fminf(32767.f, fmaxf(-32767.f, rintf(s * 32767.f)));
+    static_cast<uint32_t*>(g)[i] = (uint32_t)(uint16_t)(int16_t)q | (weight_code(w) << 16);
+  }
+};
+
+inline int storage_format(const dtsdf_params& p) {
+  if (p.sdf_fmt == DTSDF_SDF_F32 && p.w_fmt == DTSDF_W_F32) return 0;
+  if (p.sdf_fmt == DTSDF_SDF_F16 && p.w_fmt == DTSDF_W_U8) return 1;
+  if (p.sdf_fmt == DTSDF_SDF_I16 && p.w_fmt == DTSDF_W_U8) return 2;
+  return -1;
+}
+
 struct MapView {
   const HashEntry* entries;
   uint32_t mask;            // buckets - 1
-  float2* sw;
+  int fmt;
+  void* geo;
   uint32_t* rgb;
   float* wc;
   const int4* bkey;
@@ -148,9 +235,10 @@ struct dtsdf_map {
   dtsdf::HashEntry* entries;
   uint32_t* req;
   int4* bkey;
-  float2* sw;
+  void* geo;
   uint32_t* rgb;
   float* wc;
+  int fmt;              // storage format (see Vox)
   int32_t* counters;
   int64_t n_bricks;     // host mirror of the bricks in use
   int64_t n_blocks;     // host mirror of occupied entries (updated on sync points)
@@ -177,11 +265,13 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Minima of the eight 4^3 sub-blocks of brick `b` over voxels with w > 0 (+inf if none),
 // written to out8[0..7]; called by every thread of a 256-thread workgroup.
-__device__ inline void brick_sub_min(const float2* __restrict__ sw, size_t b, float* out8) {
+template <int F>
+__device__ inline void brick_sub_min(const void* geo, size_t b, float* out8) {
   __shared__ float vals[kVox];
   for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
-    const float2 s = sw[b * kVox + l];
-    vals[l] = s.y > 0.f ? s.x : INFINITY;
+    float sd, w;
+    Vox<F>::load(geo, b * kVox + l, sd, w);
+    vals[l] = w > 0.f ? sd : INFINITY;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

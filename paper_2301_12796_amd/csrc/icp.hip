@@ -2,14 +2,19 @@
 //
 //   reduce_k<DIM>  per live pixel: transform, projective association, rejection, residual
 //                  r = <q - y, n> and Jacobian J = (-n, -(y x n)[, -<n, y>]); every thread
-//                  sums a fixed strided subset of pixels in float32, the workgroup folds its
-//                  four waves with xor shuffles and a fixed-order LDS pass, and writes one
-//                  partial vector.  No atomics: the result is bitwise reproducible (the paper
-//                  replaced atomic block sums for exactly this reason, Sec. 5).
-//   solve_k<DIM>   one workgroup: float64 sum of the partials in block order, Cholesky
+//                  sums a fixed strided subset of pixels in float32 (optionally with Neumaier
+//                  compensation, merged by TwoSum), the workgroup folds its four waves with
+//                  xor shuffles and a fixed-order LDS pass, and writes one partial vector.
+//                  No atomics: the result is bitwise reproducible (the paper replaced atomic
+//                  block sums for exactly this reason, Sec. 5).
+//   Requests are reduced in 128 fixed pixel chunks (one workgroup each), so the summation
+//   order of a request does not depend on what else is in its batch: a request's result is
+//   bitwise the same alone (icp_step) and batched (icp_step_batch).
+//   solve_k<DIM>   one workgroup: float64 sum of the partials in chunk order, Cholesky
 //                  factorisation of H (eq. ICP_Hessian; the factor 2 cancels), xi = -H^-1 g
 //                  (eq. ICP_solution), exp(xi) in closed form and T <- exp(xi) T
 //                  (eq. deltaT_update), all on the device.
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -19,7 +24,7 @@ using namespace dtsdf;
 
 namespace {
 
-constexpr int kReduceBlocks = 512;
+constexpr int kChunks = 128;          // fixed pixel chunks per request (reduction order)
 constexpr int kReduceThreads = 256;
 
 template <int DIM>
@@ -43,24 +48,59 @@ struct IcpArgs {
   const double* pose;     // device 4x4 row-major, live -> model
 };
 
-struct ResultDev {
-  double xi[7];
-  double H[49];
-  double g[7];
-  double err;
-  double count;
-  double step;
-  int status;     // 0 ok, 1 too few inliers, 2 not positive definite
+constexpr int kNSMax = 7 * 8 / 2 + 7 + 2;   // partial sums of a 7-dof request
+
+// Device descriptor of one registration request of a batch.
+struct IcpJob {
+  IcpArgs a;
+  int dim;
+  int compensated;
+  int min_inliers;
   int pad;
+  double min_step;
+  int32_t* active;               // step only while *active != 0 (may be null: always)
+  dtsdf_icp_result* result;      // may be null
 };
 
-template <int DIM>
-__global__ __launch_bounds__(kReduceThreads) void reduce_k(IcpArgs a, float* partials) {
+// Error-free sum of two floats (Knuth's TwoSum): a + b = s + e exactly.
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Running sum with Neumaier's compensation term.
+struct CSum {
+  float s, c;
+  __device__ void add(float x) {
+    const float t = s + x;
+    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ void merge(float s2, float c2) {
+    float t, e;
+    two_sum(s, s2, t, e);
+    c = c + c2 + e;
+    s = t;
+  }
+};
+
+// Plain float32 accumulator with the same interface (compensation always zero).
+struct PSum {
+  float s, c;
+  __device__ void add(float x) { s += x; }
+  __device__ void merge(float s2, float) { s += s2; }
+};
+
+// Reduces the pixels of one chunk of a request into out[NS][2] (sum, compensation); called by
+// all threads of a 256-thread workgroup.
+template <int DIM, class Acc>
+__device__ void reduce_chunk(const IcpArgs& a, int chunk, float* __restrict__ out) {
   constexpr int NS = Sizes<DIM>::NS;
   constexpr int NH = Sizes<DIM>::NH;
-  float acc[NS];
+  Acc acc[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) acc[s] = 0.f;
+  for (int s = 0; s < NS; ++s) acc[s] = Acc{0.f, 0.f};
   float R[9], t[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -69,8 +109,9 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_k(IcpArgs a, float* par
   }
   const size_t LHW = (size_t)a.lW * a.lH;
   const size_t MHW = (size_t)a.mW * a.mH;
-  for (size_t i = (size_t)blockIdx.x * kReduceThreads + threadIdx.x; i < LHW;
-       i += (size_t)gridDim.x * kReduceThreads) {
+  const size_t per = (LHW + kChunks - 1) / kChunks;
+  const size_t begin = (size_t)chunk * per, end = begin + per < LHW ? begin + per : LHW;
+  for (size_t i = begin + threadIdx.x; i < end; i += kReduceThreads) {
     const float nlx = a.ln[i], nly = a.ln[LHW + i], nlz = a.ln[2 * LHW + i];
     if (nlx == 0.f && nly == 0.f && nlz == 0.f) continue;
     const float px = a.lv[i], py = a.lv[LHW + i], pz = a.lv[2 * LHW + i];
@@ -111,26 +152,34 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_k(IcpArgs a, float* par
 #pragma unroll
     for (int r = 0; r < DIM; ++r)
 #pragma unroll
-      for (int c = r; c < DIM; ++c) acc[s++] += w * J[r] * J[c];
+      for (int c = r; c < DIM; ++c) acc[s++].add(w * J[r] * J[c]);
 #pragma unroll
-    for (int r = 0; r < DIM; ++r) acc[NH + r] += w * J[r] * res;
-    acc[NS - 2] += w * res * res;
-    acc[NS - 1] += 1.f;
+    for (int r = 0; r < DIM; ++r) acc[NH + r].add(w * J[r] * res);
+    acc[NS - 2].add(w * res * res);
+    acc[NS - 1].add(1.f);
   }
-  __shared__ float lds[kReduceThreads / 64][NS];
+  // fixed-order tree: xor shuffles within the wave, then the four waves in LDS order
+  __shared__ float lds[kReduceThreads / 64][NS][2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    float v = acc[s];
+    Acc v = acc[s];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) lds[wave][s] = v;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const float s2 = __shfl_xor(v.s, off, 64), c2 = __shfl_xor(v.c, off, 64);
+      v.merge(s2, c2);
+    }
+    if (lane == 0) {
+      lds[wave][s][0] = v.s;
+      lds[wave][s][1] = v.c;
+    }
   }
   __syncthreads();
   if (threadIdx.x < NS) {
-    float v = 0.f;
-    for (int wv = 0; wv < kReduceThreads / 64; ++wv) v += lds[wv][threadIdx.x];
-    partials[(size_t)blockIdx.x * NS + threadIdx.x] = v;
+    Acc v{lds[0][threadIdx.x][0], lds[0][threadIdx.x][1]};
+    for (int wv = 1; wv < kReduceThreads / 64; ++wv) v.merge(lds[wv][threadIdx.x][0], lds[wv][threadIdx.x][1]);
+    out[threadIdx.x * 2] = v.s;
+    out[threadIdx.x * 2 + 1] = v.c;
   }
 }
 
@@ -187,14 +236,15 @@ __device__ void exp_sim3(const double* xi, int dim, double* E) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(64) void solve_k(const float* partials, int nblocks,
-                                             int min_inliers, double* pose, ResultDev* res) {
+__device__ void solve_one(const float* __restrict__ partials, const IcpJob& j) {
   constexpr int NS = Sizes<DIM>::NS;
   constexpr int NH = Sizes<DIM>::NH;
-  __shared__ double sums[NS];
+  __shared__ double sums[kNSMax];
   if (threadIdx.x < NS) {
     double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v += (double)partials[(size_t)b * NS + threadIdx.x];
+    for (int c = 0; c < kChunks; ++c)
+      v += (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2] +
+           (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2 + 1];
     sums[threadIdx.x] = v;
   }
   __syncthreads();
@@ -208,32 +258,26 @@ __global__ __launch_bounds__(64) void solve_k(const float* partials, int nblocks
       ++s;
     }
   for (int r = 0; r < DIM; ++r) g[r] = sums[NH + r];
-  for (int k = 0; k < 49; ++k) res->H[k] = 0.0;
-  for (int r = 0; r < DIM; ++r) {
-    for (int c = 0; c < DIM; ++c) res->H[r * DIM + c] = H[r * DIM + c];
-    res->g[r] = g[r];
-  }
-  res->err = sums[NS - 2];
-  res->count = sums[NS - 1];
   int status = 0;
-  if (sums[NS - 1] < (double)min_inliers * DIM) status = 1;
+  if (sums[NS - 1] < (double)j.min_inliers * DIM) status = 1;
   // Cholesky H = L L^T
-  for (int j = 0; j < DIM && status == 0; ++j) {
-    double d = H[j * DIM + j];
-    for (int k = 0; k < j; ++k) d -= L[j * DIM + k] * L[j * DIM + k];
+  for (int jj = 0; jj < DIM && status == 0; ++jj) {
+    double d = H[jj * DIM + jj];
+    for (int k = 0; k < jj; ++k) d -= L[jj * DIM + k] * L[jj * DIM + k];
     if (!(d > 0.0)) {
       status = 2;
       break;
     }
     const double ljj = sqrt(d);
-    L[j * DIM + j] = ljj;
-    for (int i = j + 1; i < DIM; ++i) {
-      double v = H[i * DIM + j];
-      for (int k = 0; k < j; ++k) v -= L[i * DIM + k] * L[j * DIM + k];
-      L[i * DIM + j] = v / ljj;
+    L[jj * DIM + jj] = ljj;
+    for (int i = jj + 1; i < DIM; ++i) {
+      double v = H[i * DIM + jj];
+      for (int k = 0; k < jj; ++k) v -= L[i * DIM + k] * L[jj * DIM + k];
+      L[i * DIM + jj] = v / ljj;
     }
   }
   double step = 0.0;
+  double* pose = const_cast<double*>(j.a.pose);
   if (status == 0) {
     for (int i = 0; i < DIM; ++i) {   // L y = -g
       double v = -g[i];
@@ -257,58 +301,57 @@ __global__ __launch_bounds__(64) void solve_k(const float* partials, int nblocks
         pose[4 * r + c] = v;
       }
   }
-  for (int i = 0; i < 7; ++i) res->xi[i] = xi[i];
-  res->step = step;
-  res->status = status;
-}
-
-struct Scratch {
-  double* pose = nullptr;
-  float* partials = nullptr;
-  ResultDev* res = nullptr;
-  ResultDev* host_res = nullptr;
-  double* host_pose = nullptr;
-};
-
-std::mutex g_mu;
-std::vector<Scratch> g_scratch;
-
-dtsdf_status get_scratch(Scratch** out) {
-  int dev = 0;
-  DTSDF_HIP(hipGetDevice(&dev));
-  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
-  Scratch& s = g_scratch[dev];
-  if (!s.pose) {
-    if (hipMalloc(&s.pose, sizeof(double) * 16) != hipSuccess ||
-        hipMalloc(&s.partials, sizeof(float) * kReduceBlocks * Sizes<7>::NS) != hipSuccess ||
-        hipMalloc(&s.res, sizeof(ResultDev)) != hipSuccess ||
-        hipHostMalloc(&s.host_res, sizeof(ResultDev), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s.host_pose, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
-      return DTSDF_E_NOMEM;
+  if (j.result) {
+    dtsdf_icp_result* res = j.result;
+    for (int k = 0; k < 49; ++k) res->H[k] = 0.0;
+    for (int k = 0; k < 7; ++k) res->g[k] = 0.0;
+    for (int r = 0; r < DIM; ++r) {
+      for (int c = 0; c < DIM; ++c) res->H[r * DIM + c] = H[r * DIM + c];
+      res->g[r] = g[r];
+    }
+    for (int i = 0; i < 7; ++i) res->xi[i] = xi[i];
+    res->error = sums[NS - 2];
+    res->inliers = (int64_t)sums[NS - 1];
+    res->step_norm = step;
+    res->status = status == 0 ? DTSDF_OK : DTSDF_E_DEGENERATE;
   }
-  *out = &s;
-  return DTSDF_OK;
+  if (j.active && (status != 0 || step < j.min_step)) *j.active = 0;
 }
 
-}  // namespace
+__global__ __launch_bounds__(kReduceThreads) void reduce_batch_k(const IcpJob* __restrict__ jobs,
+                                                                 float* partials) {
+  const int r = blockIdx.y, c = blockIdx.x;
+  const IcpJob& j = jobs[r];
+  if (j.active && *j.active == 0) return;
+  float* out = partials + ((size_t)r * kChunks + c) * kNSMax * 2;
+  if (j.dim == 6) {
+    if (j.compensated) reduce_chunk<6, CSum>(j.a, c, out);
+    else reduce_chunk<6, PSum>(j.a, c, out);
+  } else {
+    if (j.compensated) reduce_chunk<7, CSum>(j.a, c, out);
+    else reduce_chunk<7, PSum>(j.a, c, out);
+  }
+}
 
-extern "C" dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
-                                 const dtsdf_icp_params* p, double T[16], dtsdf_icp_result* out,
-                                 void* stream) {
-  if (!live || !model || !p || !T || (dim != 6 && dim != 7)) return DTSDF_E_INVAL;
-  if (!live->vertex || !live->normal || !model->vertex || !model->normal) return DTSDF_E_INVAL;
+__global__ __launch_bounds__(64) void solve_batch_k(const IcpJob* __restrict__ jobs,
+                                                    const float* __restrict__ partials) {
+  const IcpJob& j = jobs[blockIdx.x];
+  if (j.active && *j.active == 0) return;
+  const float* p = partials + (size_t)blockIdx.x * kChunks * kNSMax * 2;
+  if (j.dim == 6) solve_one<6>(p, j);
+  else solve_one<7>(p, j);
+}
+
+bool make_job(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
+              const dtsdf_icp_params* p, double* pose, int32_t* active, double min_step,
+              dtsdf_icp_result* result, IcpJob& j) {
+  if (!live || !model || !p || !pose || (dim != 6 && dim != 7)) return false;
+  if (!live->vertex || !live->normal || !model->vertex || !model->normal) return false;
   if (live->intr.width <= 0 || live->intr.height <= 0 || model->intr.width <= 0 ||
       model->intr.height <= 0 || !(model->intr.fx > 0) || !(model->intr.fy > 0) ||
       !(p->max_dist > 0) || !(p->max_angle_deg > 0) || p->min_inliers_per_dim < 0)
-    return DTSDF_E_INVAL;
-  std::lock_guard<std::mutex> lock(g_mu);
-  Scratch* s = nullptr;
-  dtsdf_status st = get_scratch(&s);
-  if (st != DTSDF_OK) return st;
-  hipStream_t hs = (hipStream_t)stream;
-  for (int k = 0; k < 16; ++k) s->host_pose[k] = T[k];
-  DTSDF_HIP(hipMemcpyAsync(s->pose, s->host_pose, sizeof(double) * 16, hipMemcpyHostToDevice, hs));
-  IcpArgs a;
+    return false;
+  IcpArgs& a = j.a;
   a.lv = live->vertex;
   a.ln = live->normal;
   a.lW = live->intr.width;
@@ -326,30 +369,108 @@ extern "C" dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* mod
   a.cos_angle = (float)cos((double)p->max_angle_deg * 3.14159265358979323846 / 180.0);
   a.weight_kind = p->weight;
   a.z_min = p->z_min;
-  a.pose = s->pose;
-  if (dim == 6) {
-    hipLaunchKernelGGL(reduce_k<6>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, hs, a, s->partials);
-    hipLaunchKernelGGL(solve_k<6>, dim3(1), dim3(64), 0, hs, s->partials, kReduceBlocks,
-                       p->min_inliers_per_dim, s->pose, s->res);
-  } else {
-    hipLaunchKernelGGL(reduce_k<7>, dim3(kReduceBlocks), dim3(kReduceThreads), 0, hs, a, s->partials);
-    hipLaunchKernelGGL(solve_k<7>, dim3(1), dim3(64), 0, hs, s->partials, kReduceBlocks,
-                       p->min_inliers_per_dim, s->pose, s->res);
+  a.pose = pose;
+  j.dim = dim;
+  j.compensated = p->compensated;
+  j.min_inliers = p->min_inliers_per_dim;
+  j.pad = 0;
+  j.min_step = min_step;
+  j.active = active;
+  j.result = result;
+  return true;
+}
+
+// Per-device scratch of the single-request entry point (device pose, flag, result and the
+// partial sums), guarded by a mutex: icp_step is synchronous, so calls do not overlap.
+struct Scratch {
+  uint8_t* dev = nullptr;        // job | pose | active | result
+  float* partials = nullptr;
+  uint8_t* host = nullptr;       // pinned mirror of `dev`
+};
+
+constexpr size_t kOffPose = (sizeof(IcpJob) + 63) & ~(size_t)63;
+constexpr size_t kOffActive = kOffPose + 16 * sizeof(double);
+constexpr size_t kOffResult = (kOffActive + sizeof(int32_t) + 63) & ~(size_t)63;
+constexpr size_t kScratchBytes = kOffResult + sizeof(dtsdf_icp_result);
+
+std::mutex g_mu;
+std::vector<Scratch> g_scratch;
+
+dtsdf_status get_scratch(Scratch** out) {
+  int dev = 0;
+  DTSDF_HIP(hipGetDevice(&dev));
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+  Scratch& s = g_scratch[dev];
+  if (!s.dev) {
+    if (hipMalloc(&s.dev, kScratchBytes) != hipSuccess ||
+        hipMalloc(&s.partials, sizeof(float) * 2 * kChunks * kNSMax) != hipSuccess ||
+        hipHostMalloc(&s.host, kScratchBytes, hipHostMallocDefault) != hipSuccess)
+      return DTSDF_E_NOMEM;
   }
-  DTSDF_HIP(hipGetLastError());
-  DTSDF_HIP(hipMemcpyAsync(s->host_res, s->res, sizeof(ResultDev), hipMemcpyDeviceToHost, hs));
-  DTSDF_HIP(hipMemcpyAsync(s->host_pose, s->pose, sizeof(double) * 16, hipMemcpyDeviceToHost, hs));
-  DTSDF_HIP(hipStreamSynchronize(hs));
-  const ResultDev& r = *s->host_res;
-  if (out) {
-    for (int i = 0; i < 7; ++i) out->xi[i] = r.xi[i];
-    for (int i = 0; i < 49; ++i) out->H[i] = r.H[i];
-    for (int i = 0; i < 7; ++i) out->g[i] = r.g[i];
-    out->error = r.err;
-    out->inliers = (int64_t)r.count;
-    out->step_norm = r.step;
-  }
-  if (r.status != 0) return DTSDF_E_DEGENERATE;
-  for (int k = 0; k < 16; ++k) T[k] = s->host_pose[k];
+  *out = &s;
   return DTSDF_OK;
+}
+
+}  // namespace
+
+extern "C" dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
+                                 const dtsdf_icp_params* p, double T[16], dtsdf_icp_result* out,
+                                 void* stream) {
+  if (!T) return DTSDF_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Scratch* s = nullptr;
+  dtsdf_status st = get_scratch(&s);
+  if (st != DTSDF_OK) return st;
+  IcpJob job;
+  if (!make_job(live, model, dim, p, reinterpret_cast<double*>(s->dev + kOffPose),
+                reinterpret_cast<int32_t*>(s->dev + kOffActive), 0.0,
+                reinterpret_cast<dtsdf_icp_result*>(s->dev + kOffResult), job))
+    return DTSDF_E_INVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  std::memcpy(s->host, &job, sizeof(job));
+  std::memcpy(s->host + kOffPose, T, 16 * sizeof(double));
+  const int32_t one = 1;
+  std::memcpy(s->host + kOffActive, &one, sizeof(one));
+  DTSDF_HIP(hipMemcpyAsync(s->dev, s->host, kOffResult, hipMemcpyHostToDevice, hs));
+  hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, 1), dim3(kReduceThreads), 0, hs,
+                     reinterpret_cast<const IcpJob*>(s->dev), s->partials);
+  hipLaunchKernelGGL(solve_batch_k, dim3(1), dim3(64), 0, hs,
+                     reinterpret_cast<const IcpJob*>(s->dev), s->partials);
+  DTSDF_HIP(hipGetLastError());
+  DTSDF_HIP(hipMemcpyAsync(s->host + kOffPose, s->dev + kOffPose, kScratchBytes - kOffPose,
+                           hipMemcpyDeviceToHost, hs));
+  DTSDF_HIP(hipStreamSynchronize(hs));
+  dtsdf_icp_result r;
+  std::memcpy(&r, s->host + kOffResult, sizeof(r));
+  if (out) *out = r;
+  if (r.status != DTSDF_OK) return DTSDF_E_DEGENERATE;
+  std::memcpy(T, s->host + kOffPose, 16 * sizeof(double));
+  return DTSDF_OK;
+}
+
+extern "C" dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream) {
+  if (n < 0 || (n > 0 && !reqs) || n > 65535) return DTSDF_E_INVAL;
+  if (n == 0) return DTSDF_OK;
+  std::vector<IcpJob> jobs((size_t)n);
+  for (int r = 0; r < n; ++r)
+    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].dim, &reqs[r].params, reqs[r].pose,
+                  reqs[r].active, reqs[r].min_step, reqs[r].result, jobs[r]))
+      return DTSDF_E_INVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  const size_t jb = (sizeof(IcpJob) * n + 255) & ~(size_t)255;
+  const size_t bytes = jb + sizeof(float) * 2 * kChunks * kNSMax * (size_t)n;
+  uint8_t* dev = nullptr;
+  DTSDF_HIP(hipMallocAsync((void**)&dev, bytes, hs));
+  dtsdf_status rs = DTSDF_OK;
+  if (hipMemcpyAsync(dev, jobs.data(), sizeof(IcpJob) * n, hipMemcpyHostToDevice, hs) != hipSuccess) {
+    rs = DTSDF_E_HIP;
+  } else {
+    const IcpJob* dj = reinterpret_cast<const IcpJob*>(dev);
+    float* part = reinterpret_cast<float*>(dev + jb);
+    hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
+    hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+    if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
+  }
+  if (hipFreeAsync(dev, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
+  return rs;
 }

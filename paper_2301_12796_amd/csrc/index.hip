@@ -9,8 +9,9 @@ using namespace dtsdf;
 namespace {
 
 // Sub-block minima of every brick in use; one workgroup per brick.
-__global__ __launch_bounds__(256) void brick_stats_k(const float2* __restrict__ sw, float* sub_min) {
-  brick_sub_min(sw, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
+template <int F>
+__global__ __launch_bounds__(256) void brick_stats_k(const void* geo, float* sub_min) {
+  brick_sub_min<F>(geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
 }
 
 __device__ inline bool slot_present(const HashEntry& e) {
@@ -160,9 +161,15 @@ __global__ void bbox_reset_k(int32_t* bbox) {
 namespace dtsdf {
 
 dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st) {
-  if (m->n_bricks > 0)
-    hipLaunchKernelGGL(brick_stats_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, m->sw,
-                       m->sub_min);
+  if (m->n_bricks > 0) {
+    const dim3 g((uint32_t)m->n_bricks);
+    if (m->fmt == 0)
+      hipLaunchKernelGGL(brick_stats_k<0>, g, dim3(256), 0, st, m->geo, m->sub_min);
+    else if (m->fmt == 1)
+      hipLaunchKernelGGL(brick_stats_k<1>, g, dim3(256), 0, st, m->geo, m->sub_min);
+    else
+      hipLaunchKernelGGL(brick_stats_k<2>, g, dim3(256), 0, st, m->geo, m->sub_min);
+  }
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

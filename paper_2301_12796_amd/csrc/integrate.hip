@@ -190,6 +190,7 @@ struct FuseArgs {
 
 // Voxel-projection fusion (Sec. 3) of one brick per workgroup.  A brick with any updated
 // voxel refreshes its sub-block minima (sdf over voxels with w > 0) for the render index.
+template <int F>
 __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min) {
   const int4 key = m.bkey[blockIdx.x];
   const int D = key.w;
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
     // point-to-plane distance (eq. point-to-plane) with the normal facing the camera, so that
     // positive values lie in front of the surface
     const double dd = ((xc[0] - pc[0]) * nx + (xc[1] - pc[1]) * ny + (xc[2] - pc[2]) * nz) / tau;
-    float2* swp = &m.sw[(size_t)blockIdx.x * kVox + l];
+    const size_t vi = (size_t)blockIdx.x * kVox + l;
     if (dd > 1.0) {
       // free space: value 1 with a constant weight unless a depth jump above tau lies within
       // two pixels (Sec. 3)
@@ -235,11 +236,10 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
           }
         }
       if (ok) {
-        float2 s = *swp;
-        float nw = s.y + m.w_carve;
-        s.x = (s.x * s.y + 1.0f * m.w_carve) / nw;
-        s.y = fminf(nw, m.w_max);
-        *swp = s;
+        float sd, w;
+        Vox<F>::load(m.geo, vi, sd, w);
+        const float nw = w + m.w_carve;
+        Vox<F>::store(m.geo, vi, (sd * w + 1.0f * m.w_carve) / nw, fminf(nw, m.w_max));
         upd = true;
       }
       continue;
@@ -256,11 +256,12 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
     const float w_angle = fmaxf(0.f, (float)(-(pc[0] * nx + pc[1] * ny + pc[2] * nz) / plen));
     const float wd = w_angle * wdir;
     if (wd < m.w_min) continue;
-    float2 s = *swp;
-    float nw = s.y + wd;
-    s.x = (s.x * s.y + (float)dd * wd) / nw;
-    s.y = fminf(nw, m.w_max);
-    *swp = s;
+    {
+      float sd, w;
+      Vox<F>::load(m.geo, vi, sd, w);
+      const float nw = w + wd;
+      Vox<F>::store(m.geo, vi, (sd * w + (float)dd * wd) / nw, fminf(nw, m.w_max));
+    }
     upd = true;
     if (m.with_color && a.rgb) {
       // colour weight w_c = w_d (1 - min(1, |p - x| / tau)) (eq. color_weight)
@@ -268,9 +269,9 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
                                (pc[2] - xc[2]) * (pc[2] - xc[2]));
       const float wc = wd * (1.0f - fminf(1.0f, (float)(dist / tau)));
       if (wc > 0.f) {
-        const size_t vi = (size_t)blockIdx.x * kVox + l;
-        float Wc = m.wc[vi];
-        uint32_t c = m.rgb[vi];
+        float Wc;
+        uint32_t c;
+        Vox<F>::load_color(m.rgb, m.wc, vi, c, Wc);
         const float inv = 1.0f / (Wc + wc);
         uint32_t outc = 0;
         for (int ch = 0; ch < 3; ++ch) {
@@ -280,12 +281,11 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
           val = fminf(255.f, fmaxf(0.f, val));
           outc |= (uint32_t)val << (8 * ch);
         }
-        m.rgb[vi] = outc;
-        m.wc[vi] = fminf(Wc + wc, m.w_max);
+        Vox<F>::store_color(m.rgb, m.wc, vi, outc, fminf(Wc + wc, m.w_max));
       }
     }
   }
-  if (__syncthreads_or(upd)) brick_sub_min(m.sw, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
+  if (__syncthreads_or(upd)) brick_sub_min<F>(m.geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
 }
 
 Intr make_intr(const dtsdf_intrinsics* i) {
@@ -386,8 +386,13 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
   }
   if (m->n_bricks > 0) {
     FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
-    hipLaunchKernelGGL(fuse_k, dim3((uint32_t)m->n_bricks), dim3(256), 0, st, make_view(m), fa,
-                       m->sub_min);
+    const dim3 grd_b((uint32_t)m->n_bricks);
+    if (m->fmt == 0)
+      hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
+    else if (m->fmt == 1)
+      hipLaunchKernelGGL(fuse_k<1>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
+    else
+      hipLaunchKernelGGL(fuse_k<2>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
   }
   DTSDF_HIP(hipGetLastError());
   dtsdf_status is = launch_index_update(m, st);

@@ -15,7 +15,8 @@ MapView make_view(const dtsdf_map* m) {
   MapView v;
   v.entries = m->entries;
   v.mask = m->buckets - 1;
-  v.sw = m->sw;
+  v.fmt = m->fmt;
+  v.geo = m->geo;
   v.rgb = m->rgb;
   v.wc = m->wc;
   v.bkey = m->bkey;
@@ -108,7 +109,7 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->entries);
   (void)hipFree(m->req);
   (void)hipFree(m->bkey);
-  (void)hipFree(m->sw);
+  (void)hipFree(m->geo);
   (void)hipFree(m->rgb);
   (void)hipFree(m->wc);
   (void)hipFree(m->counters);
@@ -123,9 +124,33 @@ void free_map(dtsdf_map* m) {
   delete m;
 }
 
+size_t geo_bytes(int fmt) { return fmt == 0 ? (size_t)Vox<0>::kGeoBytes : (size_t)VoxPacked::kGeoBytes; }
+
+// Host encode / decode of one voxel in format F (same rounding as the device).
+template <int F>
+void host_store(void* geo, uint32_t* rgb, float* wc, size_t i, float s, float w,
+                const uint8_t* c3, float cw, bool color) {
+  Vox<F>::store(geo, i, s, w);
+  if (color) {
+    uint32_t code = 0;
+    if (c3)
+      for (int ch = 0; ch < 3; ++ch) code |= (uint32_t)c3[ch] << (8 * ch);
+    Vox<F>::store_color(rgb, wc, i, code, cw);
+  }
+}
+
+template <int F>
+void host_load(const void* geo, const uint32_t* rgb, const float* wc, size_t i, float& s,
+               float& w, uint32_t& code, float& cw, bool color) {
+  Vox<F>::load(geo, i, s, w);
+  code = 0;
+  cw = 0.f;
+  if (color) Vox<F>::load_color(rgb, wc, i, code, cw);
+}
+
 dtsdf_status zero_pool(dtsdf_map* m) {
   size_t nv = (size_t)m->p.brick_capacity * kVox;
-  DTSDF_HIP(hipMemset(m->sw, 0, nv * sizeof(float2)));
+  DTSDF_HIP(hipMemset(m->geo, 0, nv * geo_bytes(m->fmt)));
   // 0x7f7f7f7f = 3.4e38: a brick without observed voxels bounds nothing
   DTSDF_HIP(hipMemset(m->sub_min, 0x7f, sizeof(float) * 8 * m->p.brick_capacity));
   if (m->rgb) DTSDF_HIP(hipMemset(m->rgb, 0, nv * sizeof(uint32_t)));
@@ -159,11 +184,12 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
   if (!(p->w_max > 0) || p->w_carve < 0 || p->w_min < 0) return DTSDF_E_INVAL;
   if (p->hash_buckets < 2 || (p->hash_buckets & (p->hash_buckets - 1)) != 0) return DTSDF_E_INVAL;
   if (p->brick_capacity == 0 || p->brick_capacity > (1u << 28)) return DTSDF_E_INVAL;
-  if (p->sdf_fmt != DTSDF_SDF_F32 || p->w_fmt != DTSDF_W_F32) return DTSDF_E_INVAL;
+  if (storage_format(*p) < 0) return DTSDF_E_INVAL;
   dtsdf_map* m = new (std::nothrow) dtsdf_map();
   if (!m) return DTSDF_E_NOMEM;
   std::memset(m, 0, sizeof(*m));
   m->p = *p;
+  m->fmt = storage_format(*p);
   m->buckets = p->hash_buckets;
   if (hipGetDevice(&m->device) != hipSuccess) {
     delete m;
@@ -173,13 +199,14 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
   bool ok = hipMalloc(&m->entries, sizeof(HashEntry) * m->buckets) == hipSuccess &&
             hipMalloc(&m->req, sizeof(uint32_t) * m->buckets) == hipSuccess &&
             hipMalloc(&m->bkey, sizeof(int4) * p->brick_capacity) == hipSuccess &&
-            hipMalloc(&m->sw, sizeof(float2) * nv) == hipSuccess &&
+            hipMalloc(&m->geo, geo_bytes(m->fmt) * nv) == hipSuccess &&
             hipMalloc(&m->counters, sizeof(int32_t) * 16) == hipSuccess &&
             hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess;
-  if (ok && p->with_color)
-    ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess &&
-         hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
+  if (ok && p->with_color) {
+    ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess;
+    if (ok && m->fmt == 0) ok = hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
+  }
   if (!ok) {
     free_map(m);
     return DTSDF_E_NOMEM;
@@ -224,8 +251,8 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   out->device_bytes = (int64_t)(sizeof(HashEntry) * m->buckets + sizeof(uint32_t) * m->buckets +
                                 (sizeof(int4) + 8 * sizeof(float)) * m->p.brick_capacity +
                                 8 * sizeof(float) * m->buckets +
-                                sizeof(float2) * nv +
-                                (m->p.with_color ? (sizeof(uint32_t) + sizeof(float)) * nv : 0) +
+                                geo_bytes(m->fmt) * nv +
+                                (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
                                 (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap);
   return DTSDF_OK;
 }
@@ -240,17 +267,21 @@ dtsdf_status dtsdf_export(const dtsdf_map* m, dtsdf_blob* b) {
   }
   if (b->n_bricks < n || !b->sdf || !b->w) return DTSDF_E_INVAL;
   std::vector<int4> bk((size_t)n);
-  std::vector<float2> sw((size_t)n * kVox);
+  const size_t gb = geo_bytes(m->fmt);
+  std::vector<uint8_t> geo((size_t)n * kVox * gb);
   std::vector<uint32_t> rgb;
   std::vector<float> wc;
+  const bool color = m->p.with_color != 0;
   if (n > 0) {
     DTSDF_HIP(hipMemcpy(bk.data(), m->bkey, sizeof(int4) * n, hipMemcpyDeviceToHost));
-    DTSDF_HIP(hipMemcpy(sw.data(), m->sw, sizeof(float2) * n * kVox, hipMemcpyDeviceToHost));
-    if (m->p.with_color) {
+    DTSDF_HIP(hipMemcpy(geo.data(), m->geo, gb * n * kVox, hipMemcpyDeviceToHost));
+    if (color) {
       rgb.resize((size_t)n * kVox);
-      wc.resize((size_t)n * kVox);
       DTSDF_HIP(hipMemcpy(rgb.data(), m->rgb, sizeof(uint32_t) * n * kVox, hipMemcpyDeviceToHost));
-      DTSDF_HIP(hipMemcpy(wc.data(), m->wc, sizeof(float) * n * kVox, hipMemcpyDeviceToHost));
+      if (m->fmt == 0) {
+        wc.resize((size_t)n * kVox);
+        DTSDF_HIP(hipMemcpy(wc.data(), m->wc, sizeof(float) * n * kVox, hipMemcpyDeviceToHost));
+      }
     }
   }
   std::vector<int64_t> order((size_t)n);
@@ -266,14 +297,20 @@ dtsdf_status dtsdf_export(const dtsdf_map* m, dtsdf_blob* b) {
     b->keys[4 * j + 2] = bk[i].z;
     b->keys[4 * j + 3] = bk[i].w;
     for (int l = 0; l < kVox; ++l) {
-      float2 v = sw[(size_t)i * kVox + l];
-      b->sdf[(size_t)j * kVox + l] = v.x;
-      b->w[(size_t)j * kVox + l] = v.y;
-      if (b->rgb) {
-        uint32_t c = m->p.with_color ? rgb[(size_t)i * kVox + l] : 0u;
-        for (int ch = 0; ch < 3; ++ch) b->rgb[((size_t)j * kVox + l) * 3 + ch] = (c >> (8 * ch)) & 0xFF;
-      }
-      if (b->wc) b->wc[(size_t)j * kVox + l] = m->p.with_color ? wc[(size_t)i * kVox + l] : 0.f;
+      const size_t src = (size_t)i * kVox + l, dst = (size_t)j * kVox + l;
+      float sd, w, cw;
+      uint32_t c;
+      if (m->fmt == 0)
+        host_load<0>(geo.data(), rgb.data(), wc.data(), src, sd, w, c, cw, color);
+      else if (m->fmt == 1)
+        host_load<1>(geo.data(), rgb.data(), wc.data(), src, sd, w, c, cw, color);
+      else
+        host_load<2>(geo.data(), rgb.data(), wc.data(), src, sd, w, c, cw, color);
+      b->sdf[dst] = sd;
+      b->w[dst] = w;
+      if (b->rgb)
+        for (int ch = 0; ch < 3; ++ch) b->rgb[dst * 3 + ch] = (c >> (8 * ch)) & 0xFF;
+      if (b->wc) b->wc[dst] = cw;
     }
   }
   b->n_bricks = n;
@@ -294,21 +331,25 @@ dtsdf_status dtsdf_import(dtsdf_map* m, const dtsdf_blob* b) {
   std::sort(order.begin(), order.end(),
             [&](int64_t a, int64_t c) { return key_less(keys[a], keys[c]); });
   std::vector<HostKey> sorted((size_t)n);
-  std::vector<float2> sw((size_t)n * kVox);
-  std::vector<uint32_t> rgb(m->p.with_color ? (size_t)n * kVox : 0);
-  std::vector<float> wc(m->p.with_color ? (size_t)n * kVox : 0);
+  const size_t gb = geo_bytes(m->fmt);
+  const bool color = m->p.with_color != 0;
+  std::vector<uint8_t> geo((size_t)n * kVox * gb);
+  std::vector<uint32_t> rgb(color ? (size_t)n * kVox : 0);
+  std::vector<float> wc(color && m->fmt == 0 ? (size_t)n * kVox : 0);
   for (int64_t j = 0; j < n; ++j) {
     int64_t i = order[j];
     sorted[j] = keys[i];
     for (int l = 0; l < kVox; ++l) {
-      sw[(size_t)j * kVox + l] = make_float2(b->sdf[(size_t)i * kVox + l], b->w[(size_t)i * kVox + l]);
-      if (m->p.with_color) {
-        uint32_t c = 0;
-        if (b->rgb)
-          for (int ch = 0; ch < 3; ++ch) c |= (uint32_t)b->rgb[((size_t)i * kVox + l) * 3 + ch] << (8 * ch);
-        rgb[(size_t)j * kVox + l] = c;
-        wc[(size_t)j * kVox + l] = b->wc ? b->wc[(size_t)i * kVox + l] : 0.f;
-      }
+      const size_t src = (size_t)i * kVox + l, dst = (size_t)j * kVox + l;
+      const float sd = b->sdf[src], w = b->w[src];
+      const uint8_t* c3 = b->rgb ? &b->rgb[src * 3] : nullptr;
+      const float cw = b->wc ? b->wc[src] : 0.f;
+      if (m->fmt == 0)
+        host_store<0>(geo.data(), rgb.data(), wc.data(), dst, sd, w, c3, cw, color);
+      else if (m->fmt == 1)
+        host_store<1>(geo.data(), rgb.data(), wc.data(), dst, sd, w, c3, cw, color);
+      else
+        host_store<2>(geo.data(), rgb.data(), wc.data(), dst, sd, w, c3, cw, color);
     }
   }
   dtsdf_status st = zero_pool(m);
@@ -321,10 +362,11 @@ dtsdf_status dtsdf_import(dtsdf_map* m, const dtsdf_blob* b) {
     return st;
   }
   if (n > 0) {
-    DTSDF_HIP(hipMemcpy(m->sw, sw.data(), sizeof(float2) * n * kVox, hipMemcpyHostToDevice));
-    if (m->p.with_color) {
+    DTSDF_HIP(hipMemcpy(m->geo, geo.data(), gb * n * kVox, hipMemcpyHostToDevice));
+    if (color) {
       DTSDF_HIP(hipMemcpy(m->rgb, rgb.data(), sizeof(uint32_t) * n * kVox, hipMemcpyHostToDevice));
-      DTSDF_HIP(hipMemcpy(m->wc, wc.data(), sizeof(float) * n * kVox, hipMemcpyHostToDevice));
+      if (m->fmt == 0)
+        DTSDF_HIP(hipMemcpy(m->wc, wc.data(), sizeof(float) * n * kVox, hipMemcpyHostToDevice));
     }
   }
   DTSDF_HIP(hipMemset(m->req, 0, sizeof(uint32_t) * m->buckets));

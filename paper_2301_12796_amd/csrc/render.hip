@@ -23,7 +23,9 @@
 //     with the Illinois variant of regula falsi (every fourth step a bisection), undefined
 //     points counting as free space; outputs are evaluated at the bracket end inside the
 //     surface.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "dtsdf_internal.hpp"
 
@@ -127,7 +129,7 @@ struct Eval {
   bool color_ok;
 };
 
-template <bool FULL>
+template <int F, bool FULL>
 __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, const float r[3],
                           float inv_band, Eval& e, const Trace& tr) {
   e.defined = false;
@@ -186,9 +188,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
     for (int c = 0; c < 8; ++c) {
       const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
                       64 * ((lz + ((c >> 2) & 1)) & 7);
-      const float2 v = m.sw[(size_t)br[c] * kVox + loc];
-      sv[c] = v.x;
-      wv[c] = v.y;
+      Vox<F>::load(m.geo, (size_t)br[c] * kVox + loc, sv[c], wv[c]);
       if (tr.bricks) tr.bricks[br[c]] = 1;
     }
     bool wok = true;
@@ -242,8 +242,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
                           64 * ((lz + ((c >> 2) & 1)) & 7);
           const size_t vi = (size_t)br[c] * kVox + loc;
           if (tr.color) tr.color[br[c]] = 1;
-          const float w = m.wc[vi];
-          const uint32_t code = m.rgb[vi];
+          float w;
+          uint32_t code;
+          Vox<F>::load_color(m.rgb, m.wc, vi, code, w);
           cok = cok && (w > 0.f);
           wsum = fmaf(tw[c], w, wsum);
           c0 = fmaf(tw[c], (float)(code & 0xFFu), c0);
@@ -303,22 +304,17 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
 }
 
 // Evaluates the combined SDF at an arbitrary point (refinement, outputs).
-template <bool FULL>
+template <int F, bool FULL>
 __device__ void eval_at(const MapView& m, const double x[3], const float r[3], float inv_band,
                         Eval& e, const Trace& tr) {
   CellPos cp;
   locate(m, x, cp);
-  eval_cell<FULL>(m, cp, block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), r, inv_band, e, tr);
+  eval_cell<F, FULL>(m, cp, block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), r, inv_band, e, tr);
 }
 
-__global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
-  // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
-  const int per = (a.tiles + 7) >> 3;
-  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (tile >= a.tiles) return;
-  const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
-  const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
-  if (u >= a.W || v >= a.H) return;
+// Renders pixel (u, v) of view `a` (inside the image).
+template <int F>
+__device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v) {
   const size_t i = (size_t)v * a.W + u;
   const size_t HW = (size_t)a.W * a.H;
   const float inv_band = 1.0f / (2.0f * m.theta - 1.5707963267948966f);
@@ -432,7 +428,7 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
     if (eslot == -2 || cp.bl[0] != cb[0] || cp.bl[1] != cb[1] || cp.bl[2] != cb[2])
       eslot = block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr);
     Eval e;
-    eval_cell<false>(m, cp, eslot, rf, inv_band, e, tr);
+    eval_cell<F, false>(m, cp, eslot, rf, inv_band, e, tr);
     if (refining) {
       ++it;
       if (!e.defined || e.f > 0.f) {
@@ -467,7 +463,7 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
     const double ts = 0.5 * (ta + tb);
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
     Eval e;
-    eval_at<true>(m, x, rf, inv_band, e, tr);
+    eval_at<F, true>(m, x, rf, inv_band, e, tr);
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
@@ -504,17 +500,51 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
   }
 }
 
-}  // namespace
+template <int F>
+__global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
+  // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
+  const int per = (a.tiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= a.tiles) return;
+  const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
+  const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
+  if (u >= a.W || v >= a.H) return;
+  render_pixel<F>(m, a, u, v);
+}
 
-extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics* intr,
-                                     const double T[16], float z_near, float z_far,
-                                     const dtsdf_render_out* out, void* stream) {
-  if (!m || !intr || !T || !out || intr->width <= 0 || intr->height <= 0 || intr->width > 16384 ||
+// Views of different sizes in one persistent launch: every wave takes the next (view, tile)
+// work item from a counter until all are done.  Each pixel is computed exactly as by
+// render_k, so a view's output does not depend on the batch it is rendered in.
+template <int F>
+__global__ __launch_bounds__(64) void render_batch_k(MapView m, const RenderArgs* __restrict__ reqs,
+                                                     const int32_t* __restrict__ prefix, int n,
+                                                     int total, int32_t* counter) {
+  for (;;) {
+    int item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+    if (item >= total) break;
+    int lo = 0, hi = n;   // prefix[lo] <= item < prefix[lo + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (prefix[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    const RenderArgs a = reqs[lo];
+    const int tile = item - prefix[lo];
+    const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
+    const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
+    if (u < a.W && v < a.H) render_pixel<F>(m, a, u, v);
+  }
+}
+
+bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, float z_far,
+               const dtsdf_render_out* out, RenderArgs& a) {
+  if (!intr || !T || !out || intr->width <= 0 || intr->height <= 0 || intr->width > 16384 ||
       intr->height > 16384 || !(intr->fx > 0) || !(intr->fy > 0) || !(z_near > 0) ||
       !(z_far > z_near))
-    return DTSDF_E_INVAL;
-  if (out->rgba && ((uintptr_t)out->rgba & 3u)) return DTSDF_E_INVAL;
-  RenderArgs a;
+    return false;
+  if (out->rgba && ((uintptr_t)out->rgba & 3u)) return false;
   a.W = intr->width;
   a.H = intr->height;
   a.tiles_x = (a.W + 7) / 8;
@@ -538,8 +568,69 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
   a.trace_color = out->trace_color;
   a.trace_slots = out->trace_slots;
   a.trace_counts = out->trace_counts;
+  return true;
+}
+
+}  // namespace
+
+extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics* intr,
+                                     const double T[16], float z_near, float z_far,
+                                     const dtsdf_render_out* out, void* stream) {
+  RenderArgs a;
+  if (!m || !fill_args(intr, T, z_near, z_far, out, a)) return DTSDF_E_INVAL;
   const int per = (a.tiles + 7) / 8;
-  hipLaunchKernelGGL(render_k, dim3(per * 8), dim3(64), 0, (hipStream_t)stream, make_view(m), a);
+  const dim3 grd(per * 8);
+  if (m->fmt == 0)
+    hipLaunchKernelGGL(render_k<0>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
+  else if (m->fmt == 1)
+    hipLaunchKernelGGL(render_k<1>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
+  else
+    hipLaunchKernelGGL(render_k<2>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
+}
+
+extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
+                                           const dtsdf_render_req* reqs, void* stream) {
+  if (!m || n < 0 || (n > 0 && !reqs) || n > 4096) return DTSDF_E_INVAL;
+  if (n == 0) return DTSDF_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // descriptor block: counter (16 B) | prefix[n + 1] | RenderArgs[n]
+  const size_t off_prefix = 16;
+  const size_t off_args = (off_prefix + sizeof(int32_t) * (n + 1) + 63) & ~(size_t)63;
+  const size_t bytes = off_args + sizeof(RenderArgs) * n;
+  std::vector<uint8_t> host(bytes, 0);
+  int32_t* prefix = reinterpret_cast<int32_t*>(host.data() + off_prefix);
+  RenderArgs* args = reinterpret_cast<RenderArgs*>(host.data() + off_args);
+  int64_t total = 0;
+  for (int r = 0; r < n; ++r) {
+    if (!fill_args(&reqs[r].intr, reqs[r].T_world_cam, reqs[r].z_near, reqs[r].z_far,
+                   &reqs[r].out, args[r]))
+      return DTSDF_E_INVAL;
+    prefix[r] = (int32_t)total;
+    total += args[r].tiles;
+    if (total > (int64_t)1 << 30) return DTSDF_E_INVAL;
+  }
+  prefix[n] = (int32_t)total;
+  uint8_t* dev = nullptr;
+  DTSDF_HIP(hipMallocAsync((void**)&dev, bytes, st));
+  dtsdf_status rs = DTSDF_OK;
+  if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    rs = DTSDF_E_HIP;
+  } else {
+    const int wgs = (int)std::min<int64_t>(total, 2048);
+    const MapView v = make_view(m);
+    const RenderArgs* da = reinterpret_cast<const RenderArgs*>(dev + off_args);
+    const int32_t* dp = reinterpret_cast<const int32_t*>(dev + off_prefix);
+    int32_t* ctr = reinterpret_cast<int32_t*>(dev);
+    if (m->fmt == 0)
+      hipLaunchKernelGGL(render_batch_k<0>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    else if (m->fmt == 1)
+      hipLaunchKernelGGL(render_batch_k<1>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    else
+      hipLaunchKernelGGL(render_batch_k<2>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
+  }
+  if (hipFreeAsync(dev, st) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
+  return rs;
 }

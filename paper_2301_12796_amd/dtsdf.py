@@ -84,21 +84,37 @@ class _Image(ctypes.Structure):
 class _IcpParams(ctypes.Structure):
     _fields_ = [("max_dist", ctypes.c_float), ("max_angle_deg", ctypes.c_float),
                 ("weight", ctypes.c_int32), ("z_min", ctypes.c_float),
-                ("min_inliers_per_dim", ctypes.c_int32)]
+                ("min_inliers_per_dim", ctypes.c_int32), ("compensated", ctypes.c_int32)]
 
 
 class _IcpResult(ctypes.Structure):
     _fields_ = [("xi", ctypes.c_double * 7), ("H", ctypes.c_double * 49),
                 ("g", ctypes.c_double * 7), ("error", ctypes.c_double),
-                ("inliers", ctypes.c_int64), ("step_norm", ctypes.c_double)]
+                ("inliers", ctypes.c_int64), ("step_norm", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _RenderReq(ctypes.Structure):
+    _fields_ = [("intr", _Intr), ("T_world_cam", ctypes.c_double * 16),
+                ("z_near", ctypes.c_float), ("z_far", ctypes.c_float), ("out", _RenderOut)]
+
+
+class _IcpReq(ctypes.Structure):
+    _fields_ = [("live", _Image), ("model", _Image), ("dim", ctypes.c_int32),
+                ("params", _IcpParams), ("pose", ctypes.c_void_p), ("active", ctypes.c_void_p),
+                ("min_step", ctypes.c_double), ("result", ctypes.c_void_p)]
+
+
+ICP_RESULT_BYTES = ctypes.sizeof(_IcpResult)
 
 
 _V = ctypes.c_void_p
 _D16 = ctypes.POINTER(ctypes.c_double)
 
 EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate",
-            "dtsdf_render", "dtsdf_export", "dtsdf_import", "dtsdf_vertex_normal",
-            "dtsdf_depth_downsample", "icp_step", "dtsdf_status_string"]
+            "dtsdf_render", "dtsdf_render_batch", "dtsdf_export", "dtsdf_import",
+            "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
+            "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
 _lib.dtsdf_status_string.argtypes = [ctypes.c_int]
@@ -115,6 +131,8 @@ _lib.dtsdf_vertex_normal.argtypes = [_V, ctypes.POINTER(_Intr), ctypes.c_float, 
 _lib.dtsdf_depth_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes.c_int32,
                           ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
+_lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
+_lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 for _f in EXPORTED:
     if _f != "dtsdf_status_string":
         getattr(_lib, _f).restype = ctypes.c_int
@@ -237,6 +255,31 @@ class Map:
                         bricks=st.bricks)
         return status
 
+    def _render_out(self, cam, out: dict) -> _RenderOut:
+        H, W = int(cam.height), int(cam.width)
+        cap, nb = self.params.brick_capacity, self.params.hash_buckets
+        return _RenderOut(_dev_ptr(out.get("depth"), torch.float32, H * W),
+                          _dev_ptr(out.get("vertex"), torch.float32, 3 * H * W),
+                          _dev_ptr(out.get("normal"), torch.float32, 3 * H * W),
+                          _dev_ptr(out.get("rgba"), torch.uint8, 4 * H * W),
+                          _dev_ptr(out.get("mask"), torch.uint8, H * W),
+                          _dev_ptr(out.get("trace_bricks"), torch.uint8, cap),
+                          _dev_ptr(out.get("trace_color"), torch.uint8, cap),
+                          _dev_ptr(out.get("trace_slots"), torch.uint8, nb),
+                          _dev_ptr(out.get("trace_counts"), torch.int32, 4 * H * W))
+
+    def render_batch(self, views, stream=None) -> None:
+        """views: list of (cam, T_wc, z_near, z_far, out dict of preallocated tensors)."""
+        n = len(views)
+        reqs = (_RenderReq * n)()
+        for i, (cam, T, zn, zf, out) in enumerate(views):
+            reqs[i].intr = _intr(cam)
+            reqs[i].T_world_cam = _pose(T)
+            reqs[i].z_near = zn
+            reqs[i].z_far = zf
+            reqs[i].out = self._render_out(cam, out)
+        _check(_lib.dtsdf_render_batch(self._h, n, reqs, _stream(stream)), "dtsdf_render_batch")
+
     def render(self, cam, T_wc, z_near: float = 0.2, z_far: float = 10.0,
                out: Optional[dict] = None, outputs=("depth", "vertex", "normal", "rgba", "mask"),
                stream=None) -> dict:
@@ -250,16 +293,7 @@ class Map:
             for k in outputs:
                 shp, dt = shapes[k]
                 out[k] = torch.empty(shp, dtype=dt, device=dev)
-        cap, nb = self.params.brick_capacity, self.params.hash_buckets
-        ro = _RenderOut(_dev_ptr(out.get("depth"), torch.float32, H * W),
-                        _dev_ptr(out.get("vertex"), torch.float32, 3 * H * W),
-                        _dev_ptr(out.get("normal"), torch.float32, 3 * H * W),
-                        _dev_ptr(out.get("rgba"), torch.uint8, 4 * H * W),
-                        _dev_ptr(out.get("mask"), torch.uint8, H * W),
-                        _dev_ptr(out.get("trace_bricks"), torch.uint8, cap),
-                        _dev_ptr(out.get("trace_color"), torch.uint8, cap),
-                        _dev_ptr(out.get("trace_slots"), torch.uint8, nb),
-                        _dev_ptr(out.get("trace_counts"), torch.int32, 4 * H * W))
+        ro = self._render_out(cam, out)
         _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
                                  ctypes.byref(ro), _stream(stream)), "dtsdf_render")
         return out
@@ -321,6 +355,7 @@ class IcpParams:
     weight: int = ICP_W_CONST
     z_min: float = 0.1
     min_inliers_per_dim: int = 64
+    compensated: bool = False
 
 
 def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
@@ -337,7 +372,7 @@ def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
                    _dev_ptr(model_mask, torch.uint8, Hm * Wm) if model_mask is not None else None,
                    _intr(model_cam))
     p = _IcpParams(params.max_dist, params.max_angle_deg, params.weight, params.z_min,
-                   params.min_inliers_per_dim)
+                   params.min_inliers_per_dim, int(params.compensated))
     T = _pose(T_model_live)
     r = _IcpResult()
     status = _lib.icp_step(ctypes.byref(live), ctypes.byref(model), dim, ctypes.byref(p), T,
@@ -346,6 +381,55 @@ def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
     res = dict(xi=np.array(r.xi[:dim]), H=np.array(r.H[:dim * dim]).reshape(dim, dim),
                g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm)
     return status, np.array(T[:]).reshape(4, 4), res
+
+
+@dataclasses.dataclass
+class IcpRequest:
+    """One request of icp_step_batch: device images plus device pose / flag / result."""
+    live_vertex: torch.Tensor
+    live_normal: torch.Tensor
+    live_cam: object
+    model_vertex: torch.Tensor
+    model_normal: torch.Tensor
+    model_mask: Optional[torch.Tensor]
+    model_cam: object
+    pose: torch.Tensor                 # float64 (4, 4) device tensor, updated in place
+    active: Optional[torch.Tensor]     # int32 (1,) device tensor or None
+    result: Optional[torch.Tensor]     # uint8 (ICP_RESULT_BYTES,) device tensor or None
+    dim: int = 6
+    params: IcpParams = dataclasses.field(default_factory=IcpParams)
+    min_step: float = 0.0
+
+
+def icp_step_batch(requests, stream=None) -> None:
+    n = len(requests)
+    reqs = (_IcpReq * n)()
+    for i, q in enumerate(requests):
+        Hl, Wl = int(q.live_cam.height), int(q.live_cam.width)
+        Hm, Wm = int(q.model_cam.height), int(q.model_cam.width)
+        reqs[i].live = _Image(_dev_ptr(q.live_vertex, torch.float32, 3 * Hl * Wl),
+                              _dev_ptr(q.live_normal, torch.float32, 3 * Hl * Wl), None,
+                              _intr(q.live_cam))
+        reqs[i].model = _Image(_dev_ptr(q.model_vertex, torch.float32, 3 * Hm * Wm),
+                               _dev_ptr(q.model_normal, torch.float32, 3 * Hm * Wm),
+                               _dev_ptr(q.model_mask, torch.uint8, Hm * Wm)
+                               if q.model_mask is not None else None, _intr(q.model_cam))
+        reqs[i].dim = q.dim
+        p = q.params
+        reqs[i].params = _IcpParams(p.max_dist, p.max_angle_deg, p.weight, p.z_min,
+                                    p.min_inliers_per_dim, int(p.compensated))
+        reqs[i].pose = _dev_ptr(q.pose, torch.float64, 16)
+        reqs[i].active = _dev_ptr(q.active, torch.int32, 1) if q.active is not None else None
+        reqs[i].min_step = q.min_step
+        reqs[i].result = _dev_ptr(q.result, torch.uint8, ICP_RESULT_BYTES) \
+            if q.result is not None else None
+    _check(_lib.icp_step_batch(n, reqs, _stream(stream)), "icp_step_batch")
+
+
+def decode_result(raw: torch.Tensor) -> dict:
+    r = _IcpResult.from_buffer_copy(bytes(raw.cpu().numpy()))
+    return dict(xi=np.array(r.xi[:]), error=r.error, inliers=r.inliers, step_norm=r.step_norm,
+                status=r.status)
 
 
 def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,

@@ -1,0 +1,252 @@
+"""Continuous batching of render + ICP requests from several sensors over one resident map.
+
+A request carries a live depth frame of one sensor (any resolution, intrinsics and depth
+scale), the pose to render the model at, and a prior offset.  Its work is a three-level model
+render (one view per pyramid level) and coarse-to-fine point-to-plane ICP in Sim(3)
+(or SE(3)) with the live frame, the scale factor of the sensor being part of the estimate.
+
+The server runs in rounds.  At the start of a round every request whose arrival time has
+passed is admitted while a slot is free and the device memory it needs fits the budget; the
+model pyramids of all newly admitted requests are rendered in one `dtsdf_render_batch`
+launch, and every admitted request then advances by one ICP iteration in one
+`icp_step_batch` (poses, convergence flags and results stay in device memory).  A request
+leaves after its last iteration of the finest level; its slot and memory are freed for the
+next round.  Requests that arrive while others are on the device therefore join the running
+batch (continuous batching, not a queue in front of a serial worker), and each request's
+result is bitwise the same as when it is served alone.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import dtsdf
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds from the start of the run
+    sensor: int
+    live_depth: torch.Tensor       # (H, W) float32 on the device
+    T_model: np.ndarray            # camera-to-world pose the model is rendered at
+    dT0: np.ndarray                # initial live -> model transform (4x4, may carry scale)
+    # filled by the server
+    admitted: float = math.nan
+    finished: float = math.nan
+    pose: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
+class _Slot:
+    live_levels: list              # per level (vertex, normal, cam)
+    model_levels: list             # per level (vertex, normal, mask, cam)
+    pose: torch.Tensor
+    active: torch.Tensor
+    result: torch.Tensor
+    req: Optional[Request] = None
+    level: int = 0
+    it: int = 0
+    need: int = 0
+
+
+def request_bytes(cam, levels: int = 3) -> int:
+    """Device memory one request of this sensor holds while admitted: live pyramid depth,
+    vertex and normal (28 B/px) and model vertex, normal and mask (25 B/px) per level."""
+    px = sum((cam.width >> l) * (cam.height >> l) for l in range(levels))
+    return px * (28 + 25) + 1024
+
+
+class Server:
+    def __init__(self, gmap: dtsdf.Map, sensors: Sequence, *, slots: int = 8,
+                 budget_bytes: Optional[int] = None, dim: int = 7, iters=(10, 5, 4),
+                 params: dtsdf.IcpParams = dtsdf.IcpParams(), min_step: float = 1e-6,
+                 z_near: float = 0.2, z_far: float = 10.0, stream=None):
+        self.map = gmap
+        self.sensors = list(sensors)          # list of (cam, depth_scale)
+        self.dim = dim
+        self.iters = tuple(iters)
+        self.L = len(self.iters)
+        self.params = params
+        self.min_step = min_step
+        self.z_near, self.z_far = z_near, z_far
+        self.stream = stream
+        biggest = max(request_bytes(c, self.L) for c, _ in self.sensors)
+        self.budget = budget_bytes if budget_bytes is not None else 8 * biggest
+        if self.budget < biggest:
+            raise ValueError(f"memory budget {self.budget} B is below one request of the "
+                             f"largest sensor ({biggest} B)")
+        if slots < 1:
+            raise ValueError("at least one slot is needed")
+        self.in_use = 0
+        self.peak_bytes = 0
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self._slots: List[_Slot] = []
+        # slot buffers are sized for the largest sensor and reused (no allocation per request)
+        Wm = max(c.width for c, _ in self.sensors)
+        Hm = max(c.height for c, _ in self.sensors)
+        for _ in range(slots):
+            live, model = [], []
+            for l in range(self.L):
+                w, h = Wm >> l, Hm >> l
+                live.append(dict(depth=torch.empty(h * w, dtype=torch.float32, device=dev),
+                                 vertex=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
+                                 normal=torch.empty(3 * h * w, dtype=torch.float32, device=dev)))
+                model.append(dict(vertex=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
+                                  normal=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
+                                  mask=torch.empty(h * w, dtype=torch.uint8, device=dev)))
+            self._slots.append(_Slot(
+                live_levels=live, model_levels=model,
+                pose=torch.zeros((4, 4), dtype=torch.float64, device=dev),
+                active=torch.zeros(1, dtype=torch.int32, device=dev),
+                result=torch.zeros(dtsdf.ICP_RESULT_BYTES, dtype=torch.uint8, device=dev)))
+        self.rounds = 0
+        self.batch_sizes: List[int] = []
+
+    # -- per-request set-up --------------------------------------------------------------
+    def _views(self, s: _Slot, req: Request):
+        cam, scale = self.sensors[req.sensor]
+        views = []
+        for l in range(self.L):
+            c = dtsdf.level_camera(cam, l)
+            n = c.width * c.height
+            mb = s.model_levels[l]
+            out = dict(vertex=mb["vertex"][:3 * n], normal=mb["normal"][:3 * n],
+                       mask=mb["mask"][:n])
+            views.append((c, req.T_model, self.z_near, self.z_far, out))
+        return views
+
+    def _prepare_live(self, s: _Slot, req: Request):
+        cam, scale = self.sensors[req.sensor]
+        d = req.live_depth.reshape(-1)
+        for l in range(self.L):
+            c = dtsdf.level_camera(cam, l)
+            n = c.width * c.height
+            lb = s.live_levels[l]
+            if l == 0:
+                lb["depth"][:n].copy_(d)
+            else:
+                p = dtsdf.level_camera(cam, l - 1)
+                src = s.live_levels[l - 1]["depth"][:p.width * p.height].view(p.height, p.width)
+                dtsdf._check(dtsdf._lib.dtsdf_depth_downsample(
+                    dtsdf._dev_ptr(src, torch.float32), p.width, p.height,
+                    dtsdf._dev_ptr(lb["depth"], torch.float32), dtsdf._stream(self.stream)),
+                    "dtsdf_depth_downsample")
+            dtsdf._check(dtsdf._lib.dtsdf_vertex_normal(
+                dtsdf._dev_ptr(lb["depth"], torch.float32), dtsdf.ctypes.byref(dtsdf._intr(c)),
+                1.0, dtsdf._dev_ptr(lb["vertex"], torch.float32),
+                dtsdf._dev_ptr(lb["normal"], torch.float32), dtsdf._stream(self.stream)),
+                "dtsdf_vertex_normal")
+
+    def _icp_request(self, s: _Slot) -> dtsdf.IcpRequest:
+        cam, _ = self.sensors[s.req.sensor]
+        c = dtsdf.level_camera(cam, s.level)
+        n = c.width * c.height
+        lb, mb = s.live_levels[s.level], s.model_levels[s.level]
+        return dtsdf.IcpRequest(lb["vertex"][:3 * n], lb["normal"][:3 * n], c,
+                                mb["vertex"][:3 * n], mb["normal"][:3 * n], mb["mask"][:n], c,
+                                s.pose, s.active, s.result, dim=self.dim, params=self.params,
+                                min_step=self.min_step)
+
+    # -- the loop --------------------------------------------------------------------------
+    def run(self, requests: Sequence[Request], *, realtime: bool = True) -> List[Request]:
+        """Serves `requests` (sorted by arrival).  With realtime, arrivals follow the wall
+        clock from the start of the call; otherwise every request is available at once."""
+        queue = deque(sorted(requests, key=lambda r: r.arrival))
+        done: List[Request] = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0   # noqa: E731
+        while queue or any(s.req is not None for s in self._slots):
+            # admission: arrived requests, free slot, memory budget
+            new_views, newly = [], []
+            t = now()
+            for s in self._slots:
+                if not queue or (realtime and queue[0].arrival > t):
+                    break
+                if s.req is not None:
+                    continue
+                cam, _ = self.sensors[queue[0].sensor]
+                need = request_bytes(cam, self.L)
+                if self.in_use + need > self.budget:
+                    break
+                req = queue.popleft()
+                req.admitted = t
+                s.req, s.level, s.it, s.need = req, self.L - 1, 0, need
+                self.in_use += need
+                self.peak_bytes = max(self.peak_bytes, self.in_use)
+                self._prepare_live(s, req)
+                s.pose.copy_(torch.from_numpy(np.ascontiguousarray(req.dT0, np.float64)))
+                s.active.fill_(1)
+                new_views += self._views(s, req)
+                newly.append(s)
+            busy = [s for s in self._slots if s.req is not None]
+            if not busy:
+                # idle until the next arrival
+                if queue and realtime:
+                    time.sleep(max(0.0, min(queue[0].arrival - now(), 0.002)))
+                continue
+            if new_views:
+                self.map.render_batch(new_views, stream=self.stream)
+            dtsdf.icp_step_batch([self._icp_request(s) for s in busy], stream=self.stream)
+            self.batch_sizes.append(len(busy))
+            self.rounds += 1
+            finished = []
+            for s in busy:
+                s.it += 1
+                if s.it >= self.iters[s.level]:
+                    s.level -= 1
+                    s.it = 0
+                    if s.level < 0:
+                        finished.append(s)
+                    else:
+                        s.active.fill_(1)          # the next level starts afresh
+            torch.cuda.synchronize()
+            t = now()
+            for s in finished:
+                req = s.req
+                req.finished = t
+                req.pose = s.pose.cpu().numpy()
+                done.append(req)
+                self.in_use -= s.need
+                s.req = None
+        return done
+
+
+def serve_serial(gmap: dtsdf.Map, sensors: Sequence, requests: Sequence[Request], *, dim: int = 7,
+                 iters=(10, 5, 4), params: dtsdf.IcpParams = dtsdf.IcpParams(),
+                 min_step: float = 1e-6, z_near: float = 0.2, z_far: float = 10.0,
+                 realtime: bool = True) -> List[Request]:
+    """Baseline: one request at a time with the unbatched calls (three renders, per-level
+    vertex/normal, icp_step with a host round-trip per iteration), in arrival order."""
+    out = []
+    t0 = time.perf_counter()
+    for req in sorted(requests, key=lambda r: r.arrival):
+        if realtime:
+            wait = req.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+        req.admitted = time.perf_counter() - t0
+        cam, _ = sensors[req.sensor]
+        levels = []
+        for l in range(len(iters)):
+            c = dtsdf.level_camera(cam, l)
+            o = gmap.render(c, req.T_model, z_near, z_far, outputs=("vertex", "normal", "mask"))
+            levels.append((o["vertex"], o["normal"], o["mask"], c))
+        T, _ = dtsdf.icp(req.live_depth, cam, levels, req.dT0, dim=dim, iters=iters,
+                         params=params, min_step=min_step)
+        req.finished = time.perf_counter() - t0
+        req.pose = T
+        out.append(req)
+    return out
+
+
+def latency_stats(reqs: Sequence[Request]) -> dict:
+    lat = np.array([r.finished - r.arrival for r in reqs]) * 1e3
+    return dict(p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                mean_ms=float(lat.mean()), max_ms=float(lat.max()))

@@ -10,6 +10,6 @@ from .scenes import (  # noqa: F401
     Camera, Sphere, Box, Room, Scene, look_at, raycast_scene, render_frame,
     tiny_scene, tiny_cameras, tiny_frames, tiny_render_pose,
     room_scene, room_pose, room_frames, room_camera,
-    tracking_cases, precision_scale, serving_sensors, serving_requests,
+    tracking_cases, precision_scale, serving_sensors, serving_requests, serving_workload,
     perturb_pose, random_rotation_small,
 )

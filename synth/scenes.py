@@ -432,3 +432,25 @@ def serving_requests(n: int = 3600, rate: float = 120.0, n_sensors: int = 4, see
     phi = rng.uniform(0.0, 2.0 * math.pi, n)
     offs = [perturb_pose(0.02, math.radians(2.0), rng) for _ in range(n)]
     return [(float(t[i]), int(sensor[i]), float(phi[i]), offs[i]) for i in range(n)]
+
+
+def serving_workload(n: int = 240, rate: float = 120.0, seed: int = 14, sensors=None,
+                     device: str = "cpu", prior_scale_error: float = 0.01):
+    """Request stream of the serving workload on the tiny scene: per request the arrival
+    time, the sensor index, the camera pose the model is rendered at, the live depth frame
+    of that sensor at that pose (its depth scaled by the sensor's factor s, noise
+    N(0, 0.5 mm^2) seeded by the request index) and the initial live -> model transform: a
+    2 cm / 2 degree rigid offset whose linear part is multiplied by (1 + prior_scale_error) / s,
+    i.e. a scale prior that is off by ``prior_scale_error``."""
+    sensors = sensors if sensors is not None else serving_sensors()
+    sc = tiny_scene()
+    out = []
+    for k, (t, si, phi, off) in enumerate(serving_requests(n, rate, len(sensors), seed)):
+        cam, s = sensors[si]
+        T = tiny_render_pose(phi)
+        f = render_frame(sc, cam, T, noise="const", sigma=0.0005, seed=5000 + k,
+                         depth_scale=s, device=device)
+        dT0 = off.copy()
+        dT0[:3, :3] *= (1.0 + prior_scale_error) / s
+        out.append(dict(arrival=t, sensor=si, T_model=T, depth=f["depth"], dT0=dT0, scale=s))
+    return out

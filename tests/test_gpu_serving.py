@@ -1,0 +1,185 @@
+"""Serving form: batched render and batched ICP give, per request, bitwise the result of the
+same request served alone; the continuous-batching server agrees with the serial baseline."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests import parity as P
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dtsdf():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2301_12796_amd import dtsdf as lib
+    return lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def tiny_map(dtsdf):
+    gm = dtsdf.Map(P.tiny_gpu_params(dtsdf))
+    for f in synth.tiny_frames(10):
+        gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.TINY_CAM, f["T_wc"])
+    torch.cuda.synchronize()
+    return gm
+
+
+def _alloc(cam, dev="cuda"):
+    H, W = cam.height, cam.width
+    return dict(depth=torch.full((H, W), -7.0, device=dev),
+                vertex=torch.full((3, H, W), -7.0, device=dev),
+                normal=torch.full((3, H, W), -7.0, device=dev),
+                rgba=torch.full((H, W, 4), 77, dtype=torch.uint8, device=dev),
+                mask=torch.full((H, W), 77, dtype=torch.uint8, device=dev))
+
+
+def test_render_batch_matches_single_renders(dtsdf, tiny_map):
+    """Views of four sensors (320x240 .. 1280x720) and three pyramid levels in one launch."""
+    sensors = synth.serving_sensors()
+    views, singles = [], []
+    for k, (cam, _) in enumerate(sensors):
+        T = synth.tiny_render_pose(0.7 * k + 0.2)
+        for l in range(3):
+            c = dtsdf.level_camera(cam, l)
+            out = _alloc(c)
+            views.append((c, T, 0.2, 10.0, out))
+            singles.append(tiny_map.render(c, T, 0.2, 10.0))
+    print(f"case: render_batch of {len(views)} views", flush=True)
+    tiny_map.render_batch(views)
+    torch.cuda.synchronize()
+    hits = 0
+    for (c, _, _, _, out), ref in zip(views, singles):
+        for key in ("depth", "vertex", "normal", "rgba", "mask"):
+            assert torch.equal(out[key], ref[key]), key
+        hits += int((ref["mask"] > 0).sum())
+    assert hits > 10000
+
+
+def test_render_batch_of_one_and_empty(dtsdf, tiny_map):
+    cam, _ = synth.serving_sensors()[1]
+    T = synth.tiny_render_pose(1.1)
+    out = _alloc(cam)
+    tiny_map.render_batch([(cam, T, 0.2, 10.0, out)])
+    ref = tiny_map.render(cam, T, 0.2, 10.0)
+    for key in ("depth", "vertex", "normal", "rgba", "mask"):
+        assert torch.equal(out[key], ref[key]), key
+    tiny_map.render_batch([])            # no views: nothing to do, no error
+
+
+def _live_levels(dtsdf, depth, cam):
+    pyr = [depth]
+    for _ in range(2):
+        pyr.append(dtsdf.depth_downsample(pyr[-1]))
+    return [dtsdf.vertex_normal(pyr[l], dtsdf.level_camera(cam, l)) for l in range(3)]
+
+
+def test_icp_step_batch_matches_icp_step(dtsdf, tiny_map):
+    """Three requests (SE(3) and Sim(3), different sensors) advanced together for six
+    iterations; each pose and result equals the one icp_step gives for that request alone."""
+    work = synth.serving_workload(3, seed=21, device="cuda")
+    sensors = synth.serving_sensors()
+    reqs, host_T, levels = [], [], []
+    for k, w in enumerate(work):
+        cam, _ = sensors[w["sensor"]]
+        c = dtsdf.level_camera(cam, 1)
+        m = tiny_map.render(c, w["T_model"], outputs=("vertex", "normal", "mask"))
+        lv, ln = _live_levels(dtsdf, _dev(w["depth"]), cam)[1]
+        dim = 6 if k == 0 else 7
+        dT0 = w["dT0"].copy()
+        if dim == 6:
+            dT0[:3, :3] /= np.cbrt(np.linalg.det(dT0[:3, :3]))
+        reqs.append(dtsdf.IcpRequest(lv, ln, c, m["vertex"], m["normal"], m["mask"], c,
+                                     _dev(dT0), torch.ones(1, dtype=torch.int32, device="cuda"),
+                                     torch.zeros(dtsdf.ICP_RESULT_BYTES, dtype=torch.uint8,
+                                                 device="cuda"), dim=dim))
+        host_T.append(dT0)
+        levels.append((lv, ln, c, m))
+    for it in range(6):
+        print(f"case: icp_step_batch iteration {it}", flush=True)
+        dtsdf.icp_step_batch(reqs)
+        for k, q in enumerate(reqs):
+            lv, ln, c, m = levels[k]
+            status, T, res = dtsdf.icp_step(lv, ln, c, m["vertex"], m["normal"], m["mask"], c,
+                                            host_T[k], dim=q.dim)
+            assert status == dtsdf.OK
+            host_T[k] = T
+            got = q.pose.cpu().numpy()
+            assert np.array_equal(got, T), (k, it, np.abs(got - T).max())
+            r = dtsdf.decode_result(q.result)
+            assert r["inliers"] == res["inliers"] and r["error"] == res["error"]
+            assert r["step_norm"] == res["step_norm"]
+
+
+def test_icp_step_batch_respects_inactive_flag(dtsdf, tiny_map):
+    """A request whose device flag is 0 is left untouched; min_step clears the flag."""
+    w = synth.serving_workload(1, seed=22, device="cuda")[0]
+    cam, _ = synth.serving_sensors()[w["sensor"]]
+    m = tiny_map.render(cam, w["T_model"], outputs=("vertex", "normal", "mask"))
+    lv, ln = dtsdf.vertex_normal(_dev(w["depth"]), cam)
+    pose = _dev(w["dT0"])
+    active = torch.zeros(1, dtype=torch.int32, device="cuda")
+    q = dtsdf.IcpRequest(lv, ln, cam, m["vertex"], m["normal"], m["mask"], cam, pose, active,
+                         None, dim=7)
+    dtsdf.icp_step_batch([q])
+    assert np.array_equal(pose.cpu().numpy(), w["dT0"])
+    active.fill_(1)
+    q.min_step = 1e9                       # any step is below it: one step, then inactive
+    dtsdf.icp_step_batch([q])
+    assert int(active.item()) == 0
+    after = pose.cpu().numpy()
+    assert not np.array_equal(after, w["dT0"])
+    dtsdf.icp_step_batch([q])
+    assert np.array_equal(pose.cpu().numpy(), after)
+
+
+def test_server_matches_serial_and_converges(dtsdf, tiny_map):
+    """Twelve requests over four sensors served with three slots (so requests join and
+    leave a running batch): final poses are bitwise those of the serial path, and the
+    Sim(3) estimate recovers the sensor scale and the rigid offset."""
+    from paper_2301_12796_amd import serve
+    sensors = synth.serving_sensors()
+    work = synth.serving_workload(12, seed=23, device="cuda")
+
+    def requests():
+        return [serve.Request(k, w["arrival"], w["sensor"], _dev(w["depth"]), w["T_model"],
+                              w["dT0"]) for k, w in enumerate(work)]
+    srv = serve.Server(tiny_map, sensors, slots=3)
+    print("case: server, 12 requests, 3 slots", flush=True)
+    got = {r.rid: r for r in srv.run(requests(), realtime=False)}
+    assert max(srv.batch_sizes) == 3 and len(got) == 12
+    print("case: serial baseline, 12 requests", flush=True)
+    ref = {r.rid: r for r in serve.serve_serial(tiny_map, sensors, requests(), realtime=False)}
+    for k, w in enumerate(work):
+        a, b = got[k].pose, ref[k].pose
+        assert np.array_equal(a, b), (k, np.abs(a - b).max())
+        s = np.cbrt(np.linalg.det(a[:3, :3]))
+        R = a[:3, :3] / s
+        ang = P.rotation_angle(R)
+        print(f"[serve {k}] sensor {w['sensor']} scale {s * w['scale']:.5f} rot {ang:.2e} "
+              f"trans {np.linalg.norm(a[:3, 3]):.2e}", flush=True)
+        assert abs(s * w["scale"] - 1.0) < 3e-3
+        assert ang < math.radians(0.5) and np.linalg.norm(a[:3, 3]) < 5e-3
+
+
+def test_server_memory_budget_limits_admission(dtsdf, tiny_map):
+    from paper_2301_12796_amd import serve
+    sensors = synth.serving_sensors()
+    work = synth.serving_workload(4, seed=24, device="cuda")
+    big = max(serve.request_bytes(c) for c, _ in sensors)
+    srv = serve.Server(tiny_map, sensors, slots=4, budget_bytes=big)
+    reqs = [serve.Request(k, w["arrival"], w["sensor"], _dev(w["depth"]), w["T_model"],
+                          w["dT0"]) for k, w in enumerate(work)]
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == 4 and srv.peak_bytes <= big
+    with pytest.raises(ValueError):
+        serve.Server(tiny_map, sensors, slots=2, budget_bytes=big - 1)

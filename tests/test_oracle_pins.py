@@ -549,3 +549,34 @@ def test_normal_equations_solution_is_stationary():
     g = J.T @ r
     xi = O.solve_step(H, g)
     assert np.max(np.abs(J.T @ (J @ xi + r))) < 1e-9
+
+
+# ----------------------------------------------------------------------------------------
+# Precision form: stored codes are the nearest float16 / int16 / uint8 values
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sdf_fmt", [1, 2])
+def test_quantised_storage_matches_reference_rounding(sdf_fmt):
+    """A single frontal-plane frame: each stored distance is the round-half-even code of the
+    exact distance (numpy's float16 conversion / numpy.rint), weights are multiples of 1/4."""
+    cam = TINY
+    T = np.eye(4)
+    depth = np.full((cam.height, cam.width), 0.5, np.float32)
+    m = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04, sdf_fmt=sdf_fmt, w_fmt=1, w_carve=0.5))
+    m.integrate(depth, None, cam, T)
+    b = m.export()
+    x = _voxel_positions(b, 0.01)
+    tau = O.f32(0.04)
+    d_true = (0.5 - x[..., 2]) / tau
+    band = (b["w"] > 0) & (np.abs(d_true) <= 1)
+    assert band.sum() > 10000
+    if sdf_fmt == 1:
+        expect = d_true[band].astype(np.float16).astype(np.float64)
+    else:
+        expect = np.rint(d_true[band] * 32767.0) / 32767.0
+    assert np.max(np.abs(b["sdf"][band] - expect)) < 1e-7      # float32 export of the code
+    q = b["w"] * 4
+    assert np.all(q == np.round(q)) and q.max() <= 255
+    # weights are the rounded view cosines (one frame)
+    cosang = x[..., 2] / np.linalg.norm(x, axis=-1)
+    assert np.max(np.abs(b["w"][band] - np.rint(4 * cosang[band]) / 4)) <= 0.25
