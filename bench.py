@@ -235,20 +235,25 @@ def main():
                                           sigma=0.0012, seed=2000 + k, z_max=10.0,
                                           device="cuda")
             om.integrate(f["depth"], f["rgb"], cam, synth.room_pose(k, n))
-        T = poses[30]
-        rows_done, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and rows_done < H:
+        # whole frames of consecutive trajectory poses from pose 30 on, 8 rows at a time,
+        # until cpu_seconds of oracle time have been spent
+        rays_done, t_cpu, pose_k, rows_done = 0, 0.0, 30, 0
+        while t_cpu < args.cpu_seconds:
             vv, uu = np.mgrid[rows_done:rows_done + 8, 0:W]
             pix = np.stack([uu.ravel(), vv.ravel()], 1)
             ta = time.perf_counter()
-            om.render(cam, T, pixels=pix, classify=False)
+            om.render(cam, poses[pose_k % n], pixels=pix, classify=False)
             t_cpu += time.perf_counter() - ta
+            rays_done += pix.shape[0]
             rows_done += 8
-        cpu = dict(value=rows_done * W / t_cpu, unit="rays/s", cores=orc.num_threads(),
+            if rows_done >= H:
+                rows_done, pose_k = 0, pose_k + 1
+        frames_txt = f"{rays_done / (H * W):.2f} frames from trajectory pose 30 on"
+        cpu = dict(value=rays_done / t_cpu, unit="rays/s", cores=orc.num_threads(),
                    kind="oracle",
-                   sample=f"FP64 oracle render (depth+normal+colour) of the first {rows_done} "
-                          f"rows of trajectory pose 30 ({rows_done * W} rays, {t_cpu:.1f} s) "
-                          f"on an oracle map fused from frames {sample_frames}")
+                   sample=f"FP64 oracle render (depth+normal+colour) of {frames_txt} "
+                          f"({rays_done} rays, {t_cpu:.1f} s) on an oracle map fused from "
+                          f"frames {sample_frames}")
         log(f"cpu baseline: {cpu['value']:.0f} rays/s on {cpu['cores']} threads")
 
     line = {

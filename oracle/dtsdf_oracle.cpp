@@ -217,7 +217,8 @@ double round_to(double x, double quantum, double tol, bool* tie) {
 }
 
 // Stored form of a distance: float16 keeps 10 fraction bits in the binade of x (spacing
-// 2^-24 below the smallest normal); int16 keeps q / 32767 with q = round(32767 d).
+// 2^-24 below the smallest normal); int16 keeps the code q = round(32767 d), which decodes
+// as q times the float32 scale 1/32767 (the product rounded to float32).
 double store_sdf(const Params& p, double d, bool* tie) {
   if (p.sdf_fmt == 1) {
     const double ax = std::fabs(d);
@@ -228,7 +229,7 @@ double store_sdf(const Params& p, double d, bool* tie) {
   }
   if (p.sdf_fmt == 2) {
     const double q = std::min(32767.0, std::max(-32767.0, round_to(d * 32767.0, 1.0, 5e-2, tie)));
-    return q / 32767.0;
+    return (double)((float)q * (1.0f / 32767.0f));
   }
   return d;
 }

@@ -137,10 +137,12 @@ struct VoxPacked {
 
 template <>
 struct Vox<1> : VoxPacked {
-  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
-    const uint32_t v = static_cast<const uint32_t*>(g)[i];
+  __host__ __device__ static void decode(uint32_t v, float& s, float& w) {
     s = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu)));
     w = weight(v);
+  }
+  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
+    decode(static_cast<const uint32_t*>(g)[i], s, w);
   }
   __host__ __device__ static void store(void* g, size_t i, float s, float w) {
     static_cast<uint32_t*>(g)[i] =
@@ -150,10 +152,12 @@ struct Vox<1> : VoxPacked {
 
 template <>
 struct Vox<2> : VoxPacked {
-  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
-    const uint32_t v = static_cast<const uint32_t*>(g)[i];
+  __host__ __device__ static void decode(uint32_t v, float& s, float& w) {
     s = (float)(int16_t)(v & 0xFFFFu) * (1.0f / 32767.0f);
     w = weight(v);
+  }
+  __host__ __device__ static void load(const void* g, size_t i, float& s, float& w) {
+    decode(static_cast<const uint32_t*>(g)[i], s, w);
   }
   __host__ __device__ static void store(void* g, size_t i, float s, float w) {
     const float q = fminf(32767.f, fmaxf(-32767.f, rintf(s * 32767.f)));

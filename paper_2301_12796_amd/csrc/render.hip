@@ -57,13 +57,13 @@ struct Trace {
 };
 
 // Ray parameter at which the ray leaves the box [lo, hi) (world units).
-__device__ inline double box_exit(const double o[3], const double r[3], const double ir[3],
-                                  const double lo[3], const double hi[3]) {
+__device__ inline double box_exit(const double o[3], const double ir[3], const double lo[3],
+                                  const double hi[3]) {
   double t = 1e300;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    if (r[ax] > 0.0) t = fmin(t, (hi[ax] - o[ax]) * ir[ax]);
-    else if (r[ax] < 0.0) t = fmin(t, (lo[ax] - o[ax]) * ir[ax]);
+    if (ir[ax] > 0.0) t = fmin(t, (hi[ax] - o[ax]) * ir[ax]);
+    else if (ir[ax] < 0.0) t = fmin(t, (lo[ax] - o[ax]) * ir[ax]);
   }
   return t;
 }
@@ -75,11 +75,40 @@ __device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
 }
 
 // Hash slot of a block via the render index, -1 if absent.
+template <bool TRACE>
 __device__ inline int block_slot(const MapView& m, int bx, int by, int bz, const Trace& tr) {
   const int64_t i = grid_index(m, bx, by, bz);
   const int s = i < 0 ? -1 : m.grid_slot[i];
-  if (tr.slots && s >= 0) tr.slots[s] = 1;
+  if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
   return s;
+}
+
+// The six brick indices of a block (-1: direction not allocated), from its hash entry.
+struct Bricks {
+  int b0, b1, b2, b3, b4, b5;
+  __device__ int get(int d) const {
+    int r = b0;
+    r = d == 1 ? b1 : r;
+    r = d == 2 ? b2 : r;
+    r = d == 3 ? b3 : r;
+    r = d == 4 ? b4 : r;
+    r = d == 5 ? b5 : r;
+    return r;
+  }
+  __device__ uint32_t present() const {
+    return (b0 >= 0 ? 1u : 0u) | (b1 >= 0 ? 2u : 0u) | (b2 >= 0 ? 4u : 0u) |
+           (b3 >= 0 ? 8u : 0u) | (b4 >= 0 ? 16u : 0u) | (b5 >= 0 ? 32u : 0u);
+  }
+};
+
+__device__ inline Bricks load_bricks(const MapView& m, int slot) {
+  Bricks b{-1, -1, -1, -1, -1, -1};
+  if (slot >= 0) {
+    const int2 lo = *reinterpret_cast<const int2*>(&m.entries[slot].brick[0]);
+    const int4 hi = *reinterpret_cast<const int4*>(&m.entries[slot].brick[2]);
+    b = Bricks{lo.x, lo.y, hi.x, hi.y, hi.z, hi.w};
+  }
+  return b;
 }
 
 struct CellPos {
@@ -129,8 +158,30 @@ struct Eval {
   bool color_ok;
 };
 
-template <int F, bool FULL>
-__device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, const float r[3],
+// Loads (sdf, w) of voxels loc and loc + 1 (same x row of one brick).
+template <int F>
+__device__ inline void load_pair(const void* g, uint32_t i, float& s0, float& w0, float& s1,
+                                 float& w1) {
+  if constexpr (F == 0) {
+    struct __attribute__((aligned(8))) F4 { float x, y, z, w; };
+    const F4 v = *reinterpret_cast<const F4*>(static_cast<const float2*>(g) + i);
+    s0 = v.x;
+    w0 = v.y;
+    s1 = v.z;
+    w1 = v.w;
+  } else {
+    struct __attribute__((aligned(4))) U2 { uint32_t x, y; };
+    const U2 v = *reinterpret_cast<const U2*>(static_cast<const uint32_t*>(g) + i);
+    Vox<F>::decode(v.x, s0, w0);
+    Vox<F>::decode(v.y, s1, w1);
+  }
+}
+
+// Combined SDF (and, FULL, normal and colour) in the cell `cp` whose base block has bricks
+// `bb`.  Directions are taken per lane in ascending order of D, so every lane pays only for
+// the directions allocated in its own block.
+template <int F, bool FULL, bool TRACE>
+__device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb, const float r[3],
                           float inv_band, Eval& e, const Trace& tr) {
   e.defined = false;
   e.fallback = false;
@@ -140,56 +191,79 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
     e.rgb[0] = e.rgb[1] = e.rgb[2] = 0.f;
     e.color_ok = false;
   }
-  if (base_slot < 0) return;
+  uint32_t pm = bb.present();
+  if (pm == 0) return;
   const int lx = cp.lo[0], ly = cp.lo[1], lz = cp.lo[2];
-  // hash slots of the blocks the eight corners fall in, indexed by block offset bits
+  // corners leaving the base block: x when lx == 7, y when ly == 7, z when lz == 7
   const int need = (lx == 7 ? 1 : 0) | (ly == 7 ? 2 : 0) | (lz == 7 ? 4 : 0);
-  int nb[8];
-  nb[0] = base_slot;
+  int ns[8];   // hash slots of the blocks at offset o (o & need == o), else -1
+  ns[0] = -1;
 #pragma unroll
   for (int o = 1; o < 8; ++o) {
-    nb[o] = -1;
+    ns[o] = -1;
     if ((o & need) == o)
-      nb[o] = block_slot(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1), cp.bl[2] + ((o >> 2) & 1), tr);
+      ns[o] = block_slot<TRACE>(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1),
+                                cp.bl[2] + ((o >> 2) & 1), tr);
   }
   const float ax = cp.a[0], ay = cp.a[1], az = cp.a[2];
   const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
   const float tw[8] = {bx * by * bz, ax * by * bz, bx * ay * bz, ax * ay * bz,
                        bx * by * az, ax * by * az, bx * ay * az, ax * ay * az};
   const float mr[3] = {-r[0], -r[1], -r[2]};
-  const int32_t* base_br = m.entries[base_slot].brick;
+  // voxel offsets of the pair starts: x0 = min(lx, 6); the pair (x0, x0 + 1) holds corner
+  // x = lx (and x = lx + 1 when lx < 7)
+  const int x0 = lx < 7 ? lx : 6;
+  const int y1 = (ly + 1) & 7, z1 = (lz + 1) & 7;
+  const uint32_t lp[4] = {(uint32_t)(x0 + 8 * ly + 64 * lz), (uint32_t)(x0 + 8 * y1 + 64 * lz),
+                          (uint32_t)(x0 + 8 * ly + 64 * z1), (uint32_t)(x0 + 8 * y1 + 64 * z1)};
   float so = 0.f, sop = 0.f;   // gradient combination weights
   float fo = 0.f, fop = 0.f;   // fallback weights
   bool any = false;
-  // FULL accumulators: normals and colours for both branches
   float ng0 = 0.f, ng1 = 0.f, ng2 = 0.f, nf0 = 0.f, nf1 = 0.f, nf2 = 0.f;
   float cg0 = 0.f, cg1 = 0.f, cg2 = 0.f, cgo = 0.f;     // colour weights of the colour blend
   float cgg0 = 0.f, cgg1 = 0.f, cgg2 = 0.f, cggo = 0.f; // geometric weights, gradient branch
   float cgf0 = 0.f, cgf1 = 0.f, cgf2 = 0.f, cgfo = 0.f; // geometric weights, fallback branch
-#pragma unroll 1
-  for (int d = 0; d < 6; ++d) {
-    const int b0 = base_br[d];
-    if (b0 < 0) continue;
+  for (; pm; pm &= pm - 1) {
+    const int d = __builtin_ctz(pm);
+    const int b0 = bb.get(d);
     int br[8];
     bool ok = true;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int o = c & need;
-      br[c] = b0;
-      if (o) {
-        const int s = nb[o];
-        br[c] = s < 0 ? -1 : m.entries[s].brick[d];
-        ok = ok && br[c] >= 0;
+    for (int c = 0; c < 8; ++c) br[c] = b0;
+    if (need) {
+      // corner c lies in the block at offset c & need
+#pragma unroll
+      for (int o = 1; o < 8; ++o) {
+        if ((o & need) != o) continue;
+        const int bo = ns[o] >= 0 ? m.entries[ns[o]].brick[d] : -1;
+#pragma unroll
+        for (int c = 1; c < 8; ++c)
+          if ((c & o) == o) br[c] = (c & need) == o ? bo : br[c];
       }
+#pragma unroll
+      for (int c = 1; c < 8; ++c) ok = ok && br[c] >= 0;
     }
     if (!ok) continue;
     float sv[8], wv[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
-                      64 * ((lz + ((c >> 2) & 1)) & 7);
-      Vox<F>::load(m.geo, (size_t)br[c] * kVox + loc, sv[c], wv[c]);
-      if (tr.bricks) tr.bricks[br[c]] = 1;
+    for (int q = 0; q < 4; ++q) {
+      // pair q covers corners 2q (x = lx) and 2q + 1 (x = lx + 1) of one y/z row
+      float s0, w0, s1, w1;
+      load_pair<F>(m.geo, (uint32_t)br[2 * q] * kVox + lp[q], s0, w0, s1, w1);
+      if (TRACE && tr.bricks) tr.bricks[br[2 * q]] = 1;
+      if (lx < 7) {
+        sv[2 * q] = s0;
+        wv[2 * q] = w0;
+        sv[2 * q + 1] = s1;
+        wv[2 * q + 1] = w1;
+      } else {
+        sv[2 * q] = s1;
+        wv[2 * q] = w1;
+        // corner x = 0 of the block at +x
+        Vox<F>::load(m.geo, (size_t)br[2 * q + 1] * kVox + (lp[q] - 6), sv[2 * q + 1],
+                     wv[2 * q + 1]);
+        if (TRACE && tr.bricks) tr.bricks[br[2 * q + 1]] = 1;
+      }
     }
     bool wok = true;
 #pragma unroll
@@ -241,7 +315,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
           const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
                           64 * ((lz + ((c >> 2) & 1)) & 7);
           const size_t vi = (size_t)br[c] * kVox + loc;
-          if (tr.color) tr.color[br[c]] = 1;
+          if (TRACE && tr.color) tr.color[br[c]] = 1;
           float w;
           uint32_t code;
           Vox<F>::load_color(m.rgb, m.wc, vi, code, w);
@@ -303,18 +377,28 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, int base_slot, co
   }
 }
 
-// Evaluates the combined SDF at an arbitrary point (refinement, outputs).
-template <int F, bool FULL>
-__device__ void eval_at(const MapView& m, const double x[3], const float r[3], float inv_band,
-                        Eval& e, const Trace& tr) {
-  CellPos cp;
-  locate(m, x, cp);
-  eval_cell<F, FULL>(m, cp, block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), r, inv_band, e, tr);
+// Minimum over the 64 lanes of a wave (every lane must be active).
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
 }
 
-// Renders pixel (u, v) of view `a` (inside the image).
-template <int F>
-__device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v) {
+// Lattice steps a lane may run ahead of the wave's furthest-behind marching lane and still
+// evaluate in the same pass.
+constexpr int kSlack = 8;
+
+// Renders pixel (u, v) of view `a`; every lane of the wave calls it (lanes outside the image
+// pass inside = false and write nothing).
+//
+// Each pass of the outer loop evaluates the combined SDF at most once per lane.  Before it,
+// every lane advances on its own through the cheap steps (jumps over absent space, skips of
+// positive sub-blocks, refinement bookkeeping) until it holds its next evaluation point.  A
+// marching lane then evaluates only if its lattice index is within kSlack of the smallest
+// one in the wave: the 8x8 rays of a tile are then sampled at nearly the same depth, close
+// together in space, so their loads fall on the same bricks and cache lines.
+template <int F, bool TRACE>
+__device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v, bool inside) {
   const size_t i = (size_t)v * a.W + u;
   const size_t HW = (size_t)a.W * a.H;
   const float inv_band = 1.0f / (2.0f * m.theta - 1.5707963267948966f);
@@ -324,7 +408,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   double r[3];
   for (int k = 0; k < 3; ++k) r[k] = a.R[3 * k] * rc[0] + a.R[3 * k + 1] * rc[1] + a.R[3 * k + 2] * rc[2];
   const float rf[3] = {(float)r[0], (float)r[1], (float)r[2]};
-  const double* o = a.t;
+  const double o[3] = {a.t[0], a.t[1], a.t[2]};
   const double t0 = a.z_near / rc[2], tmax = a.z_far / rc[2];
   const double step = m.step;
   const Trace tr{a.trace_bricks, a.trace_color, a.trace_slots};
@@ -333,103 +417,157 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
                         r[2] != 0.0 ? 1.0 / r[2] : 0.0};
   const double inv_step = 1.0 / step;
   const double bw = kB * m.voxel;          // block edge [m]
-  int cb[3] = {0x7fffffff, 0, 0};   // block of the previous lattice sample
-  int cslot = -1;
-  uint8_t cmask = 0;
-  bool prev_def = false, hit = false, refining = false;
+  int cb0 = 0x7fffffff, cb1 = 0, cb2 = 0;  // block of the cached entry
+  Bricks cbr{-1, -1, -1, -1, -1, -1};
+  bool cpresent = false;
+  uint32_t cmask = 0;
+  bool prev_def = false, hit = false, refining = false, done = !inside;
   float prev_f = 0.f, fa = 0.f, fb = 0.f;
   double ta = 0.0, tb = 0.0;
-  long long k = 0, next_k = 0;
+  int k = 0;
   int it = 0, side = 0;
-  // One loop serves the march and the refinement so that the evaluation is inlined once.
+  bool pending = false;   // te holds an evaluation point not evaluated yet
+  double te = 0.0;        // parameter of the pending point
+  bool lattice = false;   // the pending point is lattice point k of a sub-block that may
+                          // hold a crossing
+  int ke = 0;             // lattice index of the pending point
+  int next_k = 0;         // lattice index after the pending point
   for (;;) {
-    double te;            // parameter of the point to evaluate
-    bool lattice = false; // a lattice point of a sub-block that may hold a crossing
-    int eslot;
-    if (!refining) {
+    // ---- advance to the next evaluation point ---------------------------------------
+    for (; !pending && !done;) {
+      if (refining) {
+        if (it >= 24 || !((tb - ta) > 1e-6)) {
+          done = true;
+          break;
+        }
+        double q = 0.5;
+        if ((it & 3) != 3) q = (double)__fdividef(fa, fa - fb);
+        te = ta + (tb - ta) * q;
+        if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
+        pending = true;
+        break;
+      }
       const double tk = t0 + (double)k * step;
-      if (tk > tmax) break;
+      if (tk > tmax) {
+        done = true;
+        break;
+      }
       const double x[3] = {o[0] + tk * r[0], o[1] + tk * r[1], o[2] + tk * r[2]};
       CellPos cp;
       locate(m, x, cp);
-      if (cp.bl[0] != cb[0] || cp.bl[1] != cb[1] || cp.bl[2] != cb[2]) {
-        cb[0] = cp.bl[0];
-        cb[1] = cp.bl[1];
-        cb[2] = cp.bl[2];
-        const int64_t gi = grid_index(m, cb[0], cb[1], cb[2]);
-        cslot = gi < 0 ? -1 : m.grid_slot[gi];
-        cmask = gi < 0 ? 0 : m.grid_mask[gi];
-        if (tr.slots && cslot >= 0) tr.slots[cslot] = 1;
+      if (cp.bl[0] != cb0 || cp.bl[1] != cb1 || cp.bl[2] != cb2) {
+        cb0 = cp.bl[0];
+        cb1 = cp.bl[1];
+        cb2 = cp.bl[2];
+        const int64_t gi = grid_index(m, cb0, cb1, cb2);
+        const int s = gi < 0 ? -1 : m.grid_slot[gi];
+        cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
+        cpresent = s >= 0;
+        if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
+        cbr = load_bricks(m, s);
       }
-      if (cslot < 0) {
-        // absent block: leave the largest empty cell of the hierarchy that contains it
-        const int g[3] = {cb[0] - m.gx0, cb[1] - m.gy0, cb[2] - m.gz0};
+      if (!cpresent) {
+        const int g[3] = {cb0 - m.gx0, cb1 - m.gy0, cb2 - m.gz0};
         const bool inside = g[0] >= 0 && g[1] >= 0 && g[2] >= 0 && g[0] < m.gx && g[1] < m.gy &&
                             g[2] < m.gz;
-        int sh = 4;   // log2 of the cell edge in blocks
+        const int gg[3] = {m.gx0, m.gy0, m.gz0};
+        double texit;
         if (inside) {
+          // absent block: leave the largest empty cell of the hierarchy that contains it
+          int sh = 0;   // log2 of the cell edge in blocks
           const int m1x = (m.gx + 3) >> 2, m1y = (m.gy + 3) >> 2;
           const int m2x = (m.gx + 15) >> 4, m2y = (m.gy + 15) >> 4;
-          if (m.macro2[((int64_t)(g[2] >> 4) * m2y + (g[1] >> 4)) * m2x + (g[0] >> 4)])
-            sh = m.macro1[((int64_t)(g[2] >> 2) * m1y + (g[1] >> 2)) * m1x + (g[0] >> 2)] ? 0 : 2;
-        }
-        double lo[3], hi[3];
-        const int gg[3] = {m.gx0, m.gy0, m.gz0};
+          if (!m.macro2[((int64_t)(g[2] >> 4) * m2y + (g[1] >> 4)) * m2x + (g[0] >> 4)]) sh = 4;
+          else if (!m.macro1[((int64_t)(g[2] >> 2) * m1y + (g[1] >> 2)) * m1x + (g[0] >> 2)]) sh = 2;
+          double lo[3], hi[3];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const int c0 = gg[ax] + ((g[ax] >> sh) << sh);
-          lo[ax] = (double)c0 * bw;
-          hi[ax] = (double)(c0 + (1 << sh)) * bw;
+          for (int ax = 0; ax < 3; ++ax) {
+            const int c0 = gg[ax] + ((g[ax] >> sh) << sh);
+            lo[ax] = (double)c0 * bw;
+            hi[ax] = (double)(c0 + (1 << sh)) * bw;
+          }
+          texit = box_exit(o, ir, lo, hi);
+        } else {
+          // outside the index grid (which holds every block): go to where the ray enters
+          // the grid box, or finish if it never does
+          const int gd[3] = {m.gx, m.gy, m.gz};
+          double tn = -1e300, tf = 1e300;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            const double lo = (double)gg[ax] * bw, hi = (double)(gg[ax] + gd[ax]) * bw;
+            if (ir[ax] != 0.0) {
+              const double t1 = (lo - o[ax]) * ir[ax], t2 = (hi - o[ax]) * ir[ax];
+              tn = fmax(tn, fmin(t1, t2));
+              tf = fmin(tf, fmax(t1, t2));
+            } else if (o[ax] < lo || o[ax] >= hi) {
+              tn = 1e300;
+            }
+          }
+          texit = (tn < tf && tf > tk) ? tn : 1e300;
         }
-        const double texit = box_exit(o, r, ir, lo, hi);
         const double jn = ceil((texit - 1e-6 - t0) * inv_step);
-        const long long j0 = jn > 9e15 ? (long long)9e15 : (long long)jn;
-        ++n_absent;
+        const int j0 = (int)fmin(jn, 1073741824.0);
+        if (TRACE) ++n_absent;
         prev_def = false;
         k = j0 > k + 1 ? j0 : k + 1;
         continue;
       }
       const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
-      if ((cmask >> sub) & 1) {
+      if ((cmask >> sub) & 1u) {
         // positive sub-block: evaluate only its last lattice point
         double lo[3], hi[3];
+        const int cbv[3] = {cb0, cb1, cb2};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const int v0 = cb[ax] * kB + ((sub >> ax) & 1) * 4;
+          const int v0 = cbv[ax] * kB + ((sub >> ax) & 1) * 4;
           lo[ax] = (double)v0 * m.voxel;
           hi[ax] = (double)(v0 + 4) * m.voxel;
         }
-        const double texit = box_exit(o, r, ir, lo, hi);
+        const double texit = box_exit(o, ir, lo, hi);
         const double jn = ceil((texit - 1e-6 - t0) * inv_step);
-        const long long j0 = jn > 9e15 ? (long long)9e15 : (long long)jn;
-        ++n_skip;
-        const long long last = j0 - 1 > k ? j0 - 1 : k;
+        const int j0 = (int)fmin(jn, 1073741824.0);
+        if (TRACE) ++n_skip;
+        const int last = j0 - 1 > k ? j0 - 1 : k;
         te = t0 + (double)last * step;
-        if (te > tmax) break;
+        if (te > tmax) {
+          done = true;
+          break;
+        }
+        lattice = false;
+        ke = last;
         next_k = last + 1;
       } else {
         te = tk;
         lattice = true;
+        ke = k;
         next_k = k + 1;
-        ++n_eval;
+        if (TRACE) ++n_eval;
       }
-      eslot = cslot;
-    } else {
-      if (it >= 24 || !((tb - ta) > 1e-6)) break;
-      te = (it & 3) == 3 ? 0.5 * (ta + tb)
-                         : ta + (tb - ta) * ((double)fa / ((double)fa - (double)fb));
-      if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
-      eslot = -2;
-      ++n_refine;
+      pending = true;
     }
+    // ---- wave-coherent evaluation -------------------------------------------------
+    const int kmin = wave_min(pending && !refining ? ke : 0x7fffffff);
+    if (!__any(pending)) break;
+    if (!pending || (!refining && ke - kmin > kSlack)) continue;
+    pending = false;
     const double x[3] = {o[0] + te * r[0], o[1] + te * r[1], o[2] + te * r[2]};
     CellPos cp;
     locate(m, x, cp);
-    if (eslot == -2 || cp.bl[0] != cb[0] || cp.bl[1] != cb[1] || cp.bl[2] != cb[2])
-      eslot = block_slot(m, cp.bl[0], cp.bl[1], cp.bl[2], tr);
+    if (cp.bl[0] != cb0 || cp.bl[1] != cb1 || cp.bl[2] != cb2) {
+      cb0 = cp.bl[0];
+      cb1 = cp.bl[1];
+      cb2 = cp.bl[2];
+      const int64_t gi = grid_index(m, cb0, cb1, cb2);
+      const int s = gi < 0 ? -1 : m.grid_slot[gi];
+      cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
+      cpresent = s >= 0;
+      if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
+      cbr = load_bricks(m, s);
+    }
     Eval e;
-    eval_cell<F, false>(m, cp, eslot, rf, inv_band, e, tr);
+    eval_cell<F, false, TRACE>(m, cp, cbr, rf, inv_band, e, tr);
     if (refining) {
+      if (TRACE) ++n_refine;
       ++it;
       if (!e.defined || e.f > 0.f) {
         ta = te;
@@ -462,8 +600,11 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   if (hit) {
     const double ts = 0.5 * (ta + tb);
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
+    CellPos cp;
+    locate(m, x, cp);
+    const Bricks bb = load_bricks(m, block_slot<TRACE>(m, cp.bl[0], cp.bl[1], cp.bl[2], tr));
     Eval e;
-    eval_at<F, true>(m, x, rf, inv_band, e, tr);
+    eval_cell<F, true, TRACE>(m, cp, bb, rf, inv_band, e, tr);
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
@@ -479,6 +620,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       }
     }
   }
+  if (!inside) return;
   if (a.depth) a.depth[i] = out_depth;
   if (a.vertex) {
     a.vertex[i] = out_v[0];
@@ -492,7 +634,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   }
   if (a.rgba) reinterpret_cast<uint32_t*>(a.rgba)[i] = out_c;
   if (a.mask) a.mask[i] = hit ? 1 : 0;
-  if (a.trace_counts) {
+  if (TRACE && a.trace_counts) {
     a.trace_counts[4 * i + 0] = n_eval;
     a.trace_counts[4 * i + 1] = n_skip;
     a.trace_counts[4 * i + 2] = n_absent;
@@ -500,7 +642,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   }
 }
 
-template <int F>
+template <int F, bool TRACE>
 __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
   // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
   const int per = (a.tiles + 7) >> 3;
@@ -508,14 +650,13 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
   if (tile >= a.tiles) return;
   const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
   const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
-  if (u >= a.W || v >= a.H) return;
-  render_pixel<F>(m, a, u, v);
+  render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
 }
 
 // Views of different sizes in one persistent launch: every wave takes the next (view, tile)
 // work item from a counter until all are done.  Each pixel is computed exactly as by
 // render_k, so a view's output does not depend on the batch it is rendered in.
-template <int F>
+template <int F, bool TRACE>
 __global__ __launch_bounds__(64) void render_batch_k(MapView m, const RenderArgs* __restrict__ reqs,
                                                      const int32_t* __restrict__ prefix, int n,
                                                      int total, int32_t* counter) {
@@ -534,7 +675,7 @@ __global__ __launch_bounds__(64) void render_batch_k(MapView m, const RenderArgs
     const int tile = item - prefix[lo];
     const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
     const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
-    if (u < a.W && v < a.H) render_pixel<F>(m, a, u, v);
+    render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
   }
 }
 
@@ -580,12 +721,18 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
   if (!m || !fill_args(intr, T, z_near, z_far, out, a)) return DTSDF_E_INVAL;
   const int per = (a.tiles + 7) / 8;
   const dim3 grd(per * 8);
-  if (m->fmt == 0)
-    hipLaunchKernelGGL(render_k<0>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
-  else if (m->fmt == 1)
-    hipLaunchKernelGGL(render_k<1>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
-  else
-    hipLaunchKernelGGL(render_k<2>, grd, dim3(64), 0, (hipStream_t)stream, make_view(m), a);
+  const bool trace = a.trace_bricks || a.trace_color || a.trace_slots || a.trace_counts;
+  const MapView v = make_view(m);
+  hipStream_t st = (hipStream_t)stream;
+  if (trace) {
+    if (m->fmt == 0) hipLaunchKernelGGL((render_k<0, true>), grd, dim3(64), 0, st, v, a);
+    else if (m->fmt == 1) hipLaunchKernelGGL((render_k<1, true>), grd, dim3(64), 0, st, v, a);
+    else hipLaunchKernelGGL((render_k<2, true>), grd, dim3(64), 0, st, v, a);
+  } else {
+    if (m->fmt == 0) hipLaunchKernelGGL((render_k<0, false>), grd, dim3(64), 0, st, v, a);
+    else if (m->fmt == 1) hipLaunchKernelGGL((render_k<1, false>), grd, dim3(64), 0, st, v, a);
+    else hipLaunchKernelGGL((render_k<2, false>), grd, dim3(64), 0, st, v, a);
+  }
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }
@@ -603,10 +750,13 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
   int32_t* prefix = reinterpret_cast<int32_t*>(host.data() + off_prefix);
   RenderArgs* args = reinterpret_cast<RenderArgs*>(host.data() + off_args);
   int64_t total = 0;
+  bool trace = false;
   for (int r = 0; r < n; ++r) {
     if (!fill_args(&reqs[r].intr, reqs[r].T_world_cam, reqs[r].z_near, reqs[r].z_far,
                    &reqs[r].out, args[r]))
       return DTSDF_E_INVAL;
+    const RenderArgs& q = args[r];
+    trace = trace || q.trace_bricks || q.trace_color || q.trace_slots || q.trace_counts;
     prefix[r] = (int32_t)total;
     total += args[r].tiles;
     if (total > (int64_t)1 << 30) return DTSDF_E_INVAL;
@@ -623,12 +773,21 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
     const RenderArgs* da = reinterpret_cast<const RenderArgs*>(dev + off_args);
     const int32_t* dp = reinterpret_cast<const int32_t*>(dev + off_prefix);
     int32_t* ctr = reinterpret_cast<int32_t*>(dev);
-    if (m->fmt == 0)
-      hipLaunchKernelGGL(render_batch_k<0>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
-    else if (m->fmt == 1)
-      hipLaunchKernelGGL(render_batch_k<1>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
-    else
-      hipLaunchKernelGGL(render_batch_k<2>, dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    if (trace) {
+      if (m->fmt == 0)
+        hipLaunchKernelGGL((render_batch_k<0, true>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+      else if (m->fmt == 1)
+        hipLaunchKernelGGL((render_batch_k<1, true>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+      else
+        hipLaunchKernelGGL((render_batch_k<2, true>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    } else {
+      if (m->fmt == 0)
+        hipLaunchKernelGGL((render_batch_k<0, false>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+      else if (m->fmt == 1)
+        hipLaunchKernelGGL((render_batch_k<1, false>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+      else
+        hipLaunchKernelGGL((render_batch_k<2, false>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    }
     if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
   }
   if (hipFreeAsync(dev, st) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;

@@ -426,10 +426,12 @@ def icp_step_batch(requests, stream=None) -> None:
     _check(_lib.icp_step_batch(n, reqs, _stream(stream)), "icp_step_batch")
 
 
-def decode_result(raw: torch.Tensor) -> dict:
+def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:
+    """The dtsdf_icp_result a batched ICP step wrote to device memory."""
     r = _IcpResult.from_buffer_copy(bytes(raw.cpu().numpy()))
-    return dict(xi=np.array(r.xi[:]), error=r.error, inliers=r.inliers, step_norm=r.step_norm,
-                status=r.status)
+    return dict(xi=np.array(r.xi[:dim]), H=np.array(r.H[:dim * dim]).reshape(dim, dim),
+                g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers,
+                step_norm=r.step_norm, status=r.status)
 
 
 def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
@@ -450,7 +452,8 @@ def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
         for _ in range(iters[l]):
             status, T_new, res = icp_step(v, n, cam_l, mv, mn, mm, mcam, T, dim, params, stream)
             if status != OK:
-                log.append(dict(level=l, status="degenerate", inliers=res["inliers"]))
+                log.append(dict(level=l, status="degenerate", inliers=res["inliers"],
+                                err=res["error"]))
                 break
             T = T_new
             log.append(dict(level=l, inliers=res["inliers"], err=res["error"],

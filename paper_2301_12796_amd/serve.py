@@ -41,6 +41,9 @@ class Request:
     admitted: float = math.nan
     finished: float = math.nan
     pose: Optional[np.ndarray] = None
+    error: float = math.nan        # residual sum of squares of the last ICP step
+    inliers: int = 0               # correspondences of the last ICP step
+    H: Optional[np.ndarray] = None # normal matrix of the last ICP step (server only)
 
 
 @dataclasses.dataclass
@@ -212,6 +215,8 @@ class Server:
                 req = s.req
                 req.finished = t
                 req.pose = s.pose.cpu().numpy()
+                res = dtsdf.decode_result(s.result, self.dim)
+                req.error, req.inliers, req.H = float(res["error"]), int(res["inliers"]), res["H"]
                 done.append(req)
                 self.in_use -= s.need
                 s.req = None
@@ -238,10 +243,12 @@ def serve_serial(gmap: dtsdf.Map, sensors: Sequence, requests: Sequence[Request]
             c = dtsdf.level_camera(cam, l)
             o = gmap.render(c, req.T_model, z_near, z_far, outputs=("vertex", "normal", "mask"))
             levels.append((o["vertex"], o["normal"], o["mask"], c))
-        T, _ = dtsdf.icp(req.live_depth, cam, levels, req.dT0, dim=dim, iters=iters,
-                         params=params, min_step=min_step)
+        T, log = dtsdf.icp(req.live_depth, cam, levels, req.dT0, dim=dim, iters=iters,
+                           params=params, min_step=min_step)
         req.finished = time.perf_counter() - t0
         req.pose = T
+        if log:
+            req.error, req.inliers = float(log[-1]["err"]), int(log[-1]["inliers"])
         out.append(req)
     return out
 

@@ -573,7 +573,10 @@ def test_quantised_storage_matches_reference_rounding(sdf_fmt):
     if sdf_fmt == 1:
         expect = d_true[band].astype(np.float16).astype(np.float64)
     else:
-        expect = np.rint(d_true[band] * 32767.0) / 32767.0
+        # the code times the float32 scale 1/32767, product rounded to float32
+        expect = (np.rint(d_true[band] * 32767.0).astype(np.float32) *
+                  np.float32(1.0 / 32767.0)).astype(np.float64)
+        assert np.mean(b["sdf"][band] == expect) > 0.999
     assert np.max(np.abs(b["sdf"][band] - expect)) < 1e-7      # float32 export of the code
     q = b["w"] * 4
     assert np.all(q == np.round(q)) and q.max() <= 255
