@@ -27,6 +27,14 @@
 //                                   w > 0 (+inf if none); sub-block s = sx | sy << 1 | sz << 2
 //   slot_min float[buckets*8]       per hash entry and sub-block: min of sub_min over the
 //                                   block's directions
+//   brick_neg u64[capacity*8]       per brick, word z, bit x + 8 y: the voxel has w > 0 and
+//                                   sdf <= kSkipMin
+//   block_neg u64[buckets*8]        per hash entry: OR of brick_neg over the block's bricks
+//   cell_mask u64[buckets*8]        per hash entry, word z, bit x + 8 y: no corner of the cell
+//                                   based at voxel (x, y, z) (corners in the +x/+y/+z
+//                                   neighbours included) is set in block_neg, so every
+//                                   direction defined there interpolates positive values
+//                                   and the combined SDF is positive wherever defined
 //
 // Render index (updated after every integrate / import): a dense grid over the bounding box
 // of the occupied blocks.  288 GB of HBM make a dense block grid affordable for room- and
@@ -185,6 +193,7 @@ struct MapView {
   const uint8_t* grid_mask;
   const uint8_t* macro1;
   const uint8_t* macro2;
+  const uint64_t* cell_mask;
   int gx0, gy0, gz0;        // grid origin (block coordinates)
   int gx, gy, gz;           // grid dimensions (blocks)
   double voxel, inv_voxel;
@@ -249,6 +258,9 @@ struct dtsdf_map {
   int64_t dropped;
   float* sub_min;
   float* slot_min;
+  uint64_t* brick_neg;
+  uint64_t* block_neg;
+  uint64_t* cell_mask;
   int32_t* grid_slot;
   uint8_t* grid_mask;
   uint8_t* macro1;
@@ -268,9 +280,11 @@ MapView make_view(const dtsdf_map* m);
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Minima of the eight 4^3 sub-blocks of brick `b` over voxels with w > 0 (+inf if none),
-// written to out8[0..7]; called by every thread of a 256-thread workgroup.
+// written to out8[0..7], and the brick's non-positive voxel mask (w > 0, sdf <= kSkipMin;
+// word z, bit x + 8 y) written to neg8[0..7]; called by every thread of a 256-thread
+// workgroup.
 template <int F>
-__device__ inline void brick_sub_min(const void* geo, size_t b, float* out8) {
+__device__ inline void brick_sub_min(const void* geo, size_t b, float* out8, uint64_t* neg8) {
   __shared__ float vals[kVox];
   for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
     float sd, w;
@@ -287,10 +301,13 @@ __device__ inline void brick_sub_min(const void* geo, size_t b, float* out8) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
     if (lane == 0) out8[sb] = v;
+    const int z = 2 * wave + q;
+    const uint64_t bits = __ballot(vals[lane + 64 * z] <= kSkipMin);
+    if (lane == 0) neg8[z] = bits;
   }
   __syncthreads();
 }
-// Recomputes sub_min of every brick in use.
+// Recomputes sub_min and brick_neg of every brick in use.
 dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st);
 // Enqueues the bounding-box reduction into counters[4..9].
 void launch_bbox(dtsdf_map* m, hipStream_t st);

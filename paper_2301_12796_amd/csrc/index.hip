@@ -10,8 +10,10 @@ namespace {
 
 // Sub-block minima of every brick in use; one workgroup per brick.
 template <int F>
-__global__ __launch_bounds__(256) void brick_stats_k(const void* geo, float* sub_min) {
-  brick_sub_min<F>(geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
+__global__ __launch_bounds__(256) void brick_stats_k(const void* geo, float* sub_min,
+                                                     uint64_t* brick_neg) {
+  brick_sub_min<F>(geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8,
+                   brick_neg + (size_t)blockIdx.x * 8);
 }
 
 __device__ inline bool slot_present(const HashEntry& e) {
@@ -151,6 +153,76 @@ __global__ __launch_bounds__(256) void grid_mask_k(const HashEntry* __restrict__
   mask[i] = bits;
 }
 
+// Per entry and slice z: OR of the non-positive voxel masks of the block's bricks.
+__global__ __launch_bounds__(256) void block_neg_k(const HashEntry* __restrict__ e,
+                                                   uint32_t buckets,
+                                                   const uint64_t* __restrict__ brick_neg,
+                                                   uint64_t* block_neg) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (uint32_t)(t >> 3);
+  const int z = (int)(t & 7);
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  uint64_t v = 0;
+  for (int d = 0; d < 6; ++d)
+    if (ent.brick[d] >= 0) v |= brick_neg[(size_t)ent.brick[d] * 8 + z];
+  block_neg[(size_t)s * 8 + z] = v;
+}
+
+// OR of a voxel slice over x and x + 1 (x + 1 of the last column from the +x neighbour's
+// slice `nx`).
+__device__ inline uint64_t or_x(uint64_t w, uint64_t nx) {
+  constexpr uint64_t kCol0 = 0x0101010101010101ull, kCol7 = 0x8080808080808080ull;
+  return w | ((w >> 1) & ~kCol7) | ((nx & kCol0) << 7);
+}
+
+// OR over (x, x + 1) x (y, y + 1) of a slice, given the slices of the +x, +y and +xy blocks.
+__device__ inline uint64_t or_xy(uint64_t w, uint64_t nx, uint64_t ny, uint64_t nxy) {
+  const uint64_t r = or_x(w, nx), ry = or_x(ny, nxy);
+  return r | (r >> 8) | ((ry & 0xFFull) << 56);
+}
+
+// Positive-cell mask of every present block (see cell_mask in dtsdf_internal.hpp): a cell is
+// positive if none of its corners is non-positive in any direction of the block holding it.
+// Absent neighbours hold no values: cells that would need them are undefined in every
+// direction that lacks a corner, so they do not constrain the mask.
+__global__ __launch_bounds__(256) void cell_mask_k(const HashEntry* __restrict__ e,
+                                                   uint32_t buckets, Grid g,
+                                                   const int32_t* __restrict__ slot,
+                                                   const uint64_t* __restrict__ block_neg,
+                                                   uint64_t* cell_mask) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (uint32_t)(t >> 3);
+  const int z = (int)(t & 7);
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  int b[3];
+  unpack_key(ent.key, b[0], b[1], b[2]);
+  // slices z and z + 1 of the blocks at offsets 0, +x, +y, +xy (z + 1 = 8: slice 0 of the
+  // blocks one further in z)
+  uint64_t w[2][4];
+  for (int h = 0; h < 2; ++h) {
+    const int zz = z + h;
+    const int oz = zz >> 3;
+    for (int q = 0; q < 4; ++q) {
+      const int ox = q & 1, oy = q >> 1;
+      int sl = -1;
+      if (ox == 0 && oy == 0 && oz == 0) {
+        sl = (int)s;
+      } else {
+        const int64_t j = g.index(b[0] + ox, b[1] + oy, b[2] + oz);
+        sl = j < 0 ? -1 : slot[j];
+      }
+      w[h][q] = sl < 0 ? 0ull : block_neg[(size_t)sl * 8 + (zz & 7)];
+    }
+  }
+  const uint64_t neg = or_xy(w[0][0], w[0][1], w[0][2], w[0][3]) |
+                       or_xy(w[1][0], w[1][1], w[1][2], w[1][3]);
+  cell_mask[(size_t)s * 8 + z] = ~neg;
+}
+
 __global__ void bbox_reset_k(int32_t* bbox) {
   if (threadIdx.x < 3) bbox[threadIdx.x] = INT_MAX;
   else if (threadIdx.x < 6) bbox[threadIdx.x] = INT_MIN;
@@ -164,11 +236,11 @@ dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st) {
   if (m->n_bricks > 0) {
     const dim3 g((uint32_t)m->n_bricks);
     if (m->fmt == 0)
-      hipLaunchKernelGGL(brick_stats_k<0>, g, dim3(256), 0, st, m->geo, m->sub_min);
+      hipLaunchKernelGGL(brick_stats_k<0>, g, dim3(256), 0, st, m->geo, m->sub_min, m->brick_neg);
     else if (m->fmt == 1)
-      hipLaunchKernelGGL(brick_stats_k<1>, g, dim3(256), 0, st, m->geo, m->sub_min);
+      hipLaunchKernelGGL(brick_stats_k<1>, g, dim3(256), 0, st, m->geo, m->sub_min, m->brick_neg);
     else
-      hipLaunchKernelGGL(brick_stats_k<2>, g, dim3(256), 0, st, m->geo, m->sub_min);
+      hipLaunchKernelGGL(brick_stats_k<2>, g, dim3(256), 0, st, m->geo, m->sub_min, m->brick_neg);
   }
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
@@ -247,6 +319,11 @@ dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st) {
                      m->slot_min);
   hipLaunchKernelGGL(grid_mask_k, grd, dim3(256), 0, st, m->entries, m->buckets, g,
                      m->grid_slot, m->slot_min, m->grid_mask);
+  const dim3 grd8((uint32_t)(((uint64_t)m->buckets * 8 + 255) / 256));
+  hipLaunchKernelGGL(block_neg_k, grd8, dim3(256), 0, st, m->entries, m->buckets, m->brick_neg,
+                     m->block_neg);
+  hipLaunchKernelGGL(cell_mask_k, grd8, dim3(256), 0, st, m->entries, m->buckets, g,
+                     m->grid_slot, m->block_neg, m->cell_mask);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

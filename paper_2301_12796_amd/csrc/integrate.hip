@@ -191,7 +191,8 @@ struct FuseArgs {
 // Voxel-projection fusion (Sec. 3) of one brick per workgroup.  A brick with any updated
 // voxel refreshes its sub-block minima (sdf over voxels with w > 0) for the render index.
 template <int F>
-__global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min) {
+__global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min,
+                                              uint64_t* brick_neg) {
   const int4 key = m.bkey[blockIdx.x];
   const int D = key.w;
   const size_t HW = (size_t)a.in.W * a.in.H;
@@ -285,7 +286,9 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
       }
     }
   }
-  if (__syncthreads_or(upd)) brick_sub_min<F>(m.geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8);
+  if (__syncthreads_or(upd))
+    brick_sub_min<F>(m.geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8,
+                     brick_neg + (size_t)blockIdx.x * 8);
 }
 
 Intr make_intr(const dtsdf_intrinsics* i) {
@@ -388,11 +391,14 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
     FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
     const dim3 grd_b((uint32_t)m->n_bricks);
     if (m->fmt == 0)
-      hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
+      hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
+                         m->brick_neg);
     else if (m->fmt == 1)
-      hipLaunchKernelGGL(fuse_k<1>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
+      hipLaunchKernelGGL(fuse_k<1>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
+                         m->brick_neg);
     else
-      hipLaunchKernelGGL(fuse_k<2>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min);
+      hipLaunchKernelGGL(fuse_k<2>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
+                         m->brick_neg);
   }
   DTSDF_HIP(hipGetLastError());
   dtsdf_status is = launch_index_update(m, st);

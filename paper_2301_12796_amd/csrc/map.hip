@@ -25,6 +25,7 @@ MapView make_view(const dtsdf_map* m) {
   v.grid_mask = m->grid_mask;
   v.macro1 = m->macro1;
   v.macro2 = m->macro2;
+  v.cell_mask = m->cell_mask;
   v.gx0 = m->grid_lo[0];
   v.gy0 = m->grid_lo[1];
   v.gz0 = m->grid_lo[2];
@@ -117,6 +118,9 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->nmap);
   (void)hipFree(m->sub_min);
   (void)hipFree(m->slot_min);
+  (void)hipFree(m->brick_neg);
+  (void)hipFree(m->block_neg);
+  (void)hipFree(m->cell_mask);
   (void)hipFree(m->grid_slot);
   (void)hipFree(m->grid_mask);
   (void)hipFree(m->macro1);
@@ -153,6 +157,7 @@ dtsdf_status zero_pool(dtsdf_map* m) {
   DTSDF_HIP(hipMemset(m->geo, 0, nv * geo_bytes(m->fmt)));
   // 0x7f7f7f7f = 3.4e38: a brick without observed voxels bounds nothing
   DTSDF_HIP(hipMemset(m->sub_min, 0x7f, sizeof(float) * 8 * m->p.brick_capacity));
+  DTSDF_HIP(hipMemset(m->brick_neg, 0, sizeof(uint64_t) * 8 * m->p.brick_capacity));
   if (m->rgb) DTSDF_HIP(hipMemset(m->rgb, 0, nv * sizeof(uint32_t)));
   if (m->wc) DTSDF_HIP(hipMemset(m->wc, 0, nv * sizeof(float)));
   return DTSDF_OK;
@@ -202,7 +207,10 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
             hipMalloc(&m->geo, geo_bytes(m->fmt) * nv) == hipSuccess &&
             hipMalloc(&m->counters, sizeof(int32_t) * 16) == hipSuccess &&
             hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
-            hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess;
+            hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess &&
+            hipMalloc(&m->brick_neg, sizeof(uint64_t) * 8 * p->brick_capacity) == hipSuccess &&
+            hipMalloc(&m->block_neg, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess &&
+            hipMalloc(&m->cell_mask, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess;
   if (ok && p->with_color) {
     ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess;
     if (ok && m->fmt == 0) ok = hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
@@ -249,8 +257,9 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   out->dropped = m->dropped;
   size_t nv = (size_t)m->p.brick_capacity * kVox;
   out->device_bytes = (int64_t)(sizeof(HashEntry) * m->buckets + sizeof(uint32_t) * m->buckets +
-                                (sizeof(int4) + 8 * sizeof(float)) * m->p.brick_capacity +
-                                8 * sizeof(float) * m->buckets +
+                                (sizeof(int4) + 8 * sizeof(float) + 8 * sizeof(uint64_t)) *
+                                    m->p.brick_capacity +
+                                (8 * sizeof(float) + 16 * sizeof(uint64_t)) * m->buckets +
                                 geo_bytes(m->fmt) * nv +
                                 (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
                                 (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap);

@@ -20,7 +20,8 @@
 //     gradient-free fallback W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight), both summed in
 //     one pass over the directions;
 //   * hit: first k >= 1 with f(t_{k-1}) > 0 >= f(t_k), both defined; the bracket is refined
-//     with the Illinois variant of regula falsi (every fourth step a bisection), undefined
+//     with the Illinois variant of regula falsi (a bisection after any step that does not
+//     halve the bracket) to 1e-6 m, undefined
 //     points counting as free space; outputs are evaluated at the bracket end inside the
 //     surface.
 #include <algorithm>
@@ -83,32 +84,28 @@ __device__ inline int block_slot(const MapView& m, int bx, int by, int bz, const
   return s;
 }
 
-// The six brick indices of a block (-1: direction not allocated), from its hash entry.
-struct Bricks {
-  int b0, b1, b2, b3, b4, b5;
-  __device__ int get(int d) const {
-    int r = b0;
-    r = d == 1 ? b1 : r;
-    r = d == 2 ? b2 : r;
-    r = d == 3 ? b3 : r;
-    r = d == 4 ? b4 : r;
-    r = d == 5 ? b5 : r;
-    return r;
-  }
-  __device__ uint32_t present() const {
-    return (b0 >= 0 ? 1u : 0u) | (b1 >= 0 ? 2u : 0u) | (b2 >= 0 ? 4u : 0u) |
-           (b3 >= 0 ? 8u : 0u) | (b4 >= 0 ? 16u : 0u) | (b5 >= 0 ? 32u : 0u);
-  }
-};
-
-__device__ inline Bricks load_bricks(const MapView& m, int slot) {
-  Bricks b{-1, -1, -1, -1, -1, -1};
+// The six brick indices of a block (-1: direction not allocated), from its hash entry, kept
+// in LDS at row[d * 64] (one column per lane, so that the per-lane direction index selects
+// a row without a dynamically indexed private array); returns the present-direction mask.
+__device__ inline uint32_t load_bricks(const MapView& m, int slot, int* row) {
+  int b[6] = {-1, -1, -1, -1, -1, -1};
   if (slot >= 0) {
     const int2 lo = *reinterpret_cast<const int2*>(&m.entries[slot].brick[0]);
     const int4 hi = *reinterpret_cast<const int4*>(&m.entries[slot].brick[2]);
-    b = Bricks{lo.x, lo.y, hi.x, hi.y, hi.z, hi.w};
+    b[0] = lo.x;
+    b[1] = lo.y;
+    b[2] = hi.x;
+    b[3] = hi.y;
+    b[4] = hi.z;
+    b[5] = hi.w;
   }
-  return b;
+  uint32_t pm = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    row[d * 64] = b[d];
+    pm |= b[d] >= 0 ? 1u << d : 0u;
+  }
+  return pm;
 }
 
 struct CellPos {
@@ -158,30 +155,12 @@ struct Eval {
   bool color_ok;
 };
 
-// Loads (sdf, w) of voxels loc and loc + 1 (same x row of one brick).
-template <int F>
-__device__ inline void load_pair(const void* g, uint32_t i, float& s0, float& w0, float& s1,
-                                 float& w1) {
-  if constexpr (F == 0) {
-    struct __attribute__((aligned(8))) F4 { float x, y, z, w; };
-    const F4 v = *reinterpret_cast<const F4*>(static_cast<const float2*>(g) + i);
-    s0 = v.x;
-    w0 = v.y;
-    s1 = v.z;
-    w1 = v.w;
-  } else {
-    struct __attribute__((aligned(4))) U2 { uint32_t x, y; };
-    const U2 v = *reinterpret_cast<const U2*>(static_cast<const uint32_t*>(g) + i);
-    Vox<F>::decode(v.x, s0, w0);
-    Vox<F>::decode(v.y, s1, w1);
-  }
-}
-
 // Combined SDF (and, FULL, normal and colour) in the cell `cp` whose base block has bricks
 // `bb`.  Directions are taken per lane in ascending order of D, so every lane pays only for
 // the directions allocated in its own block.
 template <int F, bool FULL, bool TRACE>
-__device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb, const float r[3],
+__device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, const int* brow,
+                          const float r[3],
                           float inv_band, Eval& e, const Trace& tr) {
   e.defined = false;
   e.fallback = false;
@@ -191,31 +170,37 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb,
     e.rgb[0] = e.rgb[1] = e.rgb[2] = 0.f;
     e.color_ok = false;
   }
-  uint32_t pm = bb.present();
   if (pm == 0) return;
   const int lx = cp.lo[0], ly = cp.lo[1], lz = cp.lo[2];
   // corners leaving the base block: x when lx == 7, y when ly == 7, z when lz == 7
   const int need = (lx == 7 ? 1 : 0) | (ly == 7 ? 2 : 0) | (lz == 7 ? 4 : 0);
-  int ns[8];   // hash slots of the blocks at offset o (o & need == o), else -1
-  ns[0] = -1;
+  // hash slots of the blocks at offset o (o & need == o), else -1.  Every load is issued
+  // unconditionally (absent ones read cell 0) so that they overlap instead of queueing
+  // behind one another.
+  int ns[8];
 #pragma unroll
-  for (int o = 1; o < 8; ++o) {
-    ns[o] = -1;
-    if ((o & need) == o)
-      ns[o] = block_slot<TRACE>(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1),
-                                cp.bl[2] + ((o >> 2) & 1), tr);
+  for (int o = 0; o < 8; ++o) ns[o] = -1;
+  if (need) {
+#pragma unroll
+    for (int o = 1; o < 8; ++o) {
+      const int64_t gi = grid_index(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1),
+                                    cp.bl[2] + ((o >> 2) & 1));
+      const bool use = (o & need) == o && gi >= 0;
+      const int sl = m.grid_slot[use ? gi : 0];
+      ns[o] = use ? sl : -1;
+      if (TRACE && tr.slots && ns[o] >= 0) tr.slots[ns[o]] = 1;
+    }
   }
   const float ax = cp.a[0], ay = cp.a[1], az = cp.a[2];
   const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
   const float tw[8] = {bx * by * bz, ax * by * bz, bx * ay * bz, ax * ay * bz,
                        bx * by * az, ax * by * az, bx * ay * az, ax * ay * az};
   const float mr[3] = {-r[0], -r[1], -r[2]};
-  // voxel offsets of the pair starts: x0 = min(lx, 6); the pair (x0, x0 + 1) holds corner
-  // x = lx (and x = lx + 1 when lx < 7)
-  const int x0 = lx < 7 ? lx : 6;
+  // offsets of the four corner rows (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1) within
+  // their bricks
   const int y1 = (ly + 1) & 7, z1 = (lz + 1) & 7;
-  const uint32_t lp[4] = {(uint32_t)(x0 + 8 * ly + 64 * lz), (uint32_t)(x0 + 8 * y1 + 64 * lz),
-                          (uint32_t)(x0 + 8 * ly + 64 * z1), (uint32_t)(x0 + 8 * y1 + 64 * z1)};
+  const uint32_t rq[4] = {(uint32_t)(8 * ly + 64 * lz), (uint32_t)(8 * y1 + 64 * lz),
+                          (uint32_t)(8 * ly + 64 * z1), (uint32_t)(8 * y1 + 64 * z1)};
   float so = 0.f, sop = 0.f;   // gradient combination weights
   float fo = 0.f, fop = 0.f;   // fallback weights
   bool any = false;
@@ -225,51 +210,52 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb,
   float cgf0 = 0.f, cgf1 = 0.f, cgf2 = 0.f, cgfo = 0.f; // geometric weights, fallback branch
   for (; pm; pm &= pm - 1) {
     const int d = __builtin_ctz(pm);
-    const int b0 = bb.get(d);
+    const int b0 = brow[d * 64];
     int br[8];
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < 8; ++c) br[c] = b0;
     if (need) {
       // corner c lies in the block at offset c & need
+      int nbr[8];
+#pragma unroll
+      for (int o = 1; o < 8; ++o) {
+        const int so = ns[o];
+        const int bo = m.entries[so >= 0 ? so : 0].brick[d];
+        nbr[o] = so >= 0 ? bo : -1;
+      }
 #pragma unroll
       for (int o = 1; o < 8; ++o) {
         if ((o & need) != o) continue;
-        const int bo = ns[o] >= 0 ? m.entries[ns[o]].brick[d] : -1;
 #pragma unroll
         for (int c = 1; c < 8; ++c)
-          if ((c & o) == o) br[c] = (c & need) == o ? bo : br[c];
+          if ((c & o) == o) br[c] = (c & need) == o ? nbr[o] : br[c];
       }
 #pragma unroll
       for (int c = 1; c < 8; ++c) ok = ok && br[c] >= 0;
     }
     if (!ok) continue;
+    // corner 2q at x = lx and corner 2q + 1 at x = lx + 1 of row q (x = 0 of the brick at +x
+    // when lx == 7); all eight loads are issued before any is used
     float sv[8], wv[8];
+    const bool xin = lx < 7;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      // pair q covers corners 2q (x = lx) and 2q + 1 (x = lx + 1) of one y/z row
-      float s0, w0, s1, w1;
-      load_pair<F>(m.geo, (uint32_t)br[2 * q] * kVox + lp[q], s0, w0, s1, w1);
-      if (TRACE && tr.bricks) tr.bricks[br[2 * q]] = 1;
-      if (lx < 7) {
-        sv[2 * q] = s0;
-        wv[2 * q] = w0;
-        sv[2 * q + 1] = s1;
-        wv[2 * q + 1] = w1;
-      } else {
-        sv[2 * q] = s1;
-        wv[2 * q] = w1;
-        // corner x = 0 of the block at +x
-        Vox<F>::load(m.geo, (size_t)br[2 * q + 1] * kVox + (lp[q] - 6), sv[2 * q + 1],
-                     wv[2 * q + 1]);
-        if (TRACE && tr.bricks) tr.bricks[br[2 * q + 1]] = 1;
+      const uint32_t ia = (uint32_t)br[2 * q] * kVox + rq[q] + (uint32_t)lx;
+      const uint32_t ib = xin ? ia + 1u : (uint32_t)br[2 * q + 1] * kVox + rq[q];
+      Vox<F>::load(m.geo, ia, sv[2 * q], wv[2 * q]);
+      Vox<F>::load(m.geo, ib, sv[2 * q + 1], wv[2 * q + 1]);
+      if (TRACE && tr.bricks) {
+        tr.bricks[br[2 * q]] = 1;
+        tr.bricks[br[2 * q + 1]] = 1;
       }
     }
+    // defined only if every corner has W > 0; evaluated regardless (then dropped by
+    // zero weights) so that the distance loads need not wait for the weight test
     bool wok = true;
 #pragma unroll
     for (int c = 0; c < 8; ++c) wok = wok && (wv[c] > 0.f);
-    if (!wok) continue;
-    any = true;
+    any = any || wok;
     float phi = 0.f, W = 0.f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -294,9 +280,11 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb,
       wdc = wd * fmaxf(0.f, n0 * mr[0] + n1 * mr[1] + n2 * mr[2]);
       om = wdc * W;
     }
+    om = wok ? om : 0.f;
+    wdc = wok ? wdc : 0.f;
     so += om;
     sop += om * phi;
-    const float fb = W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d));
+    const float fb = wok ? W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
     fo += fb;
     fop += fb * phi;
     if (FULL) {
@@ -307,7 +295,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb,
       nf0 += d < 2 ? sfb : 0.f;
       nf1 += (d >> 1) == 1 ? sfb : 0.f;
       nf2 += d >= 4 ? sfb : 0.f;
-      if (m.with_color) {
+      if (m.with_color && wok) {
         float wsum = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
         bool cok = true;
 #pragma unroll
@@ -377,26 +365,19 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, const Bricks& bb,
   }
 }
 
-// Minimum over the 64 lanes of a wave (every lane must be active).
-__device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-// Lattice steps a lane may run ahead of the wave's furthest-behind marching lane and still
-// evaluate in the same pass.
-constexpr int kSlack = 8;
+// Refinement of the bracket of a crossing: Illinois regula falsi, with a bisection after
+// every step that does not halve the bracket, until the bracket is shorter than kRefineTol
+// (metres along the ray) or after kRefineMaxIter evaluations.
+constexpr double kRefineTol = 1e-6;
+constexpr int kRefineMaxIter = 24;
 
 // Renders pixel (u, v) of view `a`; every lane of the wave calls it (lanes outside the image
 // pass inside = false and write nothing).
 //
-// Each pass of the outer loop evaluates the combined SDF at most once per lane.  Before it,
-// every lane advances on its own through the cheap steps (jumps over absent space, skips of
-// positive sub-blocks, refinement bookkeeping) until it holds its next evaluation point.  A
-// marching lane then evaluates only if its lattice index is within kSlack of the smallest
-// one in the wave: the 8x8 rays of a tile are then sampled at nearly the same depth, close
-// together in space, so their loads fall on the same bricks and cache lines.
+// Each pass of the outer loop evaluates the combined SDF once per lane.  Before it, every
+// lane advances on its own through the cheap steps (jumps over absent space and positive
+// sub-blocks, steps through positive cells, refinement bookkeeping) until it holds its next
+// evaluation point, so that the lanes of a wave evaluate together instead of taking turns.
 template <int F, bool TRACE>
 __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v, bool inside) {
   const size_t i = (size_t)v * a.W + u;
@@ -418,30 +399,37 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   const double inv_step = 1.0 / step;
   const double bw = kB * m.voxel;          // block edge [m]
   int cb0 = 0x7fffffff, cb1 = 0, cb2 = 0;  // block of the cached entry
-  Bricks cbr{-1, -1, -1, -1, -1, -1};
+  // brick indices of each lane's current block, direction d at [d * 64 + lane]
+  __shared__ int brick_rows[6 * 64];
+  int* const brow = brick_rows + (threadIdx.x & 63);
+  uint32_t cpm = 0;                // present directions of the current block
   bool cpresent = false;
   uint32_t cmask = 0;
+  int pos_last = -1;              // last lattice point of the current positive run
+  // positive-cell words of each lane's current block, slice z at [z * 64 + lane]
+  __shared__ uint64_t cell_words[8 * 64];
+  const int lane = (int)(threadIdx.x & 63);
   bool prev_def = false, hit = false, refining = false, done = !inside;
   float prev_f = 0.f, fa = 0.f, fb = 0.f;
   double ta = 0.0, tb = 0.0;
   int k = 0;
   int it = 0, side = 0;
+  bool bisect = false;
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
   bool lattice = false;   // the pending point is lattice point k of a sub-block that may
                           // hold a crossing
-  int ke = 0;             // lattice index of the pending point
   int next_k = 0;         // lattice index after the pending point
   for (;;) {
     // ---- advance to the next evaluation point ---------------------------------------
     for (; !pending && !done;) {
       if (refining) {
-        if (it >= 24 || !((tb - ta) > 1e-6)) {
+        if (it >= kRefineMaxIter || !((tb - ta) > kRefineTol)) {
           done = true;
           break;
         }
         double q = 0.5;
-        if ((it & 3) != 3) q = (double)__fdividef(fa, fa - fb);
+        if (!bisect) q = (double)__fdividef(fa, fa - fb);
         te = ta + (tb - ta) * q;
         if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
         pending = true;
@@ -464,7 +452,18 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
         cpresent = s >= 0;
         if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
-        cbr = load_bricks(m, s);
+        cpm = load_bricks(m, s, brow);
+        if (s >= 0) {
+          const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
+          uint4 q[4];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) q[h] = cw[h];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
+            cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
+          }
+        }
       }
       if (!cpresent) {
         const int g[3] = {cb0 - m.gx0, cb1 - m.gy0, cb2 - m.gz0};
@@ -509,12 +508,14 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         const int j0 = (int)fmin(jn, 1073741824.0);
         if (TRACE) ++n_absent;
         prev_def = false;
+        pos_last = -1;
         k = j0 > k + 1 ? j0 : k + 1;
         continue;
       }
       const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
       if ((cmask >> sub) & 1u) {
-        // positive sub-block: evaluate only its last lattice point
+        // positive sub-block: no crossing can end in it; jump past it, remembering its last
+        // lattice point (evaluated only if the point after it is)
         double lo[3], hi[3];
         const int cbv[3] = {cb0, cb1, cb2};
 #pragma unroll
@@ -526,29 +527,39 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         const double texit = box_exit(o, ir, lo, hi);
         const double jn = ceil((texit - 1e-6 - t0) * inv_step);
         const int j0 = (int)fmin(jn, 1073741824.0);
-        if (TRACE) ++n_skip;
         const int last = j0 - 1 > k ? j0 - 1 : k;
-        te = t0 + (double)last * step;
-        if (te > tmax) {
+        if (t0 + (double)last * step > tmax) {
           done = true;
           break;
         }
+        pos_last = last;
+        k = last + 1;
+        continue;
+      }
+      if ((cell_words[cp.lo[2] * 64 + lane] >> (cp.lo[0] + 8 * cp.lo[1])) & 1ull) {
+        // positive cell: the same, one lattice point
+        pos_last = k;
+        k = k + 1;
+        continue;
+      }
+      if (pos_last == k - 1 && k >= 1) {
+        // the crossing test at k needs the value at k - 1, skipped so far
+        te = t0 + (double)(k - 1) * step;
         lattice = false;
-        ke = last;
-        next_k = last + 1;
+        next_k = k;
+        pos_last = -1;
+        if (TRACE) ++n_skip;
       } else {
         te = tk;
         lattice = true;
-        ke = k;
         next_k = k + 1;
         if (TRACE) ++n_eval;
       }
       pending = true;
     }
-    // ---- wave-coherent evaluation -------------------------------------------------
-    const int kmin = wave_min(pending && !refining ? ke : 0x7fffffff);
+    // ---- evaluate -----------------------------------------------------------------
     if (!__any(pending)) break;
-    if (!pending || (!refining && ke - kmin > kSlack)) continue;
+    if (!pending) continue;
     pending = false;
     const double x[3] = {o[0] + te * r[0], o[1] + te * r[1], o[2] + te * r[2]};
     CellPos cp;
@@ -562,13 +573,25 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
       cpresent = s >= 0;
       if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
-      cbr = load_bricks(m, s);
+      cpm = load_bricks(m, s, brow);
+      if (s >= 0) {
+        const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
+        uint4 q[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) q[h] = cw[h];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
+          cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
+        }
+      }
     }
     Eval e;
-    eval_cell<F, false, TRACE>(m, cp, cbr, rf, inv_band, e, tr);
+    eval_cell<F, false, TRACE>(m, cp, cpm, brow, rf, inv_band, e, tr);
     if (refining) {
       if (TRACE) ++n_refine;
       ++it;
+      const double len = tb - ta;
       if (!e.defined || e.f > 0.f) {
         ta = te;
         if (e.defined) fa = e.f;
@@ -580,6 +603,8 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         if (side == -1) fa *= 0.5f;
         side = -1;
       }
+      // safeguard: a step that did not halve the bracket is followed by a bisection
+      bisect = !bisect && (tb - ta) > 0.5 * len;
       continue;
     }
     if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
@@ -602,9 +627,9 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
     CellPos cp;
     locate(m, x, cp);
-    const Bricks bb = load_bricks(m, block_slot<TRACE>(m, cp.bl[0], cp.bl[1], cp.bl[2], tr));
+    const uint32_t pm = load_bricks(m, block_slot<TRACE>(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), brow);
     Eval e;
-    eval_cell<F, true, TRACE>(m, cp, bb, rf, inv_band, e, tr);
+    eval_cell<F, true, TRACE>(m, cp, pm, brow, rf, inv_band, e, tr);
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
