@@ -96,9 +96,9 @@ typedef struct {
  * render sets to 1 the entry of every brick whose (sdf, w) a sample read (trace_bricks,
  * brick_capacity bytes), every brick whose colour an output read (trace_color, same size)
  * and every hash entry whose brick indices a lookup read (trace_slots, hash_buckets bytes);
- * trace_counts (4 int32 per pixel) receives the number of full evaluations in blocks that
- * may hold a crossing, evaluations at the end of skipped positive blocks, jumps over absent
- * blocks, and refinement evaluations. */
+ * trace_counts (4 int32 per pixel) receives the number of evaluations at lattice points that
+ * may end a crossing, evaluations of a skipped positive point that precedes such a point,
+ * jumps over absent space, and refinement evaluations. */
 typedef struct {
   float* depth;   /* H*W camera-frame z of the hit, 0 where nothing was hit */
   float* vertex;  /* 3*H*W planes, camera-frame hit point */

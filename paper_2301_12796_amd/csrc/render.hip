@@ -20,8 +20,8 @@
 //     gradient-free fallback W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight), both summed in
 //     one pass over the directions;
 //   * hit: first k >= 1 with f(t_{k-1}) > 0 >= f(t_k), both defined; the bracket is refined
-//     with the Illinois variant of regula falsi (a bisection after any step that does not
-//     halve the bracket) to 1e-6 m, undefined
+//     with the Illinois variant of regula falsi (every fourth step a bisection) to 1e-6 m,
+//     undefined
 //     points counting as free space; outputs are evaluated at the bracket end inside the
 //     surface.
 #include <algorithm>
@@ -365,9 +365,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   }
 }
 
-// Refinement of the bracket of a crossing: Illinois regula falsi, with a bisection after
-// every step that does not halve the bracket, until the bracket is shorter than kRefineTol
-// (metres along the ray) or after kRefineMaxIter evaluations.
+// Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step a
+// bisection, until the bracket is shorter than kRefineTol (metres along the ray) or after
+// kRefineMaxIter evaluations.
 constexpr double kRefineTol = 1e-6;
 constexpr int kRefineMaxIter = 24;
 
@@ -414,7 +414,6 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   double ta = 0.0, tb = 0.0;
   int k = 0;
   int it = 0, side = 0;
-  bool bisect = false;
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
   bool lattice = false;   // the pending point is lattice point k of a sub-block that may
@@ -429,7 +428,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
           break;
         }
         double q = 0.5;
-        if (!bisect) q = (double)__fdividef(fa, fa - fb);
+        if ((it & 3) != 3) q = (double)__fdividef(fa, fa - fb);
         te = ta + (tb - ta) * q;
         if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
         pending = true;
@@ -591,7 +590,6 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     if (refining) {
       if (TRACE) ++n_refine;
       ++it;
-      const double len = tb - ta;
       if (!e.defined || e.f > 0.f) {
         ta = te;
         if (e.defined) fa = e.f;
@@ -603,8 +601,6 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         if (side == -1) fa *= 0.5f;
         side = -1;
       }
-      // safeguard: a step that did not halve the bracket is followed by a bisection
-      bisect = !bisect && (tb - ta) > 0.5 * len;
       continue;
     }
     if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
