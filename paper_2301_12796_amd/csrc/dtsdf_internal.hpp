@@ -27,14 +27,19 @@
 //                                   w > 0 (+inf if none); sub-block s = sx | sy << 1 | sz << 2
 //   slot_min float[buckets*8]       per hash entry and sub-block: min of sub_min over the
 //                                   block's directions
-//   brick_neg u64[capacity*8]       per brick, word z, bit x + 8 y: the voxel has w > 0 and
-//                                   sdf <= kSkipMin
+//   brick_neg u64[capacity*16]      per brick, word z, bit x + 8 y: the voxel has w > 0 and
+//                                   sdf <= kSkipMin; words 8 + z: the voxel has w > 0
 //   block_neg u64[buckets*8]        per hash entry: OR of brick_neg over the block's bricks
 //   cell_mask u64[buckets*8]        per hash entry, word z, bit x + 8 y: no corner of the cell
 //                                   based at voxel (x, y, z) (corners in the +x/+y/+z
 //                                   neighbours included) is set in block_neg, so every
 //                                   direction defined there interpolates positive values
 //                                   and the combined SDF is positive wherever defined
+//   dir_groups u8[buckets*64]       per hash entry and 2x2x2 group of cells (byte
+//                                   gx + 4 gy + 16 gz): bit D set if direction D has all 8
+//                                   corners observed (w > 0) at some cell of the group; a
+//                                   direction whose bit is clear is undefined at every cell
+//                                   of the group and contributes nothing there
 //
 // Render index (updated after every integrate / import): a dense grid over the bounding box
 // of the occupied blocks.  288 GB of HBM make a dense block grid affordable for room- and
@@ -194,6 +199,7 @@ struct MapView {
   const uint8_t* macro1;
   const uint8_t* macro2;
   const uint64_t* cell_mask;
+  const uint8_t* dir_groups;
   int gx0, gy0, gz0;        // grid origin (block coordinates)
   int gx, gy, gz;           // grid dimensions (blocks)
   double voxel, inv_voxel;
@@ -261,6 +267,7 @@ struct dtsdf_map {
   uint64_t* brick_neg;
   uint64_t* block_neg;
   uint64_t* cell_mask;
+  uint8_t* dir_groups;
   int32_t* grid_slot;
   uint8_t* grid_mask;
   uint8_t* macro1;
@@ -280,11 +287,11 @@ MapView make_view(const dtsdf_map* m);
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Minima of the eight 4^3 sub-blocks of brick `b` over voxels with w > 0 (+inf if none),
-// written to out8[0..7], and the brick's non-positive voxel mask (w > 0, sdf <= kSkipMin;
-// word z, bit x + 8 y) written to neg8[0..7]; called by every thread of a 256-thread
-// workgroup.
+// written to out8[0..7], the brick's non-positive voxel mask (w > 0, sdf <= kSkipMin;
+// word z, bit x + 8 y) written to bits16[0..7] and its observed voxel mask (w > 0) to
+// bits16[8..15]; called by every thread of a 256-thread workgroup.
 template <int F>
-__device__ inline void brick_sub_min(const void* geo, size_t b, float* out8, uint64_t* neg8) {
+__device__ inline void brick_sub_min(const void* geo, size_t b, float* out8, uint64_t* bits16) {
   __shared__ float vals[kVox];
   for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
     float sd, w;
@@ -302,8 +309,13 @@ __device__ inline void brick_sub_min(const void* geo, size_t b, float* out8, uin
     for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
     if (lane == 0) out8[sb] = v;
     const int z = 2 * wave + q;
-    const uint64_t bits = __ballot(vals[lane + 64 * z] <= kSkipMin);
-    if (lane == 0) neg8[z] = bits;
+    const float vz = vals[lane + 64 * z];
+    const uint64_t neg = __ballot(vz <= kSkipMin);
+    const uint64_t obs = __ballot(vz < INFINITY);
+    if (lane == 0) {
+      bits16[z] = neg;
+      bits16[8 + z] = obs;
+    }
   }
   __syncthreads();
 }

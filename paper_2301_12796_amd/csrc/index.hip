@@ -13,7 +13,7 @@ template <int F>
 __global__ __launch_bounds__(256) void brick_stats_k(const void* geo, float* sub_min,
                                                      uint64_t* brick_neg) {
   brick_sub_min<F>(geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8,
-                   brick_neg + (size_t)blockIdx.x * 8);
+                   brick_neg + (size_t)blockIdx.x * 16);
 }
 
 __device__ inline bool slot_present(const HashEntry& e) {
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void block_neg_k(const HashEntry* __restrict__
   if (!slot_present(ent)) return;
   uint64_t v = 0;
   for (int d = 0; d < 6; ++d)
-    if (ent.brick[d] >= 0) v |= brick_neg[(size_t)ent.brick[d] * 8 + z];
+    if (ent.brick[d] >= 0) v |= brick_neg[(size_t)ent.brick[d] * 16 + z];
   block_neg[(size_t)s * 8 + z] = v;
 }
 
@@ -221,6 +221,70 @@ __global__ __launch_bounds__(256) void cell_mask_k(const HashEntry* __restrict__
   const uint64_t neg = or_xy(w[0][0], w[0][1], w[0][2], w[0][3]) |
                        or_xy(w[1][0], w[1][1], w[1][2], w[1][3]);
   cell_mask[(size_t)s * 8 + z] = ~neg;
+}
+
+// AND of a voxel slice over x and x + 1, and over (x, x + 1) x (y, y + 1) (see or_x).
+__device__ inline uint64_t and_x(uint64_t w, uint64_t nx) {
+  constexpr uint64_t kCol0 = 0x0101010101010101ull, kCol7 = 0x8080808080808080ull;
+  return w & (((w >> 1) & ~kCol7) | ((nx & kCol0) << 7));
+}
+
+__device__ inline uint64_t and_xy(uint64_t w, uint64_t nx, uint64_t ny, uint64_t nxy) {
+  const uint64_t r = and_x(w, nx), ry = and_x(ny, nxy);
+  return r & ((r >> 8) | ((ry & 0xFFull) << 56));
+}
+
+// Defined-direction bytes of every present block (see dir_groups in dtsdf_internal.hpp):
+// one thread per block and slab of cells z = 2 gz, 2 gz + 1, writing the 16 group bytes of
+// that slab.  A cell is defined in D if its 8 corners (in the +x/+y/+z neighbours where it
+// leaves the block) are observed in D.
+__global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict__ e,
+                                                    uint32_t buckets, Grid g,
+                                                    const int32_t* __restrict__ slot,
+                                                    const uint64_t* __restrict__ brick_bits,
+                                                    uint8_t* dir_groups) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (uint32_t)(t >> 2);
+  const int gz = (int)(t & 3);
+  if (s >= buckets) return;
+  const HashEntry ent = e[s];
+  if (!slot_present(ent)) return;
+  int b[3];
+  unpack_key(ent.key, b[0], b[1], b[2]);
+  // slots of the blocks at offsets (ox, oy, oz), index ox + 2 oy + 4 oz
+  int nb[8];
+  nb[0] = (int)s;
+  for (int o = 1; o < 8; ++o) {
+    const int64_t j = g.index(b[0] + (o & 1), b[1] + ((o >> 1) & 1), b[2] + ((o >> 2) & 1));
+    nb[o] = j < 0 ? -1 : slot[j];
+  }
+  uint32_t bytes[4] = {0u, 0u, 0u, 0u};   // 16 group bytes of the slab
+  for (int d = 0; d < 6; ++d) {
+    if (ent.brick[d] < 0) continue;
+    int br[8];
+    for (int o = 0; o < 8; ++o) br[o] = nb[o] < 0 ? -1 : e[nb[o]].brick[d];
+    // observed words of slices 2 gz .. 2 gz + 2 for the blocks at (0,0), (+x), (+y), (+xy)
+    uint64_t w[3][4];
+    for (int h = 0; h < 3; ++h) {
+      const int zz = 2 * gz + h;
+      const int oz = zz >> 3;
+      for (int q = 0; q < 4; ++q) {
+        const int bb = br[q + 4 * oz];
+        w[h][q] = bb < 0 ? 0ull : brick_bits[(size_t)bb * 16 + 8 + (zz & 7)];
+      }
+    }
+    const uint64_t c0 = and_xy(w[0][0], w[0][1], w[0][2], w[0][3]) &
+                        and_xy(w[1][0], w[1][1], w[1][2], w[1][3]);
+    const uint64_t c1 = and_xy(w[1][0], w[1][1], w[1][2], w[1][3]) &
+                        and_xy(w[2][0], w[2][1], w[2][2], w[2][3]);
+    const uint64_t u = c0 | c1;
+    for (int gy = 0; gy < 4; ++gy)
+      for (int gx = 0; gx < 4; ++gx)
+        if ((u >> (2 * gx + 16 * gy)) & 0x0303ull)
+          bytes[gy] |= (1u << d) << (8 * gx);
+  }
+  uint32_t* out = reinterpret_cast<uint32_t*>(dir_groups + (size_t)s * 64 + 16 * gz);
+  for (int gy = 0; gy < 4; ++gy) out[gy] = bytes[gy];
 }
 
 __global__ void bbox_reset_k(int32_t* bbox) {
@@ -324,6 +388,9 @@ dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st) {
                      m->block_neg);
   hipLaunchKernelGGL(cell_mask_k, grd8, dim3(256), 0, st, m->entries, m->buckets, g,
                      m->grid_slot, m->block_neg, m->cell_mask);
+  const dim3 grd4((uint32_t)(((uint64_t)m->buckets * 4 + 255) / 256));
+  hipLaunchKernelGGL(dir_groups_k, grd4, dim3(256), 0, st, m->entries, m->buckets, g,
+                     m->grid_slot, m->brick_neg, m->dir_groups);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

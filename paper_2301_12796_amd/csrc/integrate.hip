@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
   }
   if (__syncthreads_or(upd))
     brick_sub_min<F>(m.geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8,
-                     brick_neg + (size_t)blockIdx.x * 8);
+                     brick_neg + (size_t)blockIdx.x * 16);
 }
 
 Intr make_intr(const dtsdf_intrinsics* i) {

@@ -26,6 +26,7 @@ MapView make_view(const dtsdf_map* m) {
   v.macro1 = m->macro1;
   v.macro2 = m->macro2;
   v.cell_mask = m->cell_mask;
+  v.dir_groups = m->dir_groups;
   v.gx0 = m->grid_lo[0];
   v.gy0 = m->grid_lo[1];
   v.gz0 = m->grid_lo[2];
@@ -121,6 +122,7 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->brick_neg);
   (void)hipFree(m->block_neg);
   (void)hipFree(m->cell_mask);
+  (void)hipFree(m->dir_groups);
   (void)hipFree(m->grid_slot);
   (void)hipFree(m->grid_mask);
   (void)hipFree(m->macro1);
@@ -157,7 +159,7 @@ dtsdf_status zero_pool(dtsdf_map* m) {
   DTSDF_HIP(hipMemset(m->geo, 0, nv * geo_bytes(m->fmt)));
   // 0x7f7f7f7f = 3.4e38: a brick without observed voxels bounds nothing
   DTSDF_HIP(hipMemset(m->sub_min, 0x7f, sizeof(float) * 8 * m->p.brick_capacity));
-  DTSDF_HIP(hipMemset(m->brick_neg, 0, sizeof(uint64_t) * 8 * m->p.brick_capacity));
+  DTSDF_HIP(hipMemset(m->brick_neg, 0, sizeof(uint64_t) * 16 * m->p.brick_capacity));
   if (m->rgb) DTSDF_HIP(hipMemset(m->rgb, 0, nv * sizeof(uint32_t)));
   if (m->wc) DTSDF_HIP(hipMemset(m->wc, 0, nv * sizeof(float)));
   return DTSDF_OK;
@@ -208,9 +210,10 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
             hipMalloc(&m->counters, sizeof(int32_t) * 16) == hipSuccess &&
             hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess &&
-            hipMalloc(&m->brick_neg, sizeof(uint64_t) * 8 * p->brick_capacity) == hipSuccess &&
+            hipMalloc(&m->brick_neg, sizeof(uint64_t) * 16 * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->block_neg, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess &&
-            hipMalloc(&m->cell_mask, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess;
+            hipMalloc(&m->cell_mask, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess &&
+            hipMalloc(&m->dir_groups, 64 * (size_t)m->buckets) == hipSuccess;
   if (ok && p->with_color) {
     ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess;
     if (ok && m->fmt == 0) ok = hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
@@ -257,9 +260,9 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   out->dropped = m->dropped;
   size_t nv = (size_t)m->p.brick_capacity * kVox;
   out->device_bytes = (int64_t)(sizeof(HashEntry) * m->buckets + sizeof(uint32_t) * m->buckets +
-                                (sizeof(int4) + 8 * sizeof(float) + 8 * sizeof(uint64_t)) *
+                                (sizeof(int4) + 8 * sizeof(float) + 16 * sizeof(uint64_t)) *
                                     m->p.brick_capacity +
-                                (8 * sizeof(float) + 16 * sizeof(uint64_t)) * m->buckets +
+                                (8 * sizeof(float) + 16 * sizeof(uint64_t) + 64) * m->buckets +
                                 geo_bytes(m->fmt) * nv +
                                 (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
                                 (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap);

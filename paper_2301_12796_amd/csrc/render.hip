@@ -158,13 +158,20 @@ struct Eval {
 // Combined SDF (and, FULL, normal and colour) in the cell `cp` whose base block has bricks
 // `bb`.  Directions are taken per lane in ascending order of D, so every lane pays only for
 // the directions allocated in its own block.
-template <int F, bool FULL, bool TRACE>
+// NP points of one cell are evaluated together: point 0 at cp, point j > 0 at the
+// fractional position pa[j - 1] of the same cell; the corner values are loaded once.
+template <int F, bool FULL, bool TRACE, int NP>
 __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, const int* brow,
-                          const float r[3],
-                          float inv_band, Eval& e, const Trace& tr) {
-  e.defined = false;
-  e.fallback = false;
-  e.f = 0.f;
+                          const float r[3], float inv_band, Eval* ev, const Trace& tr,
+                          const float (*pa)[3] = nullptr) {
+  static_assert(NP == 1 || !FULL, "outputs are evaluated one point at a time");
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    ev[j].defined = false;
+    ev[j].fallback = false;
+    ev[j].f = 0.f;
+  }
+  Eval& e = ev[0];
   if (FULL) {
     e.n[0] = e.n[1] = e.n[2] = 0.f;
     e.rgb[0] = e.rgb[1] = e.rgb[2] = 0.f;
@@ -195,6 +202,11 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   const float bx = 1.f - ax, by = 1.f - ay, bz = 1.f - az;
   const float tw[8] = {bx * by * bz, ax * by * bz, bx * ay * bz, ax * ay * bz,
                        bx * by * az, ax * by * az, bx * ay * az, ax * ay * az};
+  // further points: combination sums of each (the first point's sums are so .. fop)
+  float so2[NP > 1 ? NP - 1 : 1], sop2[NP > 1 ? NP - 1 : 1], fo2[NP > 1 ? NP - 1 : 1],
+      fop2[NP > 1 ? NP - 1 : 1];
+#pragma unroll
+  for (int j = 0; j + 1 < NP; ++j) so2[j] = sop2[j] = fo2[j] = fop2[j] = 0.f;
   const float mr[3] = {-r[0], -r[1], -r[2]};
   // offsets of the four corner rows (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1) within
   // their bricks
@@ -287,6 +299,39 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
     const float fb = wok ? W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
     fo += fb;
     fop += fb * phi;
+#pragma unroll
+    for (int j = 0; j + 1 < NP; ++j) {
+      const float px = pa[j][0], py = pa[j][1], pz = pa[j][2];
+      const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
+      const float uw[8] = {qx * qy * qz, px * qy * qz, qx * py * qz, px * py * qz,
+                           qx * qy * pz, px * qy * pz, qx * py * pz, px * py * pz};
+      float phj = 0.f, Wj = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        phj = fmaf(uw[c], sv[c], phj);
+        Wj = fmaf(uw[c], wv[c], Wj);
+      }
+      const float hx = (sv[1] - sv[0]) * qy * qz + (sv[3] - sv[2]) * py * qz +
+                       (sv[5] - sv[4]) * qy * pz + (sv[7] - sv[6]) * py * pz;
+      const float hy = (sv[2] - sv[0]) * qx * qz + (sv[3] - sv[1]) * px * qz +
+                       (sv[6] - sv[4]) * qx * pz + (sv[7] - sv[5]) * px * pz;
+      const float hz = (sv[4] - sv[0]) * qx * qy + (sv[5] - sv[1]) * px * qy +
+                       (sv[6] - sv[2]) * qx * py + (sv[7] - sv[3]) * px * py;
+      const float hl = sqrtf(hx * hx + hy * hy + hz * hz);
+      float omj = 0.f;
+      if (hl >= 1e-6f) {
+        const float il = 1.f / hl;
+        const float m0 = hx * il, m1 = hy * il, m2 = hz * il;
+        const float wd = w_dir_fast(axis_dot(m0, m1, m2, d), m.theta, inv_band);
+        omj = wd * fmaxf(0.f, m0 * mr[0] + m1 * mr[1] + m2 * mr[2]) * Wj;
+      }
+      omj = wok ? omj : 0.f;
+      so2[j] += omj;
+      sop2[j] += omj * phj;
+      const float fbj = wok ? Wj * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
+      fo2[j] += fbj;
+      fop2[j] += fbj * phj;
+    }
     if (FULL) {
       ng0 += om * n0;
       ng1 += om * n1;
@@ -343,6 +388,20 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
       e.f = fop / fo;
     }
   }
+#pragma unroll
+  for (int j = 0; j + 1 < NP; ++j) {
+    Eval& ej = ev[j + 1];
+    if (so2[j] > 0.f) {
+      ej.defined = true;
+      ej.f = sop2[j] / so2[j];
+    } else {
+      ej.fallback = true;
+      if (fo2[j] > 0.f) {
+        ej.defined = true;
+        ej.f = fop2[j] / fo2[j];
+      }
+    }
+  }
   if (FULL) {
     e.n[0] = e.fallback ? nf0 : ng0;
     e.n[1] = e.fallback ? nf1 : ng1;
@@ -369,6 +428,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
 // bisection, until the bracket is shorter than kRefineTol (metres along the ray) or after
 // kRefineMaxIter evaluations.
 constexpr double kRefineTol = 1e-6;
+constexpr double kRefinePair = 0.45 * kRefineTol;
 constexpr int kRefineMaxIter = 24;
 
 // Renders pixel (u, v) of view `a`; every lane of the wave calls it (lanes outside the image
@@ -406,8 +466,10 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   bool cpresent = false;
   uint32_t cmask = 0;
   int pos_last = -1;              // last lattice point of the current positive run
-  // positive-cell words of each lane's current block, slice z at [z * 64 + lane]
+  // positive-cell words of each lane's current block, slice z at [z * 64 + lane], and its
+  // defined-direction group bytes, bytes 8 w .. 8 w + 7 at [w * 64 + lane]
   __shared__ uint64_t cell_words[8 * 64];
+  __shared__ uint64_t group_words[8 * 64];
   const int lane = (int)(threadIdx.x & 63);
   bool prev_def = false, hit = false, refining = false, done = !inside;
   float prev_f = 0.f, fa = 0.f, fb = 0.f;
@@ -416,6 +478,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   int it = 0, side = 0;
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
+  double te2 = 0.0;       // refinement: second point of the pending pair
   bool lattice = false;   // the pending point is lattice point k of a sub-block that may
                           // hold a crossing
   int next_k = 0;         // lattice index after the pending point
@@ -429,8 +492,12 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         }
         double q = 0.5;
         if ((it & 3) != 3) q = (double)__fdividef(fa, fa - fb);
-        te = ta + (tb - ta) * q;
-        if (!(te > ta && te < tb)) te = 0.5 * (ta + tb);
+        double tc = ta + (tb - ta) * q;
+        if (!(tc > ta && tc < tb)) tc = 0.5 * (ta + tb);
+        // the estimate is evaluated as a pair straddling it by kRefinePair: when the estimate
+        // is that close to the root the pair is the final bracket
+        te = fmax(tc - kRefinePair, 0.5 * (ta + tc));
+        te2 = fmin(tc + kRefinePair, 0.5 * (tc + tb));
         pending = true;
         break;
       }
@@ -454,13 +521,19 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         cpm = load_bricks(m, s, brow);
         if (s >= 0) {
           const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
-          uint4 q[4];
+          const uint4* gw = reinterpret_cast<const uint4*>(m.dir_groups + (size_t)s * 64);
+          uint4 q[4], qg[4];
 #pragma unroll
-          for (int h = 0; h < 4; ++h) q[h] = cw[h];
+          for (int h = 0; h < 4; ++h) {
+            q[h] = cw[h];
+            qg[h] = gw[h];
+          }
 #pragma unroll
           for (int h = 0; h < 4; ++h) {
             cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
             cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
+            group_words[(2 * h) * 64 + lane] = (uint64_t)qg[h].x | ((uint64_t)qg[h].y << 32);
+            group_words[(2 * h + 1) * 64 + lane] = (uint64_t)qg[h].z | ((uint64_t)qg[h].w << 32);
           }
         }
       }
@@ -575,24 +648,57 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       cpm = load_bricks(m, s, brow);
       if (s >= 0) {
         const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
-        uint4 q[4];
+        const uint4* gw = reinterpret_cast<const uint4*>(m.dir_groups + (size_t)s * 64);
+        uint4 q[4], qg[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) q[h] = cw[h];
+        for (int h = 0; h < 4; ++h) {
+          q[h] = cw[h];
+          qg[h] = gw[h];
+        }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
           cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
           cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
+          group_words[(2 * h) * 64 + lane] = (uint64_t)qg[h].x | ((uint64_t)qg[h].y << 32);
+          group_words[(2 * h + 1) * 64 + lane] = (uint64_t)qg[h].z | ((uint64_t)qg[h].w << 32);
         }
       }
     }
-    Eval e;
-    eval_cell<F, false, TRACE>(m, cp, cpm, brow, rf, inv_band, e, tr);
+    // a refinement pair is evaluated together when both points share the cell
+    bool pair = false;
+    float pa1[1][3] = {{cp.a[0], cp.a[1], cp.a[2]}};
+    if (refining) {
+      const double x2[3] = {o[0] + te2 * r[0], o[1] + te2 * r[1], o[2] + te2 * r[2]};
+      CellPos cp2;
+      locate(m, x2, cp2);
+      pair = cp2.bl[0] == cp.bl[0] && cp2.bl[1] == cp.bl[1] && cp2.bl[2] == cp.bl[2] &&
+             cp2.lo[0] == cp.lo[0] && cp2.lo[1] == cp.lo[1] && cp2.lo[2] == cp.lo[2];
+      pa1[0][0] = cp2.a[0];
+      pa1[0][1] = cp2.a[1];
+      pa1[0][2] = cp2.a[2];
+    }
+    Eval ev[2];
+    // only the directions defined somewhere in the cell's 2x2x2 group can contribute
+    const int grp = (cp.lo[0] >> 1) + 4 * (cp.lo[1] >> 1) + 16 * (cp.lo[2] >> 1);
+    const uint32_t gdef =
+        (uint32_t)(group_words[(grp >> 3) * 64 + lane] >> (8 * (grp & 7))) & 0x3Fu;
+    eval_cell<F, false, TRACE, 2>(m, cp, cpm & gdef, brow, rf, inv_band, ev, tr, pa1);
+    const Eval& e = ev[0];
     if (refining) {
       if (TRACE) ++n_refine;
       ++it;
-      if (!e.defined || e.f > 0.f) {
+      const bool pos1 = !e.defined || e.f > 0.f;
+      const bool pos2 = !ev[1].defined || ev[1].f > 0.f;
+      if (pos1 && pair && !pos2) {
+        // the pair straddles the root: final bracket
         ta = te;
+        tb = te2;
         if (e.defined) fa = e.f;
+        fb = ev[1].f;
+      } else if (pos1) {
+        ta = pair ? te2 : te;
+        const Eval& ea = pair ? ev[1] : e;
+        if (ea.defined) fa = ea.f;
         if (side == 1) fb *= 0.5f;
         side = 1;
       } else {
@@ -625,7 +731,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     locate(m, x, cp);
     const uint32_t pm = load_bricks(m, block_slot<TRACE>(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), brow);
     Eval e;
-    eval_cell<F, true, TRACE>(m, cp, pm, brow, rf, inv_band, e, tr);
+    eval_cell<F, true, TRACE, 1>(m, cp, pm, brow, rf, inv_band, &e, tr);
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
@@ -663,8 +769,10 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   }
 }
 
+// Three waves per SIMD (at most 168 VGPRs): the march is latency-bound and needs the waves.
 template <int F, bool TRACE>
-__global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_k(
+    MapView m, RenderArgs a) {
   // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
   const int per = (a.tiles + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
@@ -678,7 +786,7 @@ __global__ __launch_bounds__(64) void render_k(MapView m, RenderArgs a) {
 // work item from a counter until all are done.  Each pixel is computed exactly as by
 // render_k, so a view's output does not depend on the batch it is rendered in.
 template <int F, bool TRACE>
-__global__ __launch_bounds__(64) void render_batch_k(MapView m, const RenderArgs* __restrict__ reqs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_batch_k(MapView m, const RenderArgs* __restrict__ reqs,
                                                      const int32_t* __restrict__ prefix, int n,
                                                      int total, int32_t* counter) {
   for (;;) {
