@@ -9,7 +9,10 @@ colour per direction).  One step renders depth + normal + colour at all 300 traj
 Printed as one JSON line, with the roofline of the render kernel (algorithmic bytes per
 launch from the traced brick / bucket sets, divided by the launch duration measured with HIP
 events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
-Separately timed and reported beside it: integration ms/frame and three-level ICP ms/frame.
+Separately timed and reported beside it: integration ms/frame, three-level ICP ms/frame, the
+precision forms (f16 / i16 distance with u8 weights, fused from the same frames: rays/s and
+depth against the plain render) and the serving workload (p50/p99 latency and capacity of
+the continuous-batching server against serial calls).
 """
 from __future__ import annotations
 
@@ -72,6 +75,7 @@ def main():
     ap.add_argument("--no-icp", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="leading requests of the 120/s Poisson stream that are served")
     ap.add_argument("--copy-probe", action="store_true",
@@ -101,12 +105,14 @@ def main():
     t_gen = 0.0
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     integ_ms = 0.0
+    frames_dev = []          # kept for the precision-form maps
     for k in range(n):
         t = time.time()
         f = synth.scenes.render_frame(sc, cam, synth.room_pose(k, n), noise="quadratic",
                                       sigma=0.0012, seed=2000 + k, z_max=10.0, device="cuda")
         depth = torch.from_numpy(f["depth"]).to(dev)
         rgb = torch.from_numpy(f["rgb"]).to(dev)
+        frames_dev.append((depth, rgb))
         t_gen += time.time() - t
         ev0.record(stream)
         gm.integrate(depth, rgb, cam, synth.room_pose(k, n))
@@ -191,6 +197,50 @@ def main():
     mean_launch_s = float(launch_ms.mean()) * 1e-3
     achieved = bytes_per_launch / mean_launch_s / 1e9
     traffic = read_traffic(os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip"))
+
+    # ---- precision forms: the same frames fused into f16 / i16 maps ---------------------
+    precision = None
+    if not args.no_precision:
+        precision = {}
+        ref = gm.render(cam, poses[150], outputs=("depth", "mask"))
+        ref_d = ref["depth"].cpu().numpy()
+        for name, sf in (("f16", dtsdf.SDF_F16), ("i16", dtsdf.SDF_I16)):
+            pm_ = dtsdf.Map(dtsdf.Params(voxel_size=0.005, truncation=0.02,
+                                         brick_capacity=1 << 20, hash_buckets=1 << 21,
+                                         sdf_fmt=sf, w_fmt=dtsdf.W_U8))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for k, (d_, c_) in enumerate(frames_dev):
+                pm_.integrate(d_, c_, cam, poses[k])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            for T in poses[:10]:
+                pm_.render(cam, T, out=out)
+            torch.cuda.synchronize()
+            pevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    for _ in poses]
+            for (a_, b_), T in zip(pevs, poses):
+                a_.record(stream)
+                pm_.render(cam, T, out=out)
+                b_.record(stream)
+            torch.cuda.synchronize()
+            pms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in pevs]))
+            q = pm_.render(cam, poses[150], outputs=("depth", "mask"))
+            qd = q["depth"].cpu().numpy()
+            both = (ref_d > 0) & (qd > 0)
+            dz = np.abs(qd - ref_d)[both]
+            precision[name] = dict(
+                rays_per_s=H * W / (pms * 1e-3), mean_launch_ms=pms,
+                integrate_ms_per_frame=e0.elapsed_time(e1) / n,
+                device_bytes=pm_.info()["device_bytes"],
+                vs_plain_depth_median_m=float(np.median(dz)),
+                vs_plain_depth_over_1mm=float(np.mean(dz > 1e-3)),
+                vs_plain_depth_over_1cm=float(np.mean(dz > 1e-2)),
+                vs_plain_mask_mismatch=float(((ref_d > 0) != (qd > 0)).mean()))
+            log(f"precision {name}: {H * W / (pms * 1e-3) / 1e6:.1f} M rays/s, depth vs plain "
+                f"median {np.median(dz):.2e} m, over 1 cm {np.mean(dz > 1e-2):.4f}")
+            del pm_
+            torch.cuda.empty_cache()
 
     # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
     icp_ms = None
@@ -297,6 +347,7 @@ def main():
         "samples_per_wave_max": per_wave_max,
         "input_generation_s": t_gen,
         "serving": serving,
+        "precision": precision,
     }
     print(json.dumps(line), flush=True)
 

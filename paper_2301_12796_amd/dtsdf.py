@@ -401,29 +401,37 @@ class IcpRequest:
     min_step: float = 0.0
 
 
-def icp_step_batch(requests, stream=None) -> None:
-    n = len(requests)
-    reqs = (_IcpReq * n)()
-    for i, q in enumerate(requests):
-        Hl, Wl = int(q.live_cam.height), int(q.live_cam.width)
-        Hm, Wm = int(q.model_cam.height), int(q.model_cam.width)
-        reqs[i].live = _Image(_dev_ptr(q.live_vertex, torch.float32, 3 * Hl * Wl),
-                              _dev_ptr(q.live_normal, torch.float32, 3 * Hl * Wl), None,
-                              _intr(q.live_cam))
-        reqs[i].model = _Image(_dev_ptr(q.model_vertex, torch.float32, 3 * Hm * Wm),
-                               _dev_ptr(q.model_normal, torch.float32, 3 * Hm * Wm),
-                               _dev_ptr(q.model_mask, torch.uint8, Hm * Wm)
-                               if q.model_mask is not None else None, _intr(q.model_cam))
-        reqs[i].dim = q.dim
-        p = q.params
-        reqs[i].params = _IcpParams(p.max_dist, p.max_angle_deg, p.weight, p.z_min,
-                                    p.min_inliers_per_dim, int(p.compensated))
-        reqs[i].pose = _dev_ptr(q.pose, torch.float64, 16)
-        reqs[i].active = _dev_ptr(q.active, torch.int32, 1) if q.active is not None else None
-        reqs[i].min_step = q.min_step
-        reqs[i].result = _dev_ptr(q.result, torch.uint8, ICP_RESULT_BYTES) \
-            if q.result is not None else None
+def icp_request_struct(q: IcpRequest) -> _IcpReq:
+    """The C descriptor of one batched ICP request (kept by callers that reuse it)."""
+    r = _IcpReq()
+    Hl, Wl = int(q.live_cam.height), int(q.live_cam.width)
+    Hm, Wm = int(q.model_cam.height), int(q.model_cam.width)
+    r.live = _Image(_dev_ptr(q.live_vertex, torch.float32, 3 * Hl * Wl),
+                    _dev_ptr(q.live_normal, torch.float32, 3 * Hl * Wl), None, _intr(q.live_cam))
+    r.model = _Image(_dev_ptr(q.model_vertex, torch.float32, 3 * Hm * Wm),
+                     _dev_ptr(q.model_normal, torch.float32, 3 * Hm * Wm),
+                     _dev_ptr(q.model_mask, torch.uint8, Hm * Wm)
+                     if q.model_mask is not None else None, _intr(q.model_cam))
+    r.dim = q.dim
+    p = q.params
+    r.params = _IcpParams(p.max_dist, p.max_angle_deg, p.weight, p.z_min,
+                          p.min_inliers_per_dim, int(p.compensated))
+    r.pose = _dev_ptr(q.pose, torch.float64, 16)
+    r.active = _dev_ptr(q.active, torch.int32, 1) if q.active is not None else None
+    r.min_step = q.min_step
+    r.result = _dev_ptr(q.result, torch.uint8, ICP_RESULT_BYTES) if q.result is not None else None
+    return r
+
+
+def icp_step_batch_structs(structs, stream=None) -> None:
+    """icp_step_batch over prebuilt descriptors (see icp_request_struct)."""
+    n = len(structs)
+    reqs = (_IcpReq * n)(*structs)
     _check(_lib.icp_step_batch(n, reqs, _stream(stream)), "icp_step_batch")
+
+
+def icp_step_batch(requests, stream=None) -> None:
+    icp_step_batch_structs([icp_request_struct(q) for q in requests], stream)
 
 
 def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:

@@ -14,6 +14,11 @@ leaves after its last iteration of the finest level; its slot and memory are fre
 next round.  Requests that arrive while others are on the device therefore join the running
 batch (continuous batching, not a queue in front of a serial worker), and each request's
 result is bitwise the same as when it is served alone.
+
+The iteration schedule is fixed (convergence only clears a device flag), so the host never
+waits for a round: it enqueues rounds back to back and, for each request that leaves, a
+copy of its pose into pinned memory followed by an event; the request is complete when the
+host sees that event.
 """
 from __future__ import annotations
 
@@ -57,6 +62,8 @@ class _Slot:
     level: int = 0
     it: int = 0
     need: int = 0
+    c_req: object = None           # C descriptor of the current level's ICP request
+    stage: Optional[torch.Tensor] = None   # pinned initial pose being copied in
 
 
 def request_bytes(cam, levels: int = 3) -> int:
@@ -162,12 +169,33 @@ class Server:
         """Serves `requests` (sorted by arrival).  With realtime, arrivals follow the wall
         clock from the start of the call; otherwise every request is available at once."""
         queue = deque(sorted(requests, key=lambda r: r.arrival))
+        stream = self.stream if self.stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(stream):
+            return self._run(queue, stream, realtime)
+
+    def _run(self, queue, stream, realtime: bool) -> List[Request]:
         done: List[Request] = []
+        leaving = []        # (event, request, pinned pose, pinned result)
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0   # noqa: E731
-        while queue or any(s.req is not None for s in self._slots):
+        while queue or leaving or any(s.req is not None for s in self._slots):
+            # requests whose last round has completed on the device
+            if leaving:
+                still = []
+                for item in leaving:
+                    ev, req, hp, hr = item
+                    if ev.query():
+                        req.finished = now()
+                        req.pose = hp.numpy().copy()
+                        res = dtsdf.decode_result(hr, self.dim)
+                        req.error, req.inliers, req.H = (float(res["error"]),
+                                                         int(res["inliers"]), res["H"])
+                        done.append(req)
+                    else:
+                        still.append(item)
+                leaving = still
             # admission: arrived requests, free slot, memory budget
-            new_views, newly = [], []
+            new_views = []
             t = now()
             for s in self._slots:
                 if not queue or (realtime and queue[0].arrival > t):
@@ -184,40 +212,40 @@ class Server:
                 self.in_use += need
                 self.peak_bytes = max(self.peak_bytes, self.in_use)
                 self._prepare_live(s, req)
-                s.pose.copy_(torch.from_numpy(np.ascontiguousarray(req.dT0, np.float64)))
+                s.stage = torch.from_numpy(np.ascontiguousarray(req.dT0, np.float64)).pin_memory()
+                s.pose.copy_(s.stage, non_blocking=True)
                 s.active.fill_(1)
                 new_views += self._views(s, req)
-                newly.append(s)
+                s.c_req = dtsdf.icp_request_struct(self._icp_request(s))
             busy = [s for s in self._slots if s.req is not None]
             if not busy:
-                # idle until the next arrival
-                if queue and realtime:
+                if not leaving and queue and realtime:
                     time.sleep(max(0.0, min(queue[0].arrival - now(), 0.002)))
                 continue
             if new_views:
                 self.map.render_batch(new_views, stream=self.stream)
-            dtsdf.icp_step_batch([self._icp_request(s) for s in busy], stream=self.stream)
+            dtsdf.icp_step_batch_structs([s.c_req for s in busy], stream=self.stream)
             self.batch_sizes.append(len(busy))
             self.rounds += 1
-            finished = []
             for s in busy:
                 s.it += 1
-                if s.it >= self.iters[s.level]:
-                    s.level -= 1
-                    s.it = 0
-                    if s.level < 0:
-                        finished.append(s)
-                    else:
-                        s.active.fill_(1)          # the next level starts afresh
-            torch.cuda.synchronize()
-            t = now()
-            for s in finished:
-                req = s.req
-                req.finished = t
-                req.pose = s.pose.cpu().numpy()
-                res = dtsdf.decode_result(s.result, self.dim)
-                req.error, req.inliers, req.H = float(res["error"]), int(res["inliers"]), res["H"]
-                done.append(req)
+                if s.it < self.iters[s.level]:
+                    continue
+                s.level -= 1
+                s.it = 0
+                if s.level >= 0:
+                    s.active.fill_(1)          # the next level starts afresh
+                    s.c_req = dtsdf.icp_request_struct(self._icp_request(s))
+                    continue
+                # last round of this request: copy its pose and result out, then free the
+                # slot (later work on the slot's buffers is ordered after these copies)
+                hp = torch.empty((4, 4), dtype=torch.float64, pin_memory=True)
+                hr = torch.empty(dtsdf.ICP_RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+                hp.copy_(s.pose, non_blocking=True)
+                hr.copy_(s.result, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                leaving.append((ev, s.req, hp, hr))
                 self.in_use -= s.need
                 s.req = None
         return done
