@@ -624,6 +624,7 @@ Sample eval(const Map& m, const double x[3], const double r[3], std::vector<uint
     ds.grad_ok = false;
     ds.color_ok = false;
     ds.omega = 0;
+    ds.n[0] = ds.n[1] = ds.n[2] = 0.0;
     if (p.single_direction && d != 0) continue;
     double sd[8], ww[8], cc[8][3], wcc[8];
     bool ok = true, cok = true;
@@ -996,5 +997,284 @@ double orc_w_dir(const Params* p, const double n[3], int d) { return w_dir(*p, n
 
 // Threads an OpenMP region of the oracle uses.
 int orc_num_threads() { return omp_get_max_threads(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// View-dependent combined ("rendering") TSDF (Sec. 4: Lemma positional_unambiguity, the
+// precomputed combined TSDF, conditional recombination; Sec. 7: evaluation at integer voxel
+// positions with six-neighbour gradients)
+// ---------------------------------------------------------------------------------------
+
+namespace {
+
+struct Frustum {
+  double R[9], t[3];                // camera -> world of the frustum's pose
+  double fx, fy, cx, cy;
+  double umin, umax, vmin, vmax;    // accepted projections: [umin, umax) x [vmin, vmax)
+};
+
+Frustum make_frustum(const double T[16], int W, int H, double fx, double fy, double cx,
+                     double cy, double margin) {
+  Frustum F;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) F.R[3 * r + c] = T[4 * r + c];
+    F.t[r] = T[4 * r + 3];
+  }
+  F.fx = fx;
+  F.fy = fy;
+  F.cx = cx;
+  F.cy = cy;
+  // pixel centres sit at integer coordinates, so the image covers [-1/2, W - 1/2); it is
+  // widened by `margin` times its size on every side
+  F.umin = -0.5 - margin * W;
+  F.umax = W - 0.5 + margin * W;
+  F.vmin = -0.5 - margin * H;
+  F.vmax = H - 0.5 + margin * H;
+  return F;
+}
+
+// Whether world point x lies in front of the camera and projects into the widened image.
+// `edge` receives how close the decision is: the distance in pixels to the nearest bound, or
+// |z| in metres when z is within 1e-9 m of zero.
+bool in_frustum(const Frustum& F, const double x[3], double* edge) {
+  double d[3] = {x[0] - F.t[0], x[1] - F.t[1], x[2] - F.t[2]};
+  double y[3];
+  for (int k = 0; k < 3; ++k) y[k] = F.R[k] * d[0] + F.R[3 + k] * d[1] + F.R[6 + k] * d[2];
+  if (std::fabs(y[2]) < 1e-9) {
+    *edge = 0.0;
+    return false;
+  }
+  if (y[2] < 0.0) {
+    *edge = 1e30;
+    return false;
+  }
+  double u = F.fx * y[0] / y[2] + F.cx, v = F.fy * y[1] / y[2] + F.cy;
+  *edge = std::min(std::min(std::fabs(u - F.umin), std::fabs(u - F.umax)),
+                   std::min(std::fabs(v - F.vmin), std::fabs(v - F.vmax)));
+  return u >= F.umin && u < F.umax && v >= F.vmin && v < F.vmax;
+}
+
+// Brick of direction d holding voxel v (world voxel index), and the voxel's local index.
+const Brick* brick_at(const Map& m, const int64_t v[3], int d, int* l) {
+  int64_t b[3] = {floor_div(v[0], kB), floor_div(v[1], kB), floor_div(v[2], kB)};
+  auto it = m.index.find(Key{(int32_t)b[0], (int32_t)b[1], (int32_t)b[2], d});
+  if (it == m.index.end()) return nullptr;
+  *l = (int)((v[0] - kB * b[0]) + kB * (v[1] - kB * b[1]) + kB * kB * (v[2] - kB * b[2]));
+  return &m.bricks[it->second];
+}
+
+struct Combined {
+  bool defined;
+  double f;
+  bool fallback;
+  double S_rel;        // gradient-weight sum / sum of W over the observed directions
+  bool color;
+  double rgb[3];
+};
+
+// Combined SDF of the six directions at voxel v for a camera centred at c (eq.
+// combine_weight at the voxel centre x = v s, view ray r = (x - c) / |x - c|).  Direction D
+// takes part if the voxel is observed in it (W^D > 0); its normal n^D is the normalised
+// central difference of Phi^D over the six axis neighbours, usable only if all six are
+// observed in D and |grad| s >= 1e-6.  Weights w_dir(n^D) max(0, <n^D, -r>) W^D; when these
+// sum to zero, eq. combine_tsdf_weight over the observed directions.  Colour: the voxel
+// colours of the directions on the gradient branch blended with w_dir(n^D) max(0, <n^D, -r>)
+// W_c^D (directions with W_c^D > 0), else with the combination weights; undefined if those
+// sum to zero.  `margin` is added to every thresholded factor (classification only).
+Combined combine_voxel(const Map& m, const int64_t v[3], const double c[3], double margin) {
+  const Params& p = m.p;
+  Combined C;
+  C.defined = false;
+  C.f = 0.0;
+  C.fallback = false;
+  C.S_rel = 0.0;
+  C.color = false;
+  C.rgb[0] = C.rgb[1] = C.rgb[2] = 0.0;
+  double x[3] = {v[0] * p.voxel, v[1] * p.voxel, v[2] * p.voxel};
+  double r[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  double rl = std::sqrt(dot3(r, r));
+  if (!(rl > 0.0)) return C;
+  for (int k = 0; k < 3; ++k) r[k] /= rl;
+  const double mr[3] = {-r[0], -r[1], -r[2]};
+  bool obs[6] = {false, false, false, false, false, false}, gok[6] = {false, false, false, false, false, false};
+  double phi[6], W[6], n[6][3], om[6], rgb[6][3], Wc[6];
+  double sumW = 0, sumO = 0, sumOP = 0;
+  for (int d = 0; d < 6; ++d) {
+    om[d] = 0.0;
+    int l;
+    const Brick* B = brick_at(m, v, d, &l);
+    if (!B || !(B->w[l] > 0.0)) continue;
+    obs[d] = true;
+    phi[d] = B->sdf[l];
+    W[d] = B->w[l];
+    Wc[d] = B->wc[l];
+    for (int ch = 0; ch < 3; ++ch) rgb[d][ch] = B->rgb[l][ch];
+    double g[3];
+    bool all = true;
+    for (int k = 0; k < 3 && all; ++k) {
+      int64_t vp[3] = {v[0], v[1], v[2]}, vm[3] = {v[0], v[1], v[2]};
+      vp[k] += 1;
+      vm[k] -= 1;
+      int lp, lm;
+      const Brick* Bp = brick_at(m, vp, d, &lp);
+      const Brick* Bm = brick_at(m, vm, d, &lm);
+      if (!Bp || !Bm || !(Bp->w[lp] > 0.0) || !(Bm->w[lm] > 0.0)) {
+        all = false;
+        break;
+      }
+      g[k] = (Bp->sdf[lp] - Bm->sdf[lm]) / (2.0 * p.voxel);
+    }
+    if (all) {
+      double gl = std::sqrt(dot3(g, g));
+      gok[d] = gl * p.voxel >= 1e-6;
+      if (gok[d])
+        for (int k = 0; k < 3; ++k) n[d][k] = g[k] / gl;
+    }
+    if (gok[d]) {
+      double wd = margin == 0.0 ? w_dir(p, n[d], d) : w_dir_shifted(p, n[d], d, margin);
+      om[d] = wd * std::max(0.0, dot3(n[d], mr) + margin) * W[d];
+    }
+    sumW += W[d];
+    sumO += om[d];
+    sumOP += om[d] * phi[d];
+  }
+  if (!(sumW > 0.0)) return C;
+  C.S_rel = sumO / sumW;
+  if (sumO > 0.0) {
+    C.defined = true;
+    C.f = sumOP / sumO;
+  } else {
+    // eq. combine_tsdf_weight
+    C.fallback = true;
+    sumO = sumOP = 0.0;
+    for (int d = 0; d < 6; ++d) {
+      if (!obs[d]) continue;
+      om[d] = W[d] * std::max(0.0, dot3(kAxis[d], mr) + margin);
+      sumO += om[d];
+      sumOP += om[d] * phi[d];
+    }
+    if (sumO > 0.0) {
+      C.defined = true;
+      C.f = sumOP / sumO;
+    }
+  }
+  if (!C.defined || !p.with_color) return C;
+  double so = 0, sc[3] = {0, 0, 0};
+  if (!C.fallback)
+    for (int d = 0; d < 6; ++d) {
+      if (!obs[d] || !gok[d] || !(Wc[d] > 0.0)) continue;
+      double wd = margin == 0.0 ? w_dir(p, n[d], d) : w_dir_shifted(p, n[d], d, margin);
+      double oc = wd * std::max(0.0, dot3(n[d], mr) + margin) * Wc[d];
+      so += oc;
+      for (int ch = 0; ch < 3; ++ch) sc[ch] += oc * rgb[d][ch];
+    }
+  if (!(so > 0.0)) {
+    so = 0;
+    sc[0] = sc[1] = sc[2] = 0;
+    for (int d = 0; d < 6; ++d) {
+      if (!obs[d] || !(Wc[d] > 0.0)) continue;
+      so += om[d];
+      for (int ch = 0; ch < 3; ++ch) sc[ch] += om[d] * rgb[d][ch];
+    }
+  }
+  if (so > 0.0) {
+    C.color = true;
+    for (int ch = 0; ch < 3; ++ch) C.rgb[ch] = sc[ch] / so;
+  }
+  return C;
+}
+
+// Whether the discrete outcomes of combine_voxel (defined, branch, colour defined, the
+// gradient test) could change under rounding: they differ between margins of +/- eps, a
+// gradient length lies within 0.1 % of its threshold, or the gradient weights are tiny next
+// to the observed weights (S_rel < 1e-3: every eligible direction is at a grazing or
+// blend-zone edge, where f is ill-conditioned).
+bool combine_fragile(const Map& m, const int64_t v[3], const double c[3], double eps,
+                     const Combined& C0) {
+  Combined a = combine_voxel(m, v, c, eps), b = combine_voxel(m, v, c, -eps);
+  if (a.defined != C0.defined || b.defined != C0.defined || a.fallback != C0.fallback ||
+      b.fallback != C0.fallback || a.color != C0.color || b.color != C0.color)
+    return true;
+  if (C0.defined && !C0.fallback && C0.S_rel < 1e-3) return true;
+  for (int d = 0; d < 6; ++d) {
+    double g[3];
+    bool all = true;
+    for (int k = 0; k < 3 && all; ++k) {
+      int64_t vp[3] = {v[0], v[1], v[2]}, vm[3] = {v[0], v[1], v[2]};
+      vp[k] += 1;
+      vm[k] -= 1;
+      int lp, lm;
+      const Brick* Bp = brick_at(m, vp, d, &lp);
+      const Brick* Bm = brick_at(m, vm, d, &lm);
+      if (!Bp || !Bm || !(Bp->w[lp] > 0.0) || !(Bm->w[lm] > 0.0)) {
+        all = false;
+        break;
+      }
+      g[k] = (Bp->sdf[lp] - Bm->sdf[lm]) / (2.0 * m.p.voxel);
+    }
+    if (all && std::fabs(std::sqrt(dot3(g, g)) * m.p.voxel / 1e-6 - 1.0) < 1e-3) return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Combined TSDF of map `src` written into map `dst` (a single-direction map: direction 0
+// holds the combined value, weight 1 where defined and 0 where not, the colour code and
+// colour weight 1 where a colour is defined).  Every block of src gets its dst brick.
+//   only_missing == 0 (recombination): every voxel centre inside the frustum of T_frustum
+//     (image widened by margin_frac of its size per side) gets its combined value for the
+//     camera centre of T_center; every other voxel holds no value.
+//   only_missing != 0 (voxels seen for the first time): only voxels inside that frustum that
+//     hold no value are evaluated; the others keep theirs.
+// dst's border byte of a voxel: bit 0 the frustum decision is within eps_edge pixels
+// (1e-9 m in depth) of its bound, bit 1 combine_fragile with margin eps_s.
+void orc_combine(void* hsrc, void* hdst, const double Tc[16], const double Tf[16], int W, int H,
+                 double fx, double fy, double cx, double cy, double margin_frac,
+                 int only_missing, double eps_s, double eps_edge) {
+  const Map& src = *static_cast<Map*>(hsrc);
+  Map& dst = *static_cast<Map*>(hdst);
+  const Frustum F = make_frustum(Tf, W, H, fx, fy, cx, cy, margin_frac);
+  const double c[3] = {Tc[3], Tc[7], Tc[11]};
+  std::vector<BKey> blocks(src.blocks.begin(), src.blocks.end());
+  std::vector<int> ids(blocks.size());
+  for (size_t i = 0; i < blocks.size(); ++i)
+    ids[i] = add_brick(dst, Key{blocks[i].x, blocks[i].y, blocks[i].z, 0});
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < (int64_t)blocks.size(); ++i) {
+    Brick& B = dst.bricks[ids[i]];
+    for (int l = 0; l < kVox; ++l) {
+      int64_t v[3] = {(int64_t)blocks[i].x * kB + (l % kB), (int64_t)blocks[i].y * kB + (l / kB) % kB,
+                      (int64_t)blocks[i].z * kB + l / (kB * kB)};
+      double x[3] = {v[0] * src.p.voxel, v[1] * src.p.voxel, v[2] * src.p.voxel};
+      double edge;
+      bool inside = in_frustum(F, x, &edge);
+      if (only_missing && (B.w[l] > 0.0 || !inside)) continue;
+      uint8_t flags = edge < eps_edge ? 1 : 0;
+      if (!inside) {
+        B.sdf[l] = 0.0;
+        B.w[l] = 0.0;
+        B.wc[l] = 0.0;
+        B.rgb[l][0] = B.rgb[l][1] = B.rgb[l][2] = 0;
+        B.border[l] = flags;
+        continue;
+      }
+      Combined C = combine_voxel(src, v, c, 0.0);
+      if (combine_fragile(src, v, c, eps_s, C)) flags |= 2;
+      B.sdf[l] = C.defined ? C.f : 0.0;
+      B.w[l] = C.defined ? 1.0 : 0.0;
+      B.wc[l] = C.color ? 1.0 : 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        // stored as 8-bit codes, rounded half to even
+        double q = C.color ? std::nearbyint(C.rgb[ch]) : 0.0;
+        B.rgb[l][ch] = (uint8_t)std::min(255.0, std::max(0.0, q));
+      }
+      B.border[l] = flags;
+    }
+  }
+}
 
 }  // extern "C"

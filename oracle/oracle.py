@@ -106,6 +106,9 @@ def _declare(L):
                              _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_eval.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
     L.orc_brick_key.argtypes = [_P, ctypes.c_int64, _P]
+    L.orc_combine.argtypes = [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     L.orc_num_threads.restype = ctypes.c_int
     L.orc_w_dir.restype = ctypes.c_double
     L.orc_w_dir.argtypes = [ctypes.POINTER(_Params), _P, ctypes.c_int]
@@ -289,10 +292,70 @@ class OracleMap:
         lib().orc_eval(self._h, n, _ptr(xs), _ptr(rs), _ptr(f), _ptr(d), _ptr(fb))
         return f, d.astype(bool), fb.astype(bool)
 
+    def combine(self, src: "OracleMap", cam, T_center: np.ndarray,
+                T_frustum: Optional[np.ndarray] = None, margin: float = 0.125,
+                only_missing: bool = False, eps_s: float = 1e-5, eps_edge: float = 1e-6):
+        """Write into this single-direction map the view-dependent combined TSDF of ``src``
+        (Sec. 4): the combined SDF of every voxel centre in the frustum of ``T_frustum``
+        (image widened by ``margin`` of its size per side) for the camera centre of
+        ``T_center``.  ``only_missing``: evaluate only voxels of that frustum holding no value
+        (voxels seen for the first time) and keep the rest."""
+        assert self.params.single_direction, "the combined TSDF is a single-direction map"
+        Tc = np.ascontiguousarray(T_center, np.float64)
+        Tf = Tc if T_frustum is None else np.ascontiguousarray(T_frustum, np.float64)
+        lib().orc_combine(src._h, self._h, _ptr(Tc), _ptr(Tf), int(cam.width), int(cam.height),
+                          cam.fx, cam.fy, cam.cx, cam.cy, float(margin), int(only_missing),
+                          float(eps_s), float(eps_edge))
+
     def brick_key(self, i: int) -> np.ndarray:
         k = np.zeros(4, np.int32)
         lib().orc_brick_key(self._h, int(i), _ptr(k))
         return k
+
+
+# ----------------------------------------------------------------------------------------
+# Conditional recombination of the combined TSDF (Sec. 4, eq. condition_1 .. condition_4)
+# ----------------------------------------------------------------------------------------
+
+def rotation_angle(R: np.ndarray) -> float:
+    """Geodesic angle of a rotation: |log R|_F / sqrt(2) (principal matrix logarithm)."""
+    L = scipy.linalg.logm(np.asarray(R, np.float64))
+    return float(np.linalg.norm(np.real(L)) / math.sqrt(2.0))
+
+
+class RecombinePolicy:
+    """Decides per frame whether the combined TSDF is recomputed.
+
+    Frame k (counted from 0) triggers a recombination if k < boot_frames (boot up), more than
+    stale_frames frames have passed since the last recombination (stale state), or its pose
+    differs from the pose of the last recombination by more than max_translation metres or
+    max_angle radians of rotation."""
+
+    def __init__(self, boot_frames: int = 5, stale_frames: int = 50,
+                 max_translation: float = 0.05, max_angle: float = 0.05 * math.pi / 2):
+        self.boot_frames = boot_frames
+        self.stale_frames = stale_frames
+        self.max_translation = max_translation
+        self.max_angle = max_angle
+        self.frames = 0
+        self.since = 0
+        self.last = None
+
+    def decide(self, T: np.ndarray) -> bool:
+        T = np.asarray(T, np.float64)
+        need = self.last is None or self.frames < self.boot_frames or \
+            self.since > self.stale_frames
+        if not need:
+            dt = float(np.linalg.norm(T[:3, 3] - self.last[:3, 3]))
+            da = rotation_angle(self.last[:3, :3].T @ T[:3, :3])
+            need = dt > self.max_translation or da > self.max_angle
+        self.frames += 1
+        if need:
+            self.since = 1
+            self.last = T.copy()
+        else:
+            self.since += 1
+        return need
 
 
 # ----------------------------------------------------------------------------------------
