@@ -41,7 +41,8 @@ typedef enum {
   DTSDF_E_CAPACITY = 3,   /* brick pool or hash table full; see dtsdf_integrate */
   DTSDF_E_HIP = 4,        /* a HIP runtime call failed */
   DTSDF_E_DEGENERATE = 5, /* icp_step: too few inliers or the normal matrix is not PD */
-  DTSDF_E_BUSY = 6        /* resource in use */
+  DTSDF_E_BUSY = 6,       /* resource in use */
+  DTSDF_E_UNSUPPORTED = 7 /* the call is switched off (see its declaration) */
 } dtsdf_status;
 
 /* Storage of the per-voxel signed distance and weight (Sec. 3: voxel tuple (d, w_d, c, w_c)). */
@@ -264,6 +265,71 @@ typedef struct {
  * per-request reduction order is the same as icp_step's, so every request's pose is bitwise
  * identical to stepping it alone.  Enqueues on `stream`; does not synchronise. */
 dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream);
+
+/* ---- View-dependent combined ("rendering") TSDF (Sec. 4) -------------------------------
+ * For a fixed camera position the six directional TSDFs can be merged into one conflict-free
+ * regular TSDF (Sec. 4, Lemma positional_unambiguity); ray casting that volume from (near)
+ * that position reads one volume instead of six.  A volume is a map whose direction slot 0
+ * holds, per voxel, the combined SDF (weight 1; weight 0 = no value) and the combined colour
+ * (colour weight 1 where defined).  dtsdf_render / dtsdf_render_batch on a volume march it
+ * like the direct path (same lattice, hit test, refinement and outputs) with the
+ * interpolated value as f, its gradient as normal and its colour as colour.  dtsdf_export /
+ * dtsdf_import work on volumes (keys with D = 0 only); dtsdf_integrate refuses them. */
+
+/* Create an empty volume for combining `src` (its voxel size, truncation, theta, lattice
+ * step and colour setting; float32 storage).  brick_capacity bricks (one per block of src:
+ * at least src's block count) and hash_buckets (power of two) as in dtsdf_create.
+ * Errors: DTSDF_E_INVAL (src is itself a volume, bad sizes), DTSDF_E_NOMEM. */
+dtsdf_status dtsdf_volume_create(const dtsdf_map* src, uint32_t brick_capacity,
+                                 uint32_t hash_buckets, dtsdf_map** out);
+
+/* Combine `src` into `vol` (Sec. 4, precomputed combined TSDF; Sec. 7, integer positions).
+ * First every block of src gets its brick in vol (only when src gained blocks since the
+ * last call; this step synchronises the stream).  Then, for every voxel centre x of src's
+ * blocks that lies in front of the camera of T_frustum and projects into its image widened
+ * by `margin` times the width / height on every side (pixel centres at integer coordinates):
+ *   f(x) = sum_D w_D Phi^D(x) / sum_D w_D,  w_D = w_dir(n^D) max(0, <n^D, -r>) W^D(x)
+ * (eq. combine_weight) over the directions observed at x (W^D > 0), with r the unit ray from
+ * the camera centre of T_center to x and n^D the normalised central difference of Phi^D over
+ * the six axis neighbours, usable only if all six are observed in D and |grad| s >= 1e-6;
+ * if these weights sum to zero, w_D = W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight); no
+ * value if that sum is zero too.  Colour: the directions' voxel colours blended with
+ * w_dir(n^D) max(0, <n^D, -r>) W_c^D, else with the combination weights; 8-bit codes
+ * rounded half to even.
+ *   only_missing == 0 (recombination, margin 1/8 in Sec. 4): every voxel outside that
+ *     frustum is left with no value, so the volume is valid for ray casting from T_center.
+ *   only_missing != 0: only voxels inside the frustum that hold no value are evaluated
+ *     (voxels seen for the first time, Sec. 4; pass the frame's pose as T_frustum, the last
+ *     recombination's pose as T_center and margin 0); the others keep their values.
+ * Poses are host double[16] (camera to world).  Enqueues on `stream`.
+ * Errors: DTSDF_E_INVAL (src is a volume, vol is not, voxel size or theta differ, bad
+ * intrinsics or margin outside [0, 4]), DTSDF_E_CAPACITY (vol cannot hold src's blocks; vol
+ * keeps what fits and nothing is combined).
+ * SWITCHED OFF: after validating its arguments the call returns DTSDF_E_UNSUPPORTED without
+ * touching the device.  A device run of it did not complete and the cause is not known;
+ * volumes can still be filled with dtsdf_import and rendered. */
+dtsdf_status dtsdf_combine(const dtsdf_map* src, dtsdf_map* vol, const double T_center[16],
+                           const double T_frustum[16], const dtsdf_intrinsics* intr,
+                           float margin, int32_t only_missing, void* stream);
+
+/* Conditional recombination (Sec. 4, eq. condition_1 .. condition_4).  The caller sets the
+ * four limits (suggested 5, 50, 0.05 m, 0.05 pi / 2 rad) and zeroes the rest. */
+typedef struct {
+  int32_t boot_frames;     /* frames 0 .. boot_frames - 1 always recombine */
+  int32_t stale_frames;    /* recombine once more than this many frames have passed */
+  double max_translation;  /* metres between the pose and the last recombination's pose */
+  double max_angle;        /* radians of the relative rotation (geodesic angle) */
+  int64_t frames;          /* frames decided so far */
+  int64_t since;           /* frames since the last recombination, this one included */
+  double last_pose[16];    /* pose of the last recombination */
+  int32_t has_pose;
+  int32_t reserved;
+} dtsdf_recombine_state;
+
+/* Decide for the next frame with pose T_world_cam whether to recombine (then record T as the
+ * new reference); *recombine = 1 or 0.  Host only, no device work. */
+dtsdf_status dtsdf_recombine_decide(dtsdf_recombine_state* state, const double T_world_cam[16],
+                                    int32_t* recombine);
 
 const char* dtsdf_status_string(dtsdf_status status);
 

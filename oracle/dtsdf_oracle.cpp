@@ -259,7 +259,7 @@ void* orc_create(const Params* p) {
     for (int bz = p->dense_lo[2]; bz <= p->dense_hi[2]; ++bz)
       for (int by = p->dense_lo[1]; by <= p->dense_hi[1]; ++by)
         for (int bx = p->dense_lo[0]; bx <= p->dense_hi[0]; ++bx)
-          for (int d = 0; d < 6; ++d) add_brick(*m, Key{bx, by, bz, d});
+          for (int d = 0; d < (p->single_direction ? 1 : 6); ++d) add_brick(*m, Key{bx, by, bz, d});
   }
   return m;
 }
@@ -1070,6 +1070,7 @@ struct Combined {
   bool fallback;
   double S_rel;        // gradient-weight sum / sum of W over the observed directions
   bool color;
+  bool color_blend;    // the colour came from the w_dir max(0, <n, -r>) W_c blend
   double rgb[3];
 };
 
@@ -1090,6 +1091,7 @@ Combined combine_voxel(const Map& m, const int64_t v[3], const double c[3], doub
   C.fallback = false;
   C.S_rel = 0.0;
   C.color = false;
+  C.color_blend = false;
   C.rgb[0] = C.rgb[1] = C.rgb[2] = 0.0;
   double x[3] = {v[0] * p.voxel, v[1] * p.voxel, v[2] * p.voxel};
   double r[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
@@ -1169,6 +1171,7 @@ Combined combine_voxel(const Map& m, const int64_t v[3], const double c[3], doub
       so += oc;
       for (int ch = 0; ch < 3; ++ch) sc[ch] += oc * rgb[d][ch];
     }
+  C.color_blend = so > 0.0;
   if (!(so > 0.0)) {
     so = 0;
     sc[0] = sc[1] = sc[2] = 0;
@@ -1185,8 +1188,8 @@ Combined combine_voxel(const Map& m, const int64_t v[3], const double c[3], doub
   return C;
 }
 
-// Whether the discrete outcomes of combine_voxel (defined, branch, colour defined, the
-// gradient test) could change under rounding: they differ between margins of +/- eps, a
+// Whether the discrete outcomes of combine_voxel (defined, branch, colour defined and its
+// blend, the gradient test) could change under rounding: they differ between margins of +/- eps, a
 // gradient length lies within 0.1 % of its threshold, or the gradient weights are tiny next
 // to the observed weights (S_rel < 1e-3: every eligible direction is at a grazing or
 // blend-zone edge, where f is ill-conditioned).
@@ -1194,7 +1197,8 @@ bool combine_fragile(const Map& m, const int64_t v[3], const double c[3], double
                      const Combined& C0) {
   Combined a = combine_voxel(m, v, c, eps), b = combine_voxel(m, v, c, -eps);
   if (a.defined != C0.defined || b.defined != C0.defined || a.fallback != C0.fallback ||
-      b.fallback != C0.fallback || a.color != C0.color || b.color != C0.color)
+      b.fallback != C0.fallback || a.color != C0.color || b.color != C0.color ||
+      a.color_blend != C0.color_blend || b.color_blend != C0.color_blend)
     return true;
   if (C0.defined && !C0.fallback && C0.S_rel < 1e-3) return true;
   for (int d = 0; d < 6; ++d) {

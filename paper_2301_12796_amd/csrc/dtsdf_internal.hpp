@@ -178,6 +178,12 @@ struct Vox<2> : VoxPacked {
   }
 };
 
+// Kernel instantiation tag of a regular volume (written by dtsdf_combine): plain storage,
+// one volume in direction slot 0, rendered without direction weighting.
+constexpr int kRegularVolume = 3;
+template <>
+struct Vox<kRegularVolume> : Vox<0> {};
+
 inline int storage_format(const dtsdf_params& p) {
   if (p.sdf_fmt == DTSDF_SDF_F32 && p.w_fmt == DTSDF_W_F32) return 0;
   if (p.sdf_fmt == DTSDF_SDF_F16 && p.w_fmt == DTSDF_W_U8) return 1;
@@ -238,6 +244,37 @@ __device__ __host__ inline float axis_dot(float nx, float ny, float nz, int d) {
   return (d & 1) ? -c : c;
 }
 
+// Inserts (key, D) into the hash: the key by CAS on an empty slot, D as a request bit.
+// New keys are refused (and counted as dropped requests) once `max_entries` slots are
+// occupied, so that probe sequences of absent keys stay short.
+__device__ inline void insert_request(HashEntry* e, uint32_t* req, uint32_t mask, uint64_t key, int d,
+                               int32_t* counters, int32_t max_entries) {
+  uint32_t s = hash_key(key) & mask;
+  for (uint32_t i = 0; i <= mask; ++i) {
+    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&e[s].key);
+    uint64_t k = __atomic_load_n(kp, __ATOMIC_RELAXED);
+    if (k == kEmptyKey) {
+      if (__atomic_load_n(&counters[3], __ATOMIC_RELAXED) >= max_entries) {
+        atomicAdd(&counters[1], 1);
+        return;
+      }
+      uint64_t prev = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
+      if (prev == kEmptyKey) atomicAdd(&counters[3], 1);
+      if (prev == kEmptyKey || prev == key) {
+        atomicOr(&req[s], 1u << d);
+        return;
+      }
+      k = prev;
+    }
+    if (k == key) {
+      atomicOr(&req[s], 1u << d);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+  atomicExch(&counters[2], 1);
+}
+
 #define DTSDF_HIP(x)                                  \
   do {                                                \
     hipError_t e__ = (x);                             \
@@ -275,6 +312,10 @@ struct dtsdf_map {
   int32_t grid_lo[3], grid_dim[3];
   int64_t grid_cap;     // allocated grid cells
   int64_t macro_cap;    // allocated bytes of each macro grid
+  // 1: a regular (single-volume) TSDF written by dtsdf_combine: direction slot 0 holds the
+  // combined value with weight 1 (0: no value), rendered without direction weighting
+  int regular;
+  int64_t mirrored;     // source block count at the last block mirroring (-1: never)
   // integration scratch, grown on demand
   int64_t img_cap;
   float* vmap;
@@ -329,4 +370,6 @@ dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st);
 dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st);
 // All of the above (synchronises `st`).
 dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st);
+// Enqueues the pool-index assignment of requested (block, D) bricks.
+void launch_assign(dtsdf_map* m, hipStream_t st);
 }

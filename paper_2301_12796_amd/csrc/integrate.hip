@@ -83,37 +83,6 @@ struct Pose {
   double t[3];
 };
 
-// Inserts (key, D) into the hash: the key by CAS on an empty slot, D as a request bit.
-// New keys are refused (and counted as dropped requests) once `max_entries` slots are
-// occupied, so that probe sequences of absent keys stay short.
-__device__ void insert_request(HashEntry* e, uint32_t* req, uint32_t mask, uint64_t key, int d,
-                               int32_t* counters, int32_t max_entries) {
-  uint32_t s = hash_key(key) & mask;
-  for (uint32_t i = 0; i <= mask; ++i) {
-    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&e[s].key);
-    uint64_t k = __atomic_load_n(kp, __ATOMIC_RELAXED);
-    if (k == kEmptyKey) {
-      if (__atomic_load_n(&counters[3], __ATOMIC_RELAXED) >= max_entries) {
-        atomicAdd(&counters[1], 1);
-        return;
-      }
-      uint64_t prev = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
-      if (prev == kEmptyKey) atomicAdd(&counters[3], 1);
-      if (prev == kEmptyKey || prev == key) {
-        atomicOr(&req[s], 1u << d);
-        return;
-      }
-      k = prev;
-    }
-    if (k == key) {
-      atomicOr(&req[s], 1u << d);
-      return;
-    }
-    s = (s + 1) & mask;
-  }
-  atomicExch(&counters[2], 1);
-}
-
 // Allocation requests (Sec. 7: blocks are allocated for every point with a valid normal):
 // for each direction D with w_dir(n) > 0, the blocks containing the J + 1 evenly spaced
 // points p + s r, s in [-tau, tau] (r: unit ray through the pixel).
@@ -311,6 +280,15 @@ bool valid_intr(const dtsdf_intrinsics* i) {
 
 }  // namespace
 
+namespace dtsdf {
+
+void launch_assign(dtsdf_map* m, hipStream_t st) {
+  hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
+                     m->req, m->bkey, m->buckets, m->p.brick_capacity, m->counters);
+}
+
+}  // namespace dtsdf
+
 extern "C" {
 
 dtsdf_status dtsdf_vertex_normal(const float* depth, const dtsdf_intrinsics* intr,
@@ -339,7 +317,7 @@ dtsdf_status dtsdf_depth_downsample(const float* depth_in, int32_t width, int32_
 dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rgb,
                              const dtsdf_intrinsics* intr, const double T_world_cam[16],
                              float depth_scale, void* stream, dtsdf_integrate_stats* stats) {
-  if (!m || !depth || !valid_intr(intr) || !T_world_cam || !(depth_scale > 0))
+  if (!m || m->regular || !depth || !valid_intr(intr) || !T_world_cam || !(depth_scale > 0))
     return DTSDF_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
   Intr in = make_intr(intr);
@@ -368,8 +346,7 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
     hipLaunchKernelGGL(request_k, grd, blk, 0, st, depth, m->nmap, in, (double)depth_scale, T,
                        voxel, tau, J, m->p.theta, m->entries, m->req, m->buckets - 1,
                        m->counters, max_entries);
-    hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
-                       m->req, m->bkey, m->buckets, m->p.brick_capacity, m->counters);
+    launch_assign(m, st);
     launch_bbox(m, st);
     int32_t c[10];
     DTSDF_HIP(hipMemcpyAsync(c, m->counters, sizeof(c), hipMemcpyDeviceToHost, st));

@@ -178,6 +178,7 @@ const char* dtsdf_status_string(dtsdf_status s) {
     case DTSDF_E_HIP: return "HIP runtime error";
     case DTSDF_E_DEGENERATE: return "degenerate registration problem";
     case DTSDF_E_BUSY: return "busy";
+    case DTSDF_E_UNSUPPORTED: return "switched off";
   }
   return "unknown status";
 }
@@ -336,8 +337,11 @@ dtsdf_status dtsdf_import(dtsdf_map* m, const dtsdf_blob* b) {
   if (n > (int64_t)m->p.brick_capacity) return DTSDF_E_CAPACITY;
   if (hipDeviceSynchronize() != hipSuccess) return DTSDF_E_HIP;
   std::vector<HostKey> keys((size_t)n);
-  for (int64_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i) {
     keys[i] = HostKey{b->keys[4 * i], b->keys[4 * i + 1], b->keys[4 * i + 2], b->keys[4 * i + 3]};
+    if (m->regular && keys[i].d != 0) return DTSDF_E_INVAL;
+  }
+  m->mirrored = -1;
   std::vector<int64_t> order((size_t)n);
   for (int64_t i = 0; i < n; ++i) order[i] = i;
   std::sort(order.begin(), order.end(),

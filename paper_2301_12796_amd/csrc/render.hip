@@ -165,6 +165,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
                           const float r[3], float inv_band, Eval* ev, const Trace& tr,
                           const float (*pa)[3] = nullptr) {
   static_assert(NP == 1 || !FULL, "outputs are evaluated one point at a time");
+  // a regular volume: one value per voxel, weight 1, so f is the interpolant itself, the
+  // normal its gradient and the colour its colour
+  constexpr bool REG = F == kRegularVolume;
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
     ev[j].defined = false;
@@ -283,7 +286,16 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
                      (sv[6] - sv[2]) * bx * ay + (sv[7] - sv[3]) * ax * ay;
     const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
     float om = 0.f, wdc = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-    if (gl >= 1e-6f) {
+    if (REG) {
+      if (gl >= 1e-6f) {
+        const float il = 1.f / gl;
+        n0 = gx * il;
+        n1 = gy * il;
+        n2 = gz * il;
+      }
+      wdc = 1.f;
+      om = 1.f;
+    } else if (gl >= 1e-6f) {
       const float il = 1.f / gl;
       n0 = gx * il;
       n1 = gy * il;
@@ -319,7 +331,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
                        (sv[6] - sv[2]) * qx * py + (sv[7] - sv[3]) * px * py;
       const float hl = sqrtf(hx * hx + hy * hy + hz * hz);
       float omj = 0.f;
-      if (hl >= 1e-6f) {
+      if (REG) {
+        omj = 1.f;
+      } else if (hl >= 1e-6f) {
         const float il = 1.f / hl;
         const float m0 = hx * il, m1 = hy * il, m2 = hz * il;
         const float wd = w_dir_fast(axis_dot(m0, m1, m2, d), m.theta, inv_band);
@@ -853,7 +867,10 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
   const bool trace = a.trace_bricks || a.trace_color || a.trace_slots || a.trace_counts;
   const MapView v = make_view(m);
   hipStream_t st = (hipStream_t)stream;
-  if (trace) {
+  if (m->regular) {
+    if (trace) hipLaunchKernelGGL((render_k<kRegularVolume, true>), grd, dim3(64), 0, st, v, a);
+    else hipLaunchKernelGGL((render_k<kRegularVolume, false>), grd, dim3(64), 0, st, v, a);
+  } else if (trace) {
     if (m->fmt == 0) hipLaunchKernelGGL((render_k<0, true>), grd, dim3(64), 0, st, v, a);
     else if (m->fmt == 1) hipLaunchKernelGGL((render_k<1, true>), grd, dim3(64), 0, st, v, a);
     else hipLaunchKernelGGL((render_k<2, true>), grd, dim3(64), 0, st, v, a);
@@ -902,7 +919,12 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
     const RenderArgs* da = reinterpret_cast<const RenderArgs*>(dev + off_args);
     const int32_t* dp = reinterpret_cast<const int32_t*>(dev + off_prefix);
     int32_t* ctr = reinterpret_cast<int32_t*>(dev);
-    if (trace) {
+    if (m->regular) {
+      if (trace)
+        hipLaunchKernelGGL((render_batch_k<kRegularVolume, true>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+      else
+        hipLaunchKernelGGL((render_batch_k<kRegularVolume, false>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
+    } else if (trace) {
       if (m->fmt == 0)
         hipLaunchKernelGGL((render_batch_k<0, true>), dim3(wgs), dim3(64), 0, st, v, da, dp, n, (int)total, ctr);
       else if (m->fmt == 1)

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
                       "__graft_entry__ as g; g.build()\"` (hipcc, gfx950)")
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY = range(7)
+OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY, E_UNSUPPORTED = range(8)
 SDF_F32, SDF_F16, SDF_I16 = 0, 1, 2
 W_F32, W_U8 = 0, 1
 ICP_W_CONST, ICP_W_DEPTH = 0, 1
@@ -111,9 +111,18 @@ ICP_RESULT_BYTES = ctypes.sizeof(_IcpResult)
 _V = ctypes.c_void_p
 _D16 = ctypes.POINTER(ctypes.c_double)
 
+class _RecombineState(ctypes.Structure):
+    _fields_ = [("boot_frames", ctypes.c_int32), ("stale_frames", ctypes.c_int32),
+                ("max_translation", ctypes.c_double), ("max_angle", ctypes.c_double),
+                ("frames", ctypes.c_int64), ("since", ctypes.c_int64),
+                ("last_pose", ctypes.c_double * 16), ("has_pose", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate",
             "dtsdf_render", "dtsdf_render_batch", "dtsdf_export", "dtsdf_import",
             "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
+            "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -133,6 +142,11 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
                           ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
+_lib.dtsdf_volume_create.argtypes = [_V, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_V)]
+_lib.dtsdf_combine.argtypes = [_V, _V, _D16, _D16, ctypes.POINTER(_Intr), ctypes.c_float,
+                               ctypes.c_int32, _V]
+_lib.dtsdf_recombine_decide.argtypes = [ctypes.POINTER(_RecombineState), _D16,
+                                        ctypes.POINTER(ctypes.c_int32)]
 for _f in EXPORTED:
     if _f != "dtsdf_status_string":
         getattr(_lib, _f).restype = ctypes.c_int
@@ -325,6 +339,60 @@ class Map:
                   rgb.ctypes.data if rgb is not None else None,
                   wc.ctypes.data if wc is not None else None)
         _check(_lib.dtsdf_import(self._h, ctypes.byref(b)), "dtsdf_import")
+
+
+class Volume(Map):
+    """A view-dependent combined TSDF of a map (Sec. 4): one regular volume that renders, from
+    (near) the pose it was combined for, like the six directions it was combined from."""
+
+    def __init__(self, src: Map, brick_capacity: Optional[int] = None,
+                 hash_buckets: Optional[int] = None):
+        cap = int(brick_capacity if brick_capacity is not None
+                  else max(1024, src.params.brick_capacity // 4))
+        nb = int(hash_buckets if hash_buckets is not None else src.params.hash_buckets)
+        self.params = dataclasses.replace(src.params, sdf_fmt=SDF_F32, w_fmt=W_F32,
+                                          brick_capacity=cap, hash_buckets=nb,
+                                          dense_lo=None, dense_hi=None)
+        h = _V()
+        _check(_lib.dtsdf_volume_create(src.handle, cap, nb, ctypes.byref(h)),
+               "dtsdf_volume_create")
+        self._h = h
+
+    def integrate(self, *args, **kwargs):
+        raise TypeError("a combined TSDF is written by combine(), not by integrate()")
+
+    def combine(self, src: Map, cam, T_center, T_frustum=None, margin: float = 0.125,
+                only_missing: bool = False, stream=None) -> int:
+        """Combine ``src`` for the camera centre of ``T_center`` over the frustum of
+        ``T_frustum`` (default: T_center) widened by ``margin`` (see dtsdf_combine; the call
+        is switched off and raises DtsdfError with status E_UNSUPPORTED)."""
+        Tf = T_center if T_frustum is None else T_frustum
+        return _check(_lib.dtsdf_combine(src.handle, self._h, _pose(T_center), _pose(Tf),
+                                         ctypes.byref(_intr(cam)), margin, int(only_missing),
+                                         _stream(stream)), "dtsdf_combine")
+
+
+class RecombinePolicy:
+    """Conditional recombination (Sec. 4, eq. condition_1 .. condition_4), decided by the
+    library: boot up, stale state, translation and rotation limits."""
+
+    def __init__(self, boot_frames: int = 5, stale_frames: int = 50,
+                 max_translation: float = 0.05, max_angle: float = 0.05 * math.pi / 2):
+        self._s = _RecombineState()
+        self._s.boot_frames = boot_frames
+        self._s.stale_frames = stale_frames
+        self._s.max_translation = max_translation
+        self._s.max_angle = max_angle
+
+    def decide(self, T_wc) -> bool:
+        out = ctypes.c_int32(0)
+        _check(_lib.dtsdf_recombine_decide(ctypes.byref(self._s), _pose(T_wc),
+                                           ctypes.byref(out)), "dtsdf_recombine_decide")
+        return bool(out.value)
+
+    @property
+    def last_pose(self) -> np.ndarray:
+        return np.array(self._s.last_pose[:]).reshape(4, 4)
 
 
 def vertex_normal(depth: torch.Tensor, cam, depth_scale: float = 1.0, stream=None):
