@@ -11,8 +11,10 @@ launch from the traced brick / bucket sets, divided by the launch duration measu
 events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
 Separately timed and reported beside it: integration ms/frame, three-level ICP ms/frame, the
 precision forms (f16 / i16 distance with u8 weights, fused from the same frames: rays/s and
-depth against the plain render) and the serving workload (p50/p99 latency and capacity of
-the continuous-batching server against serial calls).
+depth against the plain render), the serving workload (p50/p99 latency and capacity of
+the continuous-batching server against serial calls) and the view-dependent combined TSDF
+(recombination time, one-volume render rate and depth against the direct render, and a
+frame loop under the conditional-recombination policy).
 """
 from __future__ import annotations
 
@@ -76,6 +78,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="leading requests of the 120/s Poisson stream that are served")
     ap.add_argument("--copy-probe", action="store_true",
@@ -242,6 +245,12 @@ def main():
             del pm_
             torch.cuda.empty_cache()
 
+    # ---- combined ("rendering") TSDF: recombination, fill and the one-volume render ----
+    volume = None
+    if not args.no_volume:
+        volume = bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out,
+                              frames_dev)
+
     # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
     icp_ms = None
     if not args.no_icp:
@@ -348,8 +357,96 @@ def main():
         "input_generation_s": t_gen,
         "serving": serving,
         "precision": precision,
+        "volume": volume,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, frames_dev):
+    """The view-dependent combined TSDF on the room map: a full recombination (frustum
+    widened by 1/8) per trajectory pose, the render of the resulting volume from that pose
+    against the direct six-direction render, and a frame loop in which every frame is fused,
+    the conditional-recombination policy (boot up 5, stale 50 frames, 5 cm, 0.05 pi/2 rad)
+    decides between a recombination and a fill of the voxels seen for the first time, and
+    the volume is rendered at the frame's pose."""
+    H, W = cam.height, cam.width
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    vol = dtsdf.Volume(gm, brick_capacity=1 << 18, hash_buckets=params.hash_buckets)
+    vol.combine(gm, cam, poses[0])          # first call gives every block its brick
+    torch.cuda.synchronize()
+    comb_ms, rend_ms = [], []
+    for T in poses:
+        a_, b_, c_ = ev(), ev(), ev()
+        a_.record(stream)
+        vol.combine(gm, cam, T)
+        b_.record(stream)
+        vol.render(cam, T, out=out)
+        c_.record(stream)
+        c_.synchronize()
+        comb_ms.append(a_.elapsed_time(b_))
+        rend_ms.append(b_.elapsed_time(c_))
+    # accuracy against the direct render at 10 poses
+    dz_all, mm, one = [], [], []
+    for T in poses[::30]:
+        vol.combine(gm, cam, T)
+        v = vol.render(cam, T, outputs=("depth", "mask"))
+        d = gm.render(cam, T, outputs=("depth", "mask"))
+        vd, dd = v["depth"].cpu().numpy(), d["depth"].cpu().numpy()
+        both = (vd > 0) & (dd > 0)
+        dz_all.append(np.abs(vd - dd)[both])
+        mm.append(float(((vd > 0) != (dd > 0)).mean()))
+    dz = np.concatenate(dz_all)
+    vinfo = vol.info()
+    del vol
+    # frame loop with conditional recombination on a map fused frame by frame
+    fm = dtsdf.Map(params)
+    fv = dtsdf.Volume(fm, brick_capacity=1 << 18, hash_buckets=params.hash_buckets)
+    pol = dtsdf.RecombinePolicy()
+    n_re, loop_ms, direct_ms = 0, [], []
+    last = None
+    for k, (d_, c_) in enumerate(frames_dev):
+        T = poses[k]
+        fm.integrate(d_, c_, cam, T)
+        torch.cuda.synchronize()
+        a_, b_ = ev(), ev()
+        a_.record(stream)
+        if pol.decide(T):
+            fv.combine(fm, cam, T)
+            last = T
+            n_re += 1
+        else:
+            fv.combine(fm, cam, last, T_frustum=T, margin=0.0, only_missing=True)
+        fv.render(cam, T, out=out)
+        b_.record(stream)
+        b_.synchronize()
+        loop_ms.append(a_.elapsed_time(b_))
+        if k % 10 == 0:
+            c0, c1 = ev(), ev()
+            c0.record(stream)
+            fm.render(cam, T, out=out)
+            c1.record(stream)
+            c1.synchronize()
+            direct_ms.append(c0.elapsed_time(c1))
+    del fv, fm
+    torch.cuda.empty_cache()
+    res = dict(
+        combine_ms=float(np.mean(comb_ms)), combine_ms_max=float(np.max(comb_ms)),
+        render_ms=float(np.mean(rend_ms)), render_rays_per_s=H * W / (np.mean(rend_ms) * 1e-3),
+        vs_direct_depth_median_m=float(np.median(dz)),
+        vs_direct_depth_over_1mm=float(np.mean(dz > 1e-3)),
+        vs_direct_depth_over_1cm=float(np.mean(dz > 1e-2)),
+        vs_direct_mask_mismatch=float(np.mean(mm)),
+        volume_device_bytes=vinfo["device_bytes"], volume_blocks=vinfo["blocks"],
+        loop_frames=len(frames_dev), loop_recombined=n_re,
+        loop_ms_per_frame=float(np.mean(loop_ms)),
+        loop_direct_render_ms=float(np.mean(direct_ms)))
+    log(f"volume: combine {res['combine_ms']:.2f} ms, render {res['render_ms']:.2f} ms "
+        f"({res['render_rays_per_s'] / 1e6:.1f} M rays/s), depth vs direct median "
+        f"{res['vs_direct_depth_median_m']:.2e} m, >1 cm {res['vs_direct_depth_over_1cm']:.4f}, "
+        f"mask mismatch {res['vs_direct_mask_mismatch']:.4f}; loop: {n_re}/{len(frames_dev)} "
+        f"recombined, {res['loop_ms_per_frame']:.2f} ms/frame (combine or fill + render) vs "
+        f"direct render {res['loop_direct_render_ms']:.2f} ms")
+    return res
 
 
 def bench_serving(args, torch, synth, dtsdf, dev):

@@ -41,8 +41,7 @@ typedef enum {
   DTSDF_E_CAPACITY = 3,   /* brick pool or hash table full; see dtsdf_integrate */
   DTSDF_E_HIP = 4,        /* a HIP runtime call failed */
   DTSDF_E_DEGENERATE = 5, /* icp_step: too few inliers or the normal matrix is not PD */
-  DTSDF_E_BUSY = 6,       /* resource in use */
-  DTSDF_E_UNSUPPORTED = 7 /* the call is switched off (see its declaration) */
+  DTSDF_E_BUSY = 6        /* resource in use */
 } dtsdf_status;
 
 /* Storage of the per-voxel signed distance and weight (Sec. 3: voxel tuple (d, w_d, c, w_c)). */
@@ -304,10 +303,7 @@ dtsdf_status dtsdf_volume_create(const dtsdf_map* src, uint32_t brick_capacity,
  * Poses are host double[16] (camera to world).  Enqueues on `stream`.
  * Errors: DTSDF_E_INVAL (src is a volume, vol is not, voxel size or theta differ, bad
  * intrinsics or margin outside [0, 4]), DTSDF_E_CAPACITY (vol cannot hold src's blocks; vol
- * keeps what fits and nothing is combined).
- * SWITCHED OFF: after validating its arguments the call returns DTSDF_E_UNSUPPORTED without
- * touching the device.  A device run of it did not complete and the cause is not known;
- * volumes can still be filled with dtsdf_import and rendered. */
+ * keeps what fits and nothing is combined). */
 dtsdf_status dtsdf_combine(const dtsdf_map* src, dtsdf_map* vol, const double T_center[16],
                            const double T_frustum[16], const dtsdf_intrinsics* intr,
                            float margin, int32_t only_missing, void* stream);

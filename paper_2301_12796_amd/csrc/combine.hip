@@ -26,8 +26,6 @@ using namespace dtsdf;
 
 namespace {
 
-constexpr bool kCombineEnabled = false;
-
 struct Frus {
   double R[9], t[3];                 // camera -> world of the frustum's pose
   double fx, fy, cx, cy;
@@ -378,9 +376,6 @@ dtsdf_status dtsdf_combine(const dtsdf_map* src, dtsdf_map* vol, const double T_
     return DTSDF_E_INVAL;
   if (src->p.voxel_size != vol->p.voxel_size || src->p.theta != vol->p.theta)
     return DTSDF_E_INVAL;
-  // Switched off: a device run of this call did not complete and no cause has been found in
-  // the code below, so it stays unused until one is.
-  if (!kCombineEnabled) return DTSDF_E_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   if (vol->mirrored != src->n_blocks) {
     dtsdf_status ms = mirror_blocks(src, vol, st);

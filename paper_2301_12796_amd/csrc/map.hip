@@ -178,7 +178,6 @@ const char* dtsdf_status_string(dtsdf_status s) {
     case DTSDF_E_HIP: return "HIP runtime error";
     case DTSDF_E_DEGENERATE: return "degenerate registration problem";
     case DTSDF_E_BUSY: return "busy";
-    case DTSDF_E_UNSUPPORTED: return "switched off";
   }
   return "unknown status";
 }

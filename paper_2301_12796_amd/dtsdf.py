@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
                       "__graft_entry__ as g; g.build()\"` (hipcc, gfx950)")
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY, E_UNSUPPORTED = range(8)
+OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY = range(7)
 SDF_F32, SDF_F16, SDF_I16 = 0, 1, 2
 W_F32, W_U8 = 0, 1
 ICP_W_CONST, ICP_W_DEPTH = 0, 1
@@ -364,8 +364,7 @@ class Volume(Map):
     def combine(self, src: Map, cam, T_center, T_frustum=None, margin: float = 0.125,
                 only_missing: bool = False, stream=None) -> int:
         """Combine ``src`` for the camera centre of ``T_center`` over the frustum of
-        ``T_frustum`` (default: T_center) widened by ``margin`` (see dtsdf_combine; the call
-        is switched off and raises DtsdfError with status E_UNSUPPORTED)."""
+        ``T_frustum`` (default: T_center) widened by ``margin`` (see dtsdf_combine)."""
         Tf = T_center if T_frustum is None else T_frustum
         return _check(_lib.dtsdf_combine(src.handle, self._h, _pose(T_center), _pose(Tf),
                                          ctypes.byref(_intr(cam)), margin, int(only_missing),
