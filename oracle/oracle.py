@@ -10,7 +10,8 @@ module.  It shares no code with the HIP library; both sides only consume the see
   association, the point-to-plane residual (eq. geometric_ICP), its Jacobian
   (eq. ICP_geometric_dx; Sim(3): eq. sim3_derivative), the normal equations
   (eq. ICP_Hessian), the Cholesky solve (eq. ICP_solution) and the left-multiplied update
-  (eq. deltaT_update).  The exponential maps are the matrix exponential of the 4x4 generator
+  (eq. deltaT_update); the photometric terms of combined ICP (eq. combined_icp) against a
+  reference grey image with a keyframe offset (eq. keyframe_icp and its derivative).  The exponential maps are the matrix exponential of the 4x4 generator
   (scipy.linalg.expm), the plain definition of exp on se(3) and sim(3).
 
 Parameters are passed as float32-representable values (``f32``) so that both implementations
@@ -473,10 +474,151 @@ def associate_reduce(live_V, live_N, live_ok, model_V, model_N, model_mask, cam_
     return H, g, float((w * r * r).sum()), int(ok.sum())
 
 
+# ----------------------------------------------------------------------------------------
+# Photometric terms of combined ICP (Sec. 5.2, eq. combined_icp; Sec. 5.3, eq. keyframe_icp,
+# eq. keyframe_icp_derivative, eq. wedge_operator, eq. projection_dx)
+# ----------------------------------------------------------------------------------------
+
+def intensity(rgb: np.ndarray) -> np.ndarray:
+    """Grey value in [0, 1] of an 8-bit RGB image: (0.299 R + 0.587 G + 0.114 B) / 255."""
+    c = np.asarray(rgb, np.float64)
+    return (0.299 * c[..., 0] + 0.587 * c[..., 1] + 0.114 * c[..., 2]) / 255.0
+
+
+def intensity_pyramid(I: np.ndarray, levels: int):
+    """Level l+1 pixel = mean of its 2x2 block of level l."""
+    out = [np.asarray(I, np.float64)]
+    for _ in range(1, levels):
+        a = out[-1]
+        h, w = a.shape[0] // 2, a.shape[1] // 2
+        out.append(a[:2 * h, :2 * w].reshape(h, 2, w, 2).mean(axis=(1, 3)))
+    return out
+
+
+def image_gradient(I: np.ndarray):
+    """Central differences (I(u+1) - I(u-1)) / 2 per pixel; zero on the border pixels."""
+    gx = np.zeros_like(I)
+    gy = np.zeros_like(I)
+    gx[:, 1:-1] = 0.5 * (I[:, 2:] - I[:, :-2])
+    gy[1:-1, :] = 0.5 * (I[2:, :] - I[:-2, :])
+    return gx, gy
+
+
+def bilinear(I: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Bilinear interpolation at (u, v), pixel centres at integer coordinates; callers keep
+    u in [0, W - 1) and v in [0, H - 1)."""
+    u0 = np.floor(u).astype(np.int64)
+    v0 = np.floor(v).astype(np.int64)
+    a, b = u - u0, v - v0
+    return ((1 - a) * (1 - b) * I[v0, u0] + a * (1 - b) * I[v0, u0 + 1] +
+            (1 - a) * b * I[v0 + 1, u0] + a * b * I[v0 + 1, u0 + 1])
+
+
+def photometric_terms(P: np.ndarray, I_live: np.ndarray, I_ref: np.ndarray, cam_ref,
+                      T_ref_model: np.ndarray, dT: np.ndarray, dim: int, max_err: float):
+    """Residuals r = I_live - I_ref(pi(K T_RS dT p)) and their Jacobians (eq. keyframe_icp).
+
+    P (n,3): live points (live camera frame), I_live (n): their live grey values.
+    The warped point a = T_RS dT p must lie in front of the reference camera and project to
+    (u, v) in [1, W - 2] x [1, H - 2], so that the 2x2 interpolation stencil has central
+    differences; |r| <= max_err.  The Jacobian is the derivative of r itself,
+    -grad I_ref . dpi/da . R(T_RS) [I | -(dT p)^] (eq. keyframe_icp_derivative with the sign of
+    the residual; the projection derivative has -x/z^2 in its first row), and for Sim(3) the
+    scale column -grad I_ref . dpi/da . R(T_RS) (dT p).
+    Returns (J (m, dim), r (m,), mask over the n points)."""
+    y = P @ dT[:3, :3].T + dT[:3, 3]
+    Rr, tr = T_ref_model[:3, :3], T_ref_model[:3, 3]
+    a = y @ Rr.T + tr
+    H_, W_ = I_ref.shape
+    pos = a[:, 2] > 0
+    z = np.where(pos, a[:, 2], 1.0)
+    u = cam_ref.fx * a[:, 0] / z + cam_ref.cx
+    v = cam_ref.fy * a[:, 1] / z + cam_ref.cy
+    ok = pos & (u >= 1) & (u <= W_ - 2) & (v >= 1) & (v <= H_ - 2)
+    u = np.where(ok, u, 1.0)
+    v = np.where(ok, v, 1.0)
+    gx_img, gy_img = image_gradient(I_ref)
+    Ik = bilinear(I_ref, u, v)
+    gx = bilinear(gx_img, u, v)
+    gy = bilinear(gy_img, u, v)
+    r = I_live - Ik
+    ok &= np.abs(r) <= max_err
+    # d pixel / d a
+    du = np.stack([cam_ref.fx / z, np.zeros_like(z), -cam_ref.fx * a[:, 0] / z ** 2], 1)
+    dv = np.stack([np.zeros_like(z), cam_ref.fy / z, -cam_ref.fy * a[:, 1] / z ** 2], 1)
+    dI_da = gx[:, None] * du + gy[:, None] * dv          # (n, 3)
+    dI_dy = dI_da @ Rr                                    # row vectors: dI/da R
+    J = np.concatenate([-dI_dy, -np.cross(y, dI_dy)], 1)  # -dI/dy [I | -y^]
+    if dim == 7:
+        J = np.concatenate([J, -(dI_dy * y).sum(1, keepdims=True)], 1)
+    return J[ok], r[ok], ok
+
+
+def associate_reduce_rgb(live_V, live_N, live_ok, live_I, model_V, model_N, model_mask,
+                         cam_model, I_ref, cam_ref, T_ref_model, dT, dim,
+                         params: IcpParams = IcpParams(), lam: float = 0.1,
+                         max_err: float = 0.05):
+    """Normal equations of combined ICP (eq. combined_icp): the geometric sums of
+    associate_reduce plus lam times the photometric sums over every live pixel with depth;
+    both terms carry the live pixel's depth weight (Sec. 5.2)."""
+    H, g, err, cnt = associate_reduce(live_V, live_N, live_ok, model_V, model_N, model_mask,
+                                      cam_model, dT, dim, params)
+    has = live_V[..., 2] > 0
+    P = live_V[has].reshape(-1, 3)
+    Jp, rp, okp = photometric_terms(P, np.asarray(live_I)[has], I_ref, cam_ref, T_ref_model,
+                                    dT, dim, max_err)
+    if params.weight == "icp":
+        z = P[okp][:, 2]
+        w = 1.0 / (z + (1.0 - params.z_min)) ** 2
+    else:
+        w = np.ones(len(rp))
+    H = H + lam * (Jp * w[:, None]).T @ Jp
+    g = g + lam * (Jp * w[:, None]).T @ rp
+    err = err + lam * float((w * rp * rp).sum())
+    return H, g, err, cnt, int(okp.sum())
+
+
 def solve_step(H: np.ndarray, g: np.ndarray) -> np.ndarray:
     """xi = -H^{-1} g via Cholesky (eq. ICP_solution)."""
     c = scipy.linalg.cho_factor(H, lower=True)
     return -scipy.linalg.cho_solve(c, g)
+
+
+def icp_rgb(live_depth: np.ndarray, live_rgb: np.ndarray, live_cam, model_levels,
+            ref_levels, T_ref_model: np.ndarray, dT0: np.ndarray, dim: int = 6,
+            iters=(10, 5, 4), params: IcpParams = IcpParams(), lam: float = 0.1,
+            max_err=(0.05, 0.175, 0.175), min_step: float = 1e-6, depth_scale: float = 1.0,
+            min_inliers_per_dim: int = 64):
+    """Coarse-to-fine combined geometric + photometric ICP (Sec. 5.2, Sec. 5.3).
+
+    ref_levels[l] = (I_ref, cam_ref) is the reference grey image at level l (a keyframe, the
+    previous frame or a rendered colour image), T_ref_model maps the model camera frame to
+    the reference camera frame (identity for frame-to-frame and frame-to-render).  The live
+    grey pyramid halves by 2x2 means.  max_err[l] is the intensity outlier threshold of
+    level l (fine 0.05, coarse 0.175)."""
+    L = len(model_levels)
+    pyr = depth_pyramid(live_depth, L)
+    ipyr = intensity_pyramid(intensity(live_rgb), L)
+    dT = np.array(dT0, np.float64)
+    log = []
+    for l in reversed(range(L)):
+        V, N, ok = vertex_normal_map(pyr[l], live_cam.level(l), depth_scale)
+        mV, mN, mM, mcam = model_levels[l]
+        I_ref, rcam = ref_levels[l]
+        for _ in range(iters[l]):
+            H, g, err, cnt, cph = associate_reduce_rgb(V, N, ok, ipyr[l], mV, mN, mM, mcam,
+                                                       I_ref, rcam, T_ref_model, dT, dim,
+                                                       params, lam, max_err[l])
+            if cnt < min_inliers_per_dim * dim:
+                log.append(dict(level=l, status="degenerate", inliers=cnt))
+                break
+            xi = solve_step(H, g)
+            dT = exp_map(xi) @ dT
+            log.append(dict(level=l, inliers=cnt, photometric=cph, err=err,
+                            step=float(np.linalg.norm(xi)), xi=xi))
+            if np.linalg.norm(xi) < min_step:
+                break
+    return dT, log
 
 
 def icp(live_depth: np.ndarray, live_cam, model_levels, dT0: np.ndarray, dim: int = 6,

@@ -218,14 +218,25 @@ def raycast_scene(scene: Scene, origin, dirs, device: str = "cpu"):
             hit.cpu().numpy())
 
 
+def solid_texture(points: np.ndarray, period: float) -> np.ndarray:
+    """Smooth brightness factor in [0.2, 1.0] of world points (n, 3): a solid texture, the same
+    from every view, so that photometric registration has image gradients to work with."""
+    k = 2.0 * math.pi / period
+    x, y, z = points[:, 0], points[:, 1], points[:, 2]
+    return 0.6 + 0.25 * np.sin(k * x) * np.cos(k * y) + 0.15 * np.sin(k * z + 1.3)
+
+
 def render_frame(scene: Scene, cam: Camera, T_wc: np.ndarray, *, noise: str = "none",
                  sigma: float = 0.0, seed: Optional[int] = None, z_max: float = 10.0,
-                 depth_scale: float = 1.0, device: str = "cpu"):
+                 depth_scale: float = 1.0, device: str = "cpu",
+                 texture_period: Optional[float] = None):
     """Analytic RGB-D frame.
 
     noise: "none", "const" (N(0, sigma^2)) or "quadratic" (N(0, (sigma * z^2)^2)); the
     noise is drawn with numpy from ``seed`` so every device sees identical frames.
     ``depth_scale`` multiplies every stored depth (a sensor with a wrong depth scale).
+    ``texture_period`` (metres) modulates every albedo by ``solid_texture`` of the hit
+    point.
     Returns dict with depth (H,W float32), rgb (H,W,3 uint8), true depth (float64),
     camera-frame unit normals (H,W,3 float64, facing the camera) and hit mask.
     """
@@ -250,6 +261,9 @@ def render_frame(scene: Scene, cam: Camera, T_wc: np.ndarray, *, noise: str = "n
             raise ValueError(noise)
         zn = np.where(hit & (zn > 0), zn, 0.0)
     depth = (zn * depth_scale).astype(np.float32).reshape(cam.height, cam.width)
+    if texture_period is not None:
+        pts = T_wc[:3, 3] + d_w * np.where(hit, t, 0.0)[:, None]
+        alb = np.clip(np.rint(alb * solid_texture(pts, texture_period)[:, None]), 0, 255)
     rgb = np.where(hit[:, None], alb, 0).astype(np.uint8).reshape(cam.height, cam.width, 3)
     n_c = n_w @ R            # world -> camera: R^T n, written row-wise
     return dict(depth=depth, rgb=rgb, true_depth=z.reshape(cam.height, cam.width),
