@@ -228,7 +228,7 @@ typedef struct {
   int64_t inliers;
   double step_norm;    /* ||xi||_2 */
   int32_t status;      /* DTSDF_OK or DTSDF_E_DEGENERATE */
-  int32_t reserved;
+  int32_t photometric; /* photometric terms in the sums (icp_step_rgb), else 0 */
 } dtsdf_icp_result;
 
 /* One Gauss-Newton step of point-to-plane ICP (Sec. 5, eq. geometric_ICP .. deltaT_update;
@@ -245,6 +245,40 @@ dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t
                       const dtsdf_icp_params* params, double T_model_live[16],
                       dtsdf_icp_result* result, void* stream);
 
+/* Photometric term of combined ICP (Sec. 5.2, eq. combined_icp; Sec. 5.3, eq. keyframe_icp).
+ * For every live pixel with depth, its model-frame point y = T_model_live p is taken to the
+ * reference camera by T_ref_model, projected with ref_intr to (u, v) in [1, W - 2] x
+ * [1, H - 2], and r = I_live(pixel) - I_ref(u, v) (bilinear) enters the sums if
+ * |r| <= max_error, with Jacobian -grad I_ref(u, v) . d(u, v)/da . R(T_ref_model) [I | -y^]
+ * (eq. keyframe_icp_derivative; grad I_ref = bilinear central differences, zero on the
+ * border pixels; Sim(3) scale column -grad I . d(u, v)/da . R y) and weight lambda times the
+ * pixel's depth weight.  Grey values are in [0, 1] (dtsdf_intensity). */
+typedef struct {
+  const float* live_intensity;  /* device, live width x height (the live level's size) */
+  const float* ref_intensity;   /* device, ref_intr.width x ref_intr.height */
+  dtsdf_intrinsics ref_intr;
+  double T_ref_model[16];       /* model camera -> reference camera; the identity for
+                                   frame-to-frame and frame-to-render, T_kf^-1 T_model for a
+                                   keyframe at T_kf */
+  float lambda;                 /* weight of the photometric energy (0.1) */
+  float max_error;              /* intensity outlier threshold (0.05 fine, 0.175 coarse) */
+} dtsdf_photo;
+
+/* icp_step with the photometric term of `photo` added to the same fixed-order sums
+ * (photo == NULL: icp_step).  The degenerate test counts geometric inliers. */
+dtsdf_status icp_step_rgb(const dtsdf_image* live, const dtsdf_image* model,
+                          const dtsdf_photo* photo, int32_t dim,
+                          const dtsdf_icp_params* params, double T_model_live[16],
+                          dtsdf_icp_result* result, void* stream);
+
+/* Grey values (0.299 R + 0.587 G + 0.114 B) / 255 of a device H*W*3 uint8 image. */
+dtsdf_status dtsdf_intensity(const uint8_t* rgb, int32_t width, int32_t height, float* out,
+                             void* stream);
+
+/* Halve a grey image: output pixel = mean of its 2x2 input block. */
+dtsdf_status dtsdf_intensity_downsample(const float* in, int32_t width, int32_t height,
+                                        float* out, void* stream);
+
 /* One registration request of a batch; pose, flag and result live in device memory so that
  * a serving loop can run many iterations without host round-trips. */
 typedef struct {
@@ -257,6 +291,7 @@ typedef struct {
                                   degenerate (then the pose is left unchanged) */
   double min_step;
   dtsdf_icp_result* result;    /* device or NULL */
+  const dtsdf_photo* photo;    /* host, or NULL: geometric terms only */
 } dtsdf_icp_req;
 
 /* One Gauss-Newton step for each of n requests (any sizes, SE(3) or Sim(3)) in two launches

@@ -1,7 +1,9 @@
 // Point-to-plane ICP step in SE(3) and Sim(3) (Sec. 5 and Sec. 6).
 //
 //   reduce_k<DIM>  per live pixel: transform, projective association, rejection, residual
-//                  r = <q - y, n> and Jacobian J = (-n, -(y x n)[, -<n, y>]); every thread
+//                  r = <q - y, n> and Jacobian J = (-n, -(y x n)[, -<n, y>]), plus, for
+//                  combined ICP, the photometric residual against a reference grey image
+//                  warped through T_RS, weighted by lambda (Sec. 5.2, 5.3); every thread
 //                  sums a fixed strided subset of pixels in float32 (optionally with Neumaier
 //                  compensation, merged by TwoSum), the workgroup folds its four waves with
 //                  xor shuffles and a fixed-order LDS pass, and writes one partial vector.
@@ -30,7 +32,8 @@ constexpr int kReduceThreads = 256;
 template <int DIM>
 struct Sizes {
   static constexpr int NH = DIM * (DIM + 1) / 2;
-  static constexpr int NS = NH + DIM + 2;   // H upper triangle, g, error, count
+  // H upper triangle, g, error, geometric count, photometric count
+  static constexpr int NS = NH + DIM + 3;
 };
 
 struct IcpArgs {
@@ -46,9 +49,19 @@ struct IcpArgs {
   int weight_kind;
   float z_min;
   const double* pose;     // device 4x4 row-major, live -> model
+  // photometric term (photo != 0): live grey values (live size), reference grey image,
+  // its intrinsics, the model -> reference transform (rows of R | t) and the term's weight
+  // and outlier threshold
+  int photo;
+  const float* li;
+  const float* ri;
+  int rW, rH;
+  float rfx, rfy, rcx, rcy;
+  float trs[12];
+  float lambda, max_ierr;
 };
 
-constexpr int kNSMax = 7 * 8 / 2 + 7 + 2;   // partial sums of a 7-dof request
+constexpr int kNSMax = 7 * 8 / 2 + 7 + 3;   // partial sums of a 7-dof request
 
 // Device descriptor of one registration request of a batch.
 struct IcpJob {
@@ -92,6 +105,98 @@ struct PSum {
   __device__ void merge(float s2, float) { s += s2; }
 };
 
+// Point-to-plane term of a live point y (model frame) with live normal nl: projective
+// association, rejection, r = <q - y, n> and J = (-n, -(y x n)[, -<n, y>]) (eq. geometric_ICP,
+// eq. ICP_geometric_dx; Sim(3): eq. sim3_derivative).  False if rejected.
+template <int DIM>
+__device__ inline bool geometric_term(const IcpArgs& a, bool has_normal, float nlx, float nly,
+                                      float nlz, const float* R, const float* y, size_t MHW,
+                                      float* J, float& res) {
+  if (!has_normal || !(y[2] > 0.f)) return false;
+  float nr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nr[k] = R[3 * k] * nlx + R[3 * k + 1] * nly + R[3 * k + 2] * nlz;
+  const float inr = 1.f / sqrtf(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+  const float uf = a.fx * y[0] / y[2] + a.cx;
+  const float vf = a.fy * y[1] / y[2] + a.cy;
+  const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
+  if (!(ur >= 0.f && vr >= 0.f && ur < (float)a.mW && vr < (float)a.mH)) return false;
+  const size_t mi = (size_t)vr * a.mW + (size_t)ur;
+  if (a.mmask && !a.mmask[mi]) return false;
+  const float n[3] = {a.mn[mi], a.mn[MHW + mi], a.mn[2 * MHW + mi]};
+  if (!a.mmask && n[0] == 0.f && n[1] == 0.f && n[2] == 0.f) return false;
+  const float d[3] = {a.mv[mi] - y[0], a.mv[MHW + mi] - y[1], a.mv[2 * MHW + mi] - y[2]};
+  if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > a.max_dist2) return false;
+  if ((n[0] * nr[0] + n[1] * nr[1] + n[2] * nr[2]) * inr < a.cos_angle) return false;
+  res = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+  J[0] = -n[0];
+  J[1] = -n[1];
+  J[2] = -n[2];
+  J[3] = -(y[1] * n[2] - y[2] * n[1]);
+  J[4] = -(y[2] * n[0] - y[0] * n[2]);
+  J[5] = -(y[0] * n[1] - y[1] * n[0]);
+  if (DIM == 7) J[DIM - 1] = -(n[0] * y[0] + n[1] * y[1] + n[2] * y[2]);
+  return true;
+}
+
+// Central difference of the reference image along x at pixel (u, v), zero on the border
+// columns; the same along y.
+__device__ inline float grad_u(const IcpArgs& a, int u, int v) {
+  if (u <= 0 || u >= a.rW - 1) return 0.f;
+  const float* row = a.ri + (size_t)v * a.rW;
+  return 0.5f * (row[u + 1] - row[u - 1]);
+}
+__device__ inline float grad_v(const IcpArgs& a, int u, int v) {
+  if (v <= 0 || v >= a.rH - 1) return 0.f;
+  return 0.5f * (a.ri[(size_t)(v + 1) * a.rW + u] - a.ri[(size_t)(v - 1) * a.rW + u]);
+}
+
+// Photometric term of live pixel i with model-frame point y (eq. keyframe_icp): the point is
+// taken to the reference camera by T_RS, projected to (u, v) in [1, W - 2] x [1, H - 2], the
+// reference grey value and its central-difference gradient are interpolated bilinearly and
+// r = I_live(i) - I_ref(u, v) with |r| <= max_ierr.  J is the derivative of r:
+// -grad I . d(u, v)/da . R(T_RS) [I | -y^] (eq. keyframe_icp_derivative, eq. wedge_operator,
+// eq. projection_dx with -x/z^2), Sim(3) scale column -grad I . d(u, v)/da . R(T_RS) y.
+template <int DIM>
+__device__ inline bool photometric_term(const IcpArgs& a, size_t i, const float* y, float* J,
+                                        float& res) {
+  const float* T = a.trs;
+  const float ax = T[0] * y[0] + T[1] * y[1] + T[2] * y[2] + T[3];
+  const float ay = T[4] * y[0] + T[5] * y[1] + T[6] * y[2] + T[7];
+  const float az = T[8] * y[0] + T[9] * y[1] + T[10] * y[2] + T[11];
+  if (!(az > 0.f)) return false;
+  const float iz = 1.f / az;
+  const float u = a.rfx * ax * iz + a.rcx, v = a.rfy * ay * iz + a.rcy;
+  if (!(u >= 1.f && u <= (float)(a.rW - 2) && v >= 1.f && v <= (float)(a.rH - 2))) return false;
+  const int u0 = (int)floorf(u), v0 = (int)floorf(v);
+  const float fu = u - (float)u0, fv = v - (float)v0;
+  const float w00 = (1.f - fu) * (1.f - fv), w10 = fu * (1.f - fv), w01 = (1.f - fu) * fv,
+              w11 = fu * fv;
+  const float* r0 = a.ri + (size_t)v0 * a.rW;
+  const float* r1 = r0 + a.rW;
+  const float Ik = w00 * r0[u0] + w10 * r0[u0 + 1] + w01 * r1[u0] + w11 * r1[u0 + 1];
+  res = a.li[i] - Ik;
+  if (!(fabsf(res) <= a.max_ierr)) return false;
+  const float gx = w00 * grad_u(a, u0, v0) + w10 * grad_u(a, u0 + 1, v0) +
+                   w01 * grad_u(a, u0, v0 + 1) + w11 * grad_u(a, u0 + 1, v0 + 1);
+  const float gy = w00 * grad_v(a, u0, v0) + w10 * grad_v(a, u0 + 1, v0) +
+                   w01 * grad_v(a, u0, v0 + 1) + w11 * grad_v(a, u0 + 1, v0 + 1);
+  // dI/da = gx d u/da + gy d v/da, then c = dI/da R(T_RS) (derivative with respect to y)
+  const float da0 = gx * a.rfx * iz, da1 = gy * a.rfy * iz;
+  const float da2 = -(gx * a.rfx * ax + gy * a.rfy * ay) * iz * iz;
+  const float c0 = da0 * T[0] + da1 * T[4] + da2 * T[8];
+  const float c1 = da0 * T[1] + da1 * T[5] + da2 * T[9];
+  const float c2 = da0 * T[2] + da1 * T[6] + da2 * T[10];
+  J[0] = -c0;
+  J[1] = -c1;
+  J[2] = -c2;
+  J[3] = -(y[1] * c2 - y[2] * c1);
+  J[4] = -(y[2] * c0 - y[0] * c2);
+  J[5] = -(y[0] * c1 - y[1] * c0);
+  if (DIM == 7) J[DIM - 1] = -(c0 * y[0] + c1 * y[1] + c2 * y[2]);
+  return true;
+}
+
 // Reduces the pixels of one chunk of a request into out[NS][2] (sum, compensation); called by
 // all threads of a 256-thread workgroup.
 template <int DIM, class Acc>
@@ -112,51 +217,42 @@ __device__ void reduce_chunk(const IcpArgs& a, int chunk, float* __restrict__ ou
   const size_t per = (LHW + kChunks - 1) / kChunks;
   const size_t begin = (size_t)chunk * per, end = begin + per < LHW ? begin + per : LHW;
   for (size_t i = begin + threadIdx.x; i < end; i += kReduceThreads) {
-    const float nlx = a.ln[i], nly = a.ln[LHW + i], nlz = a.ln[2 * LHW + i];
-    if (nlx == 0.f && nly == 0.f && nlz == 0.f) continue;
     const float px = a.lv[i], py = a.lv[LHW + i], pz = a.lv[2 * LHW + i];
-    float y[3], nr[3];
+    const float nlx = a.ln[i], nly = a.ln[LHW + i], nlz = a.ln[2 * LHW + i];
+    const bool has_normal = !(nlx == 0.f && nly == 0.f && nlz == 0.f);
+    if (!has_normal && !(a.photo && pz > 0.f)) continue;
+    float y[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      y[k] = R[3 * k] * px + R[3 * k + 1] * py + R[3 * k + 2] * pz + t[k];
-      nr[k] = R[3 * k] * nlx + R[3 * k + 1] * nly + R[3 * k + 2] * nlz;
-    }
-    if (!(y[2] > 0.f)) continue;
-    const float inr = 1.f / sqrtf(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
-    const float uf = a.fx * y[0] / y[2] + a.cx;
-    const float vf = a.fy * y[1] / y[2] + a.cy;
-    const float ur = floorf(uf + 0.5f), vr = floorf(vf + 0.5f);
-    if (!(ur >= 0.f && vr >= 0.f && ur < (float)a.mW && vr < (float)a.mH)) continue;
-    const size_t mi = (size_t)vr * a.mW + (size_t)ur;
-    if (a.mmask && !a.mmask[mi]) continue;
-    const float n[3] = {a.mn[mi], a.mn[MHW + mi], a.mn[2 * MHW + mi]};
-    if (!a.mmask && n[0] == 0.f && n[1] == 0.f && n[2] == 0.f) continue;
-    const float d[3] = {a.mv[mi] - y[0], a.mv[MHW + mi] - y[1], a.mv[2 * MHW + mi] - y[2]};
-    if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > a.max_dist2) continue;
-    if ((n[0] * nr[0] + n[1] * nr[1] + n[2] * nr[2]) * inr < a.cos_angle) continue;
-    const float res = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
-    float J[DIM];
-    J[0] = -n[0];
-    J[1] = -n[1];
-    J[2] = -n[2];
-    J[3] = -(y[1] * n[2] - y[2] * n[1]);
-    J[4] = -(y[2] * n[0] - y[0] * n[2]);
-    J[5] = -(y[0] * n[1] - y[1] * n[0]);
-    if (DIM == 7) J[DIM - 1] = -(n[0] * y[0] + n[1] * y[1] + n[2] * y[2]);
+    for (int k = 0; k < 3; ++k) y[k] = R[3 * k] * px + R[3 * k + 1] * py + R[3 * k + 2] * pz + t[k];
     float w = 1.f;
     if (a.weight_kind == DTSDF_ICP_W_DEPTH) {
       const float zz = pz + (1.f - a.z_min);       // eq. ICP_weight
       w = 1.f / (zz * zz);
     }
-    int s = 0;
+    float J[DIM], res = 0.f;
+    if (geometric_term<DIM>(a, has_normal, nlx, nly, nlz, R, y, MHW, J, res)) {
+      int s = 0;
 #pragma unroll
-    for (int r = 0; r < DIM; ++r)
+      for (int r = 0; r < DIM; ++r)
 #pragma unroll
-      for (int c = r; c < DIM; ++c) acc[s++].add(w * J[r] * J[c]);
+        for (int c = r; c < DIM; ++c) acc[s++].add(w * J[r] * J[c]);
 #pragma unroll
-    for (int r = 0; r < DIM; ++r) acc[NH + r].add(w * J[r] * res);
-    acc[NS - 2].add(w * res * res);
-    acc[NS - 1].add(1.f);
+      for (int r = 0; r < DIM; ++r) acc[NH + r].add(w * J[r] * res);
+      acc[NH + DIM].add(w * res * res);
+      acc[NH + DIM + 1].add(1.f);
+    }
+    if (a.photo && pz > 0.f && photometric_term<DIM>(a, i, y, J, res)) {
+      const float lw = a.lambda * w;   // eq. combined_icp: E_geom + lambda E_photo
+      int s = 0;
+#pragma unroll
+      for (int r = 0; r < DIM; ++r)
+#pragma unroll
+        for (int c = r; c < DIM; ++c) acc[s++].add(lw * J[r] * J[c]);
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) acc[NH + r].add(lw * J[r] * res);
+      acc[NH + DIM].add(lw * res * res);
+      acc[NH + DIM + 2].add(1.f);
+    }
   }
   // fixed-order tree: xor shuffles within the wave, then the four waves in LDS order
   __shared__ float lds[kReduceThreads / 64][NS][2];
@@ -259,7 +355,7 @@ __device__ void solve_one(const float* __restrict__ partials, const IcpJob& j) {
     }
   for (int r = 0; r < DIM; ++r) g[r] = sums[NH + r];
   int status = 0;
-  if (sums[NS - 1] < (double)j.min_inliers * DIM) status = 1;
+  if (sums[NH + DIM + 1] < (double)j.min_inliers * DIM) status = 1;
   // Cholesky H = L L^T
   for (int jj = 0; jj < DIM && status == 0; ++jj) {
     double d = H[jj * DIM + jj];
@@ -310,8 +406,9 @@ __device__ void solve_one(const float* __restrict__ partials, const IcpJob& j) {
       res->g[r] = g[r];
     }
     for (int i = 0; i < 7; ++i) res->xi[i] = xi[i];
-    res->error = sums[NS - 2];
-    res->inliers = (int64_t)sums[NS - 1];
+    res->error = sums[NH + DIM];
+    res->inliers = (int64_t)sums[NH + DIM + 1];
+    res->photometric = (int32_t)sums[NH + DIM + 2];
     res->step_norm = step;
     res->status = status == 0 ? DTSDF_OK : DTSDF_E_DEGENERATE;
   }
@@ -342,9 +439,9 @@ __global__ __launch_bounds__(64) void solve_batch_k(const IcpJob* __restrict__ j
   else solve_one<7>(p, j);
 }
 
-bool make_job(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
-              const dtsdf_icp_params* p, double* pose, int32_t* active, double min_step,
-              dtsdf_icp_result* result, IcpJob& j) {
+bool make_job(const dtsdf_image* live, const dtsdf_image* model, const dtsdf_photo* ph,
+              int32_t dim, const dtsdf_icp_params* p, double* pose, int32_t* active,
+              double min_step, dtsdf_icp_result* result, IcpJob& j) {
   if (!live || !model || !p || !pose || (dim != 6 && dim != 7)) return false;
   if (!live->vertex || !live->normal || !model->vertex || !model->normal) return false;
   if (live->intr.width <= 0 || live->intr.height <= 0 || model->intr.width <= 0 ||
@@ -370,6 +467,31 @@ bool make_job(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
   a.weight_kind = p->weight;
   a.z_min = p->z_min;
   a.pose = pose;
+  a.photo = ph ? 1 : 0;
+  a.li = nullptr;
+  a.ri = nullptr;
+  a.rW = a.rH = 0;
+  a.rfx = a.rfy = a.rcx = a.rcy = 0.f;
+  for (int k = 0; k < 12; ++k) a.trs[k] = 0.f;
+  a.lambda = a.max_ierr = 0.f;
+  if (ph) {
+    if (!ph->live_intensity || !ph->ref_intensity || ph->ref_intr.width < 3 ||
+        ph->ref_intr.height < 3 || !(ph->ref_intr.fx > 0) || !(ph->ref_intr.fy > 0) ||
+        !(ph->lambda >= 0.f) || !(ph->max_error > 0.f))
+      return false;
+    a.li = ph->live_intensity;
+    a.ri = ph->ref_intensity;
+    a.rW = ph->ref_intr.width;
+    a.rH = ph->ref_intr.height;
+    a.rfx = ph->ref_intr.fx;
+    a.rfy = ph->ref_intr.fy;
+    a.rcx = ph->ref_intr.cx;
+    a.rcy = ph->ref_intr.cy;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 4; ++c) a.trs[4 * r + c] = (float)ph->T_ref_model[4 * r + c];
+    a.lambda = ph->lambda;
+    a.max_ierr = ph->max_error;
+  }
   j.dim = dim;
   j.compensated = p->compensated;
   j.min_inliers = p->min_inliers_per_dim;
@@ -411,18 +533,62 @@ dtsdf_status get_scratch(Scratch** out) {
   return DTSDF_OK;
 }
 
+__global__ __launch_bounds__(256) void intensity_k(const uint8_t* __restrict__ rgb, size_t n,
+                                                   float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t* c = rgb + 3 * i;
+  out[i] = (0.299f * (float)c[0] + 0.587f * (float)c[1] + 0.114f * (float)c[2]) * (1.f / 255.f);
+}
+
+__global__ __launch_bounds__(256) void mean2x2_k(const float* __restrict__ in, int W, int H,
+                                                 float* __restrict__ out) {
+  const int Wo = W / 2, Ho = H / 2;
+  const int u = blockIdx.x * 16 + (threadIdx.x & 15), v = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (u >= Wo || v >= Ho) return;
+  const float* r0 = in + (size_t)(2 * v) * W + 2 * u;
+  const float* r1 = r0 + W;
+  out[(size_t)v * Wo + u] = 0.25f * ((r0[0] + r0[1]) + (r1[0] + r1[1]));
+}
+
 }  // namespace
+
+extern "C" dtsdf_status dtsdf_intensity(const uint8_t* rgb, int32_t width, int32_t height,
+                                        float* out, void* stream) {
+  if (!rgb || !out || width <= 0 || height <= 0) return DTSDF_E_INVAL;
+  const size_t n = (size_t)width * height;
+  hipLaunchKernelGGL(intensity_k, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, rgb, n, out);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+extern "C" dtsdf_status dtsdf_intensity_downsample(const float* in, int32_t width,
+                                                   int32_t height, float* out, void* stream) {
+  if (!in || !out || width < 2 || height < 2) return DTSDF_E_INVAL;
+  dim3 grd((width / 2 + 15) / 16, (height / 2 + 15) / 16);
+  hipLaunchKernelGGL(mean2x2_k, grd, dim3(256), 0, (hipStream_t)stream, in, width, height, out);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
 
 extern "C" dtsdf_status icp_step(const dtsdf_image* live, const dtsdf_image* model, int32_t dim,
                                  const dtsdf_icp_params* p, double T[16], dtsdf_icp_result* out,
                                  void* stream) {
+  return icp_step_rgb(live, model, nullptr, dim, p, T, out, stream);
+}
+
+extern "C" dtsdf_status icp_step_rgb(const dtsdf_image* live, const dtsdf_image* model,
+                                     const dtsdf_photo* photo, int32_t dim,
+                                     const dtsdf_icp_params* p, double T[16],
+                                     dtsdf_icp_result* out, void* stream) {
   if (!T) return DTSDF_E_INVAL;
   std::lock_guard<std::mutex> lock(g_mu);
   Scratch* s = nullptr;
   dtsdf_status st = get_scratch(&s);
   if (st != DTSDF_OK) return st;
   IcpJob job;
-  if (!make_job(live, model, dim, p, reinterpret_cast<double*>(s->dev + kOffPose),
+  if (!make_job(live, model, photo, dim, p, reinterpret_cast<double*>(s->dev + kOffPose),
                 reinterpret_cast<int32_t*>(s->dev + kOffActive), 0.0,
                 reinterpret_cast<dtsdf_icp_result*>(s->dev + kOffResult), job))
     return DTSDF_E_INVAL;
@@ -453,7 +619,7 @@ extern "C" dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, voi
   if (n == 0) return DTSDF_OK;
   std::vector<IcpJob> jobs((size_t)n);
   for (int r = 0; r < n; ++r)
-    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].dim, &reqs[r].params, reqs[r].pose,
+    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params, reqs[r].pose,
                   reqs[r].active, reqs[r].min_step, reqs[r].result, jobs[r]))
       return DTSDF_E_INVAL;
   hipStream_t hs = (hipStream_t)stream;

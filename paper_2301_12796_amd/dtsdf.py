@@ -91,7 +91,13 @@ class _IcpResult(ctypes.Structure):
     _fields_ = [("xi", ctypes.c_double * 7), ("H", ctypes.c_double * 49),
                 ("g", ctypes.c_double * 7), ("error", ctypes.c_double),
                 ("inliers", ctypes.c_int64), ("step_norm", ctypes.c_double),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("photometric", ctypes.c_int32)]
+
+
+class _Photo(ctypes.Structure):
+    _fields_ = [("live_intensity", ctypes.c_void_p), ("ref_intensity", ctypes.c_void_p),
+                ("ref_intr", _Intr), ("T_ref_model", ctypes.c_double * 16),
+                ("lambda_", ctypes.c_float), ("max_error", ctypes.c_float)]
 
 
 class _RenderReq(ctypes.Structure):
@@ -102,7 +108,8 @@ class _RenderReq(ctypes.Structure):
 class _IcpReq(ctypes.Structure):
     _fields_ = [("live", _Image), ("model", _Image), ("dim", ctypes.c_int32),
                 ("params", _IcpParams), ("pose", ctypes.c_void_p), ("active", ctypes.c_void_p),
-                ("min_step", ctypes.c_double), ("result", ctypes.c_void_p)]
+                ("min_step", ctypes.c_double), ("result", ctypes.c_void_p),
+                ("photo", ctypes.c_void_p)]
 
 
 ICP_RESULT_BYTES = ctypes.sizeof(_IcpResult)
@@ -123,6 +130,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_render", "dtsdf_render_batch", "dtsdf_export", "dtsdf_import",
             "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
+            "icp_step_rgb", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -142,6 +150,11 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
                           ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
+_lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
+                              ctypes.POINTER(_Photo), ctypes.c_int32,
+                              ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
+_lib.dtsdf_intensity.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
+_lib.dtsdf_intensity_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_volume_create.argtypes = [_V, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_V)]
 _lib.dtsdf_combine.argtypes = [_V, _V, _D16, _D16, ctypes.POINTER(_Intr), ctypes.c_float,
                                ctypes.c_int32, _V]
@@ -425,11 +438,49 @@ class IcpParams:
     compensated: bool = False
 
 
+@dataclasses.dataclass
+class Photo:
+    """Photometric term of combined ICP (see dtsdf_photo): live and reference grey images
+    (float32 device tensors), the reference intrinsics and the model -> reference transform."""
+    live_intensity: torch.Tensor
+    ref_intensity: torch.Tensor
+    ref_cam: object
+    T_ref_model: np.ndarray = dataclasses.field(default_factory=lambda: np.eye(4))
+    lam: float = 0.1
+    max_error: float = 0.05
+
+    def c_struct(self, live_cam) -> _Photo:
+        Hl, Wl = int(live_cam.height), int(live_cam.width)
+        Hr, Wr = int(self.ref_cam.height), int(self.ref_cam.width)
+        return _Photo(_dev_ptr(self.live_intensity, torch.float32, Hl * Wl),
+                      _dev_ptr(self.ref_intensity, torch.float32, Hr * Wr),
+                      _intr(self.ref_cam), _pose(self.T_ref_model), self.lam, self.max_error)
+
+
+def intensity(rgb: torch.Tensor, stream=None) -> torch.Tensor:
+    """Grey values in [0, 1] of an (H, W, 3) uint8 device image."""
+    H, W = int(rgb.shape[0]), int(rgb.shape[1])
+    out = torch.empty((H, W), dtype=torch.float32, device=rgb.device)
+    _check(_lib.dtsdf_intensity(_dev_ptr(rgb, torch.uint8, H * W * 3), W, H,
+                                _dev_ptr(out, torch.float32), _stream(stream)), "dtsdf_intensity")
+    return out
+
+
+def intensity_downsample(img: torch.Tensor, stream=None) -> torch.Tensor:
+    H, W = img.shape
+    out = torch.empty((H // 2, W // 2), dtype=torch.float32, device=img.device)
+    _check(_lib.dtsdf_intensity_downsample(_dev_ptr(img, torch.float32), W, H,
+                                           _dev_ptr(out, torch.float32), _stream(stream)),
+           "dtsdf_intensity_downsample")
+    return out
+
+
 def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
              model_vertex: torch.Tensor, model_normal: torch.Tensor,
              model_mask: Optional[torch.Tensor], model_cam, T_model_live, dim: int = 6,
-             params: IcpParams = IcpParams(), stream=None):
-    """One ICP Gauss-Newton step; returns (status, updated T (4x4), result dict)."""
+             params: IcpParams = IcpParams(), stream=None, photo: Optional[Photo] = None):
+    """One ICP Gauss-Newton step (with ``photo``: combined geometric + photometric);
+    returns (status, updated T (4x4), result dict)."""
     Hl, Wl = int(live_cam.height), int(live_cam.width)
     Hm, Wm = int(model_cam.height), int(model_cam.width)
     live = _Image(_dev_ptr(live_vertex, torch.float32, 3 * Hl * Wl),
@@ -442,11 +493,13 @@ def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
                    params.min_inliers_per_dim, int(params.compensated))
     T = _pose(T_model_live)
     r = _IcpResult()
-    status = _lib.icp_step(ctypes.byref(live), ctypes.byref(model), dim, ctypes.byref(p), T,
-                           ctypes.byref(r), _stream(stream))
+    ph = ctypes.byref(photo.c_struct(live_cam)) if photo is not None else None
+    status = _lib.icp_step_rgb(ctypes.byref(live), ctypes.byref(model), ph, dim,
+                               ctypes.byref(p), T, ctypes.byref(r), _stream(stream))
     _check(status, "icp_step", allow=(E_DEGENERATE,))
     res = dict(xi=np.array(r.xi[:dim]), H=np.array(r.H[:dim * dim]).reshape(dim, dim),
-               g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm)
+               g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm,
+               photometric=r.photometric)
     return status, np.array(T[:]).reshape(4, 4), res
 
 
@@ -487,6 +540,7 @@ def icp_request_struct(q: IcpRequest) -> _IcpReq:
     r.active = _dev_ptr(q.active, torch.int32, 1) if q.active is not None else None
     r.min_step = q.min_step
     r.result = _dev_ptr(q.result, torch.uint8, ICP_RESULT_BYTES) if q.result is not None else None
+    r.photo = None
     return r
 
 
@@ -511,28 +565,43 @@ def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:
 
 def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
         iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
-        depth_scale: float = 1.0, stream=None):
+        depth_scale: float = 1.0, stream=None, live_rgb: Optional[torch.Tensor] = None,
+        ref_levels=None, T_ref_model=None, lam: float = 0.1, max_error=(0.05, 0.175, 0.175)):
     """Coarse-to-fine ICP: model_levels[l] = (vertex, normal, mask, cam) at level l.
-    ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine."""
+    ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine.
+    With ``live_rgb`` and ``ref_levels`` ([(grey image, cam)] per level) the steps are
+    combined geometric + photometric (Sec. 5.2, 5.3); ``T_ref_model`` maps the model camera to
+    the reference camera (identity: frame-to-frame / frame-to-render)."""
     L = len(model_levels)
     pyr = [live_depth]
     for _ in range(1, L):
         pyr.append(depth_downsample(pyr[-1], stream=stream))
+    ipyr = None
+    if live_rgb is not None:
+        ipyr = [intensity(live_rgb, stream=stream)]
+        for _ in range(1, L):
+            ipyr.append(intensity_downsample(ipyr[-1], stream=stream))
+    Tref = np.eye(4) if T_ref_model is None else np.asarray(T_ref_model, np.float64)
     T = np.array(T0, np.float64)
     log = []
     for l in reversed(range(L)):
         cam_l = level_camera(live_cam, l)
         v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
         mv, mn, mm, mcam = model_levels[l]
+        photo = None
+        if ipyr is not None:
+            ri, rcam = ref_levels[l]
+            photo = Photo(ipyr[l], ri, rcam, Tref, lam, max_error[l])
         for _ in range(iters[l]):
-            status, T_new, res = icp_step(v, n, cam_l, mv, mn, mm, mcam, T, dim, params, stream)
+            status, T_new, res = icp_step(v, n, cam_l, mv, mn, mm, mcam, T, dim, params, stream,
+                                          photo=photo)
             if status != OK:
                 log.append(dict(level=l, status="degenerate", inliers=res["inliers"],
                                 err=res["error"]))
                 break
             T = T_new
             log.append(dict(level=l, inliers=res["inliers"], err=res["error"],
-                            step=res["step_norm"]))
+                            step=res["step_norm"], photometric=res["photometric"]))
             if res["step_norm"] < min_step:
                 break
     return T, log
