@@ -9,7 +9,8 @@ colour per direction).  One step renders depth + normal + colour at all 300 traj
 Printed as one JSON line, with the roofline of the render kernel (algorithmic bytes per
 launch from the traced brick / bucket sets, divided by the launch duration measured with HIP
 events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
-Separately timed and reported beside it: integration ms/frame, three-level ICP ms/frame, the
+Separately timed and reported beside it: integration ms/frame, three-level ICP ms/frame
+(point-to-plane, and combined with the photometric term against a keyframe), the
 precision forms (f16 / i16 distance with u8 weights, fused from the same frames: rays/s and
 depth against the plain render), the serving workload (p50/p99 latency and capacity of
 the continuous-batching server against serial calls) and the view-dependent combined TSDF
@@ -252,7 +253,7 @@ def main():
                               frames_dev)
 
     # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
-    icp_ms = None
+    icp_ms = icp_rgb_ms = icp_rgb_err = None
     if not args.no_icp:
         icp_frames = list(range(5, n, max(1, n // 10)))[:10]
         tot = 0.0
@@ -277,6 +278,41 @@ def main():
             errs.append(float(np.linalg.norm(T_est[:3, 3])))
         icp_ms = 1e3 * tot / len(icp_frames)
         log(f"icp: {icp_ms:.2f} ms/frame, residual translation median {np.median(errs):.2e} m")
+        # combined geometric + photometric ICP against a keyframe (the textured frame of the
+        # last multiple of 10, Sec. 5.3), three levels, same offsets
+        tot_rgb, errs_rgb = 0.0, []
+        rng = np.random.default_rng(3)
+        for k in icp_frames:
+            T = poses[k]
+            kf = 10 * (k // 10) if k % 10 else max(0, k - 10)
+            T_kf = poses[kf]
+            f = synth.scenes.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012,
+                                          seed=9000 + k, device="cuda", texture_period=0.25)
+            fk = synth.scenes.render_frame(sc, cam, T_kf, device="cuda", texture_period=0.25)
+            live = torch.from_numpy(f["depth"]).to(dev)
+            live_rgb = torch.from_numpy(f["rgb"]).to(dev)
+            kf_rgb = torch.from_numpy(fk["rgb"]).to(dev)
+            dT0 = synth.perturb_pose(0.02, math.radians(2.0), rng)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            levels, refs = [], []
+            ri = dtsdf.intensity(kf_rgb)
+            for l in range(3):
+                c = dtsdf.level_camera(cam, l)
+                o = gm.render(c, T, outputs=("vertex", "normal", "mask"))
+                levels.append((o["vertex"], o["normal"], o["mask"], c))
+                refs.append((ri, c))
+                if l < 2:
+                    ri = dtsdf.intensity_downsample(ri)
+            T_est, _ = dtsdf.icp(live, cam, levels, dT0, live_rgb=live_rgb, ref_levels=refs,
+                                 T_ref_model=np.linalg.inv(T_kf) @ T)
+            torch.cuda.synchronize()
+            tot_rgb += time.perf_counter() - ta
+            errs_rgb.append(float(np.linalg.norm(T_est[:3, 3])))
+        icp_rgb_ms = 1e3 * tot_rgb / len(icp_frames)
+        icp_rgb_err = float(np.median(errs_rgb))
+        log(f"combined icp (keyframe): {icp_rgb_ms:.2f} ms/frame, residual translation "
+            f"median {icp_rgb_err:.2e} m")
 
     # ---- serving: render + Sim(3) ICP requests from four sensors on the tiny map -------
     serving = None
@@ -351,6 +387,8 @@ def main():
         "cpu_baseline": cpu,
         "integrate_ms_per_frame": integ_ms / n,
         "icp_ms_per_frame": icp_ms,
+        "icp_rgb_keyframe_ms_per_frame": icp_rgb_ms,
+        "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
         "hit_rate": float(np.mean(hits) / (H * W)),
         "samples_per_ray": per_ray,
         "samples_per_wave_max": per_wave_max,
@@ -371,7 +409,7 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     the volume is rendered at the frame's pose."""
     H, W = cam.height, cam.width
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    vol = dtsdf.Volume(gm, brick_capacity=1 << 18, hash_buckets=params.hash_buckets)
+    vol = dtsdf.Volume(gm, brick_capacity=1 << 18, hash_buckets=1 << 18)
     vol.combine(gm, cam, poses[0])          # first call gives every block its brick
     torch.cuda.synchronize()
     comb_ms, rend_ms = [], []
@@ -385,10 +423,20 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
         c_.synchronize()
         comb_ms.append(a_.elapsed_time(b_))
         rend_ms.append(b_.elapsed_time(c_))
-    # accuracy against the direct render at 10 poses
+    # algorithmic bytes of the volume render (traced brick / bucket sets, as for the direct
+    # render) and accuracy against the direct render, at 10 poses
+    vcap = 1 << 18
+    tb = torch.zeros(vcap, dtype=torch.uint8, device=dev)
+    tc = torch.zeros(vcap, dtype=torch.uint8, device=dev)
+    ts = torch.zeros(1 << 18, dtype=torch.uint8, device=dev)
+    vbytes = []
     dz_all, mm, one = [], [], []
     for T in poses[::30]:
         vol.combine(gm, cam, T)
+        tb.zero_(); tc.zero_(); ts.zero_()
+        vol.render(cam, T, out=dict(out, trace_bricks=tb, trace_color=tc, trace_slots=ts))
+        vbytes.append(int(tb.sum()) * BRICK_MARCH_BYTES + int(tc.sum()) * BRICK_COLOR_BYTES +
+                      int(ts.sum()) * BUCKET_BYTES + H * W * OUT_BYTES_PER_RAY)
         v = vol.render(cam, T, outputs=("depth", "mask"))
         d = gm.render(cam, T, outputs=("depth", "mask"))
         vd, dd = v["depth"].cpu().numpy(), d["depth"].cpu().numpy()
@@ -400,7 +448,7 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     del vol
     # frame loop with conditional recombination on a map fused frame by frame
     fm = dtsdf.Map(params)
-    fv = dtsdf.Volume(fm, brick_capacity=1 << 18, hash_buckets=params.hash_buckets)
+    fv = dtsdf.Volume(fm, brick_capacity=1 << 18, hash_buckets=1 << 18)
     pol = dtsdf.RecombinePolicy()
     n_re, loop_ms, direct_ms = 0, [], []
     last = None
@@ -432,6 +480,8 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     res = dict(
         combine_ms=float(np.mean(comb_ms)), combine_ms_max=float(np.max(comb_ms)),
         render_ms=float(np.mean(rend_ms)), render_rays_per_s=H * W / (np.mean(rend_ms) * 1e-3),
+        render_algorithmic_bytes=float(np.mean(vbytes)),
+        render_achieved_gbs=float(np.mean(vbytes)) / (np.mean(rend_ms) * 1e-3) / 1e9,
         vs_direct_depth_median_m=float(np.median(dz)),
         vs_direct_depth_over_1mm=float(np.mean(dz > 1e-3)),
         vs_direct_depth_over_1cm=float(np.mean(dz > 1e-2)),
