@@ -584,6 +584,96 @@ def solve_step(H: np.ndarray, g: np.ndarray) -> np.ndarray:
     return -scipy.linalg.cho_solve(c, g)
 
 
+# ----------------------------------------------------------------------------------------
+# Levenberg-Marquardt with Madsen's damping (Sec. 7) and scale anchoring (Sec. 6)
+# ----------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class LmState:
+    """Damping state of one Levenberg-Marquardt run (Madsen, Nielsen and Tingleff 2004):
+    mu, nu and the accepted iterate's normal equations H, g and error F = sum w r^2."""
+    tau: float = 1e-3
+    mu: float = 0.0
+    nu: float = 2.0
+    started: bool = False
+    H: Optional[np.ndarray] = None
+    g: Optional[np.ndarray] = None
+    F: float = 0.0
+    h: Optional[np.ndarray] = None       # last step, taken from the accepted iterate
+
+
+def lm_update(st: LmState, H: np.ndarray, g: np.ndarray, F: float) -> bool:
+    """Takes the normal equations (H = sum w J J^T, g = sum w J r, F = sum w r^2) at the
+    candidate iterate; returns True if the candidate is accepted.  The first call accepts and
+    sets mu = tau max(diag H).  Later calls compute the gain ratio
+    rho = (F_acc - F) / (h^T (mu h - g_acc)) of the last step h (the ratio of actual to
+    predicted reduction of the cost 1/2 sum w r^2); rho > 0 accepts the candidate and scales
+    mu by max(1/3, 1 - (2 rho - 1)^3) with nu = 2, otherwise mu *= nu and nu *= 2."""
+    if not st.started:
+        st.started = True
+        st.mu = st.tau * float(np.max(np.diag(H)))
+        st.nu = 2.0
+        st.H, st.g, st.F = H, g, F
+        return True
+    h = st.h
+    pred = float(h @ (st.mu * h - st.g))
+    rho = (st.F - F) / pred if pred > 0 else -1.0
+    if rho > 0:
+        st.mu *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+        st.nu = 2.0
+        st.H, st.g, st.F = H, g, F
+        return True
+    st.mu *= st.nu
+    st.nu *= 2.0
+    return False
+
+
+def lm_step(st: LmState) -> np.ndarray:
+    """The next step from the accepted iterate: (H + mu I) h = -g (Cholesky)."""
+    A = st.H + st.mu * np.eye(st.H.shape[0])
+    st.h = solve_step(A, st.g)
+    return st.h
+
+
+def icp_lm(live_depth: np.ndarray, live_cam, model_levels, dT0: np.ndarray, dim: int = 7,
+           iters=(10, 5, 4), params: IcpParams = IcpParams(), tau: float = 1e-3,
+           min_step: float = 1e-6, depth_scale: float = 1.0, min_inliers_per_dim: int = 64):
+    """Coarse-to-fine point-to-plane ICP solved by Levenberg-Marquardt with Madsen's damping
+    (Sec. 7); the damping restarts at every level.  Each iteration associates and reduces at
+    the candidate pose, accepts or rejects it, and steps from the accepted pose; the result
+    is the last accepted pose.  With tau = 0 it is the Gauss-Newton iteration of icp()."""
+    L = len(model_levels)
+    pyr = depth_pyramid(live_depth, L)
+    dT = np.array(dT0, np.float64)
+    log = []
+    for l in reversed(range(L)):
+        V, N, ok = vertex_normal_map(pyr[l], live_cam.level(l), depth_scale)
+        mV, mN, mM, mcam = model_levels[l]
+        st = LmState(tau=tau)
+        cand = dT.copy()
+        for _ in range(iters[l]):
+            H, g, err, cnt = associate_reduce(V, N, ok, mV, mN, mM, mcam, cand, dim, params)
+            if cnt < min_inliers_per_dim * dim:
+                log.append(dict(level=l, status="degenerate", inliers=cnt))
+                break
+            acc = lm_update(st, H, g, err)
+            if acc:
+                dT = cand
+            h = lm_step(st)
+            cand = exp_map(h) @ dT
+            log.append(dict(level=l, inliers=cnt, err=err, accepted=acc, mu=st.mu,
+                            step=float(np.linalg.norm(h))))
+            if np.linalg.norm(h) < min_step:
+                break
+    return dT, log
+
+
+def anchored_log_scales(log_scales: Sequence[float], anchor: float) -> np.ndarray:
+    """Scale anchoring (Sec. 6, eq. scale_anchor, read as a difference of log scales): the
+    compensated log scale of each sensor is its estimate minus the anchor sensor's."""
+    return np.asarray(log_scales, np.float64) - float(anchor)
+
+
 def icp_rgb(live_depth: np.ndarray, live_rgb: np.ndarray, live_cam, model_levels,
             ref_levels, T_ref_model: np.ndarray, dT0: np.ndarray, dim: int = 6,
             iters=(10, 5, 4), params: IcpParams = IcpParams(), lam: float = 0.1,
