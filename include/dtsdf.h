@@ -271,6 +271,33 @@ dtsdf_status icp_step_rgb(const dtsdf_image* live, const dtsdf_image* model,
                           const dtsdf_icp_params* params, double T_model_live[16],
                           dtsdf_icp_result* result, void* stream);
 
+/* Levenberg-Marquardt state of one registration run (Sec. 7: LM with the damping scheme of
+ * Madsen, Nielsen and Tingleff).  The caller sets T (the prior), tau (mu starts at tau times
+ * the largest diagonal entry of the first H; 1e-3 suggested) and started = 0; every
+ * icp_step_lm reduces at T, accepts or rejects it by the gain ratio
+ * rho = (F_acc - F) / (h^T (mu h - g_acc)) (rho > 0: accept, mu *= max(1/3, 1 - (2 rho - 1)^3),
+ * nu = 2; else mu *= nu, nu *= 2), solves (H_acc + mu I) h = -g_acc and sets T = exp(h) T_acc.
+ * The result of the run is T_acc. */
+typedef struct {
+  double T[16];        /* candidate pose (model <- live) the next call evaluates */
+  double T_acc[16];    /* last accepted pose */
+  double H[49];        /* normal equations at T_acc, dim x dim row-major */
+  double g[7];
+  double F;            /* sum w r^2 at T_acc */
+  double h[7];         /* last step */
+  double mu, nu, tau;
+  int32_t started;
+  int32_t accepted;    /* out: the last call accepted its candidate */
+} dtsdf_lm_state;
+
+/* One Levenberg-Marquardt iteration (geometric, or combined with `photo`); see
+ * dtsdf_lm_state.  DTSDF_E_DEGENERATE (state unchanged) if there are too few inliers or the
+ * damped system is not positive definite.  Synchronises the stream. */
+dtsdf_status icp_step_lm(const dtsdf_image* live, const dtsdf_image* model,
+                         const dtsdf_photo* photo, int32_t dim,
+                         const dtsdf_icp_params* params, dtsdf_lm_state* state,
+                         dtsdf_icp_result* result, void* stream);
+
 /* Grey values (0.299 R + 0.587 G + 0.114 B) / 255 of a device H*W*3 uint8 image. */
 dtsdf_status dtsdf_intensity(const uint8_t* rgb, int32_t width, int32_t height, float* out,
                              void* stream);

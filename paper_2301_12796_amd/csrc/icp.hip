@@ -331,6 +331,138 @@ __device__ void exp_sim3(const double* xi, int dim, double* E) {
   E[15] = 1.0;
 }
 
+// Solves (A) xi = -g by Cholesky (A symmetric DIM x DIM); false if A is not positive definite.
+template <int DIM>
+__device__ bool cholesky_solve(const double* A, const double* g, double* xi) {
+  double L[DIM * DIM], y[DIM];
+  for (int jj = 0; jj < DIM; ++jj) {
+    double d = A[jj * DIM + jj];
+    for (int k = 0; k < jj; ++k) d -= L[jj * DIM + k] * L[jj * DIM + k];
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d);
+    L[jj * DIM + jj] = ljj;
+    for (int i = jj + 1; i < DIM; ++i) {
+      double v = A[i * DIM + jj];
+      for (int k = 0; k < jj; ++k) v -= L[i * DIM + k] * L[jj * DIM + k];
+      L[i * DIM + jj] = v / ljj;
+    }
+  }
+  for (int i = 0; i < DIM; ++i) {   // L y = -g
+    double v = -g[i];
+    for (int k = 0; k < i; ++k) v -= L[i * DIM + k] * y[k];
+    y[i] = v / L[i * DIM + i];
+  }
+  for (int i = DIM - 1; i >= 0; --i) {   // L^T xi = y
+    double v = y[i];
+    for (int k = i + 1; k < DIM; ++k) v -= L[k * DIM + i] * xi[k];
+    xi[i] = v / L[i * DIM + i];
+  }
+  return true;
+}
+
+// One Levenberg-Marquardt iteration with Madsen's damping (Sec. 7) for a request whose sums
+// were taken at the candidate pose *j.a.pose: accept or reject the candidate by the gain
+// ratio, then step from the accepted pose, (H + mu I) h = -g, and write the next candidate.
+template <int DIM>
+__device__ void solve_lm_one(const float* __restrict__ partials, const IcpJob& j,
+                             dtsdf_lm_state* st) {
+  constexpr int NS = Sizes<DIM>::NS;
+  constexpr int NH = Sizes<DIM>::NH;
+  __shared__ double sums[kNSMax];
+  if (threadIdx.x < NS) {
+    double v = 0.0;
+    for (int c = 0; c < kChunks; ++c)
+      v += (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2] +
+           (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2 + 1];
+    sums[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double H[DIM * DIM], g[DIM], h[7] = {0, 0, 0, 0, 0, 0, 0};
+  int s = 0;
+  for (int r = 0; r < DIM; ++r)
+    for (int c = r; c < DIM; ++c) {
+      H[r * DIM + c] = sums[s];
+      H[c * DIM + r] = sums[s];
+      ++s;
+    }
+  for (int r = 0; r < DIM; ++r) g[r] = sums[NH + r];
+  const double F = sums[NH + DIM];
+  const double* cand = j.a.pose;
+  int status = sums[NH + DIM + 1] < (double)j.min_inliers * DIM ? 1 : 0;
+  double step = 0.0;
+  st->accepted = 0;
+  if (status == 0) {
+    bool acc = false;
+    if (!st->started) {
+      double dmax = 0.0;
+      for (int r = 0; r < DIM; ++r) dmax = fmax(dmax, H[r * DIM + r]);
+      st->started = 1;
+      st->mu = st->tau * dmax;
+      st->nu = 2.0;
+      acc = true;
+    } else {
+      double pred = 0.0;   // h^T (mu h - g_acc): the predicted reduction of sum w r^2
+      for (int r = 0; r < DIM; ++r) pred += st->h[r] * (st->mu * st->h[r] - st->g[r]);
+      const double rho = pred > 0.0 ? (st->F - F) / pred : -1.0;
+      if (rho > 0.0) {
+        const double q = 2.0 * rho - 1.0;
+        st->mu *= fmax(1.0 / 3.0, 1.0 - q * q * q);
+        st->nu = 2.0;
+        acc = true;
+      } else {
+        st->mu *= st->nu;
+        st->nu *= 2.0;
+      }
+    }
+    if (acc) {
+      for (int k = 0; k < 49; ++k) st->H[k] = k < DIM * DIM ? H[k] : 0.0;
+      for (int k = 0; k < 7; ++k) st->g[k] = k < DIM ? g[k] : 0.0;
+      st->F = F;
+      for (int k = 0; k < 16; ++k) st->T_acc[k] = cand[k];
+      st->accepted = 1;
+    }
+    double A[DIM * DIM], ga[DIM];
+    for (int k = 0; k < DIM * DIM; ++k) A[k] = st->H[k];
+    for (int r = 0; r < DIM; ++r) {
+      A[r * DIM + r] += st->mu;
+      ga[r] = st->g[r];
+    }
+    if (cholesky_solve<DIM>(A, ga, h)) {
+      for (int r = 0; r < DIM; ++r) {
+        st->h[r] = h[r];
+        step += h[r] * h[r];
+      }
+      step = sqrt(step);
+      double E[16];
+      exp_sim3(h, DIM, E);
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          double v = 0.0;
+          for (int k = 0; k < 4; ++k) v += E[4 * r + k] * st->T_acc[4 * k + c];
+          st->T[4 * r + c] = v;
+        }
+    } else {
+      status = 2;
+    }
+  }
+  if (j.result) {
+    dtsdf_icp_result* res = j.result;
+    for (int k = 0; k < 49; ++k) res->H[k] = 0.0;
+    for (int k = 0; k < 7; ++k) res->g[k] = 0.0;
+    for (int r = 0; r < DIM; ++r) {
+      for (int c = 0; c < DIM; ++c) res->H[r * DIM + c] = H[r * DIM + c];
+      res->g[r] = g[r];
+    }
+    for (int i = 0; i < 7; ++i) res->xi[i] = h[i];
+    res->error = F;
+    res->inliers = (int64_t)sums[NH + DIM + 1];
+    res->photometric = (int32_t)sums[NH + DIM + 2];
+    res->step_norm = step;
+    res->status = status == 0 ? DTSDF_OK : DTSDF_E_DEGENERATE;
+  }
+}
+
 template <int DIM>
 __device__ void solve_one(const float* __restrict__ partials, const IcpJob& j) {
   constexpr int NS = Sizes<DIM>::NS;
@@ -430,6 +562,13 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batch_k(const IcpJob* _
   }
 }
 
+__global__ __launch_bounds__(64) void solve_lm_k(const IcpJob* __restrict__ jobs,
+                                                 const float* __restrict__ partials,
+                                                 dtsdf_lm_state* st) {
+  if (jobs[0].dim == 6) solve_lm_one<6>(partials, jobs[0], st);
+  else solve_lm_one<7>(partials, jobs[0], st);
+}
+
 __global__ __launch_bounds__(64) void solve_batch_k(const IcpJob* __restrict__ jobs,
                                                     const float* __restrict__ partials) {
   const IcpJob& j = jobs[blockIdx.x];
@@ -513,7 +652,8 @@ struct Scratch {
 constexpr size_t kOffPose = (sizeof(IcpJob) + 63) & ~(size_t)63;
 constexpr size_t kOffActive = kOffPose + 16 * sizeof(double);
 constexpr size_t kOffResult = (kOffActive + sizeof(int32_t) + 63) & ~(size_t)63;
-constexpr size_t kScratchBytes = kOffResult + sizeof(dtsdf_icp_result);
+constexpr size_t kOffLm = (kOffResult + sizeof(dtsdf_icp_result) + 63) & ~(size_t)63;
+constexpr size_t kScratchBytes = kOffLm + sizeof(dtsdf_lm_state);
 
 std::mutex g_mu;
 std::vector<Scratch> g_scratch;
@@ -611,6 +751,44 @@ extern "C" dtsdf_status icp_step_rgb(const dtsdf_image* live, const dtsdf_image*
   if (out) *out = r;
   if (r.status != DTSDF_OK) return DTSDF_E_DEGENERATE;
   std::memcpy(T, s->host + kOffPose, 16 * sizeof(double));
+  return DTSDF_OK;
+}
+
+extern "C" dtsdf_status icp_step_lm(const dtsdf_image* live, const dtsdf_image* model,
+                                    const dtsdf_photo* photo, int32_t dim,
+                                    const dtsdf_icp_params* p, dtsdf_lm_state* state,
+                                    dtsdf_icp_result* out, void* stream) {
+  if (!state || !(state->tau >= 0.0)) return DTSDF_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Scratch* s = nullptr;
+  dtsdf_status st = get_scratch(&s);
+  if (st != DTSDF_OK) return st;
+  IcpJob job;
+  if (!make_job(live, model, photo, dim, p, reinterpret_cast<double*>(s->dev + kOffPose),
+                reinterpret_cast<int32_t*>(s->dev + kOffActive), 0.0,
+                reinterpret_cast<dtsdf_icp_result*>(s->dev + kOffResult), job))
+    return DTSDF_E_INVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  std::memcpy(s->host, &job, sizeof(job));
+  std::memcpy(s->host + kOffPose, state->T, 16 * sizeof(double));
+  const int32_t one = 1;
+  std::memcpy(s->host + kOffActive, &one, sizeof(one));
+  std::memcpy(s->host + kOffLm, state, sizeof(*state));
+  DTSDF_HIP(hipMemcpyAsync(s->dev, s->host, kScratchBytes, hipMemcpyHostToDevice, hs));
+  hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, 1), dim3(kReduceThreads), 0, hs,
+                     reinterpret_cast<const IcpJob*>(s->dev), s->partials);
+  hipLaunchKernelGGL(solve_lm_k, dim3(1), dim3(64), 0, hs,
+                     reinterpret_cast<const IcpJob*>(s->dev), s->partials,
+                     reinterpret_cast<dtsdf_lm_state*>(s->dev + kOffLm));
+  DTSDF_HIP(hipGetLastError());
+  DTSDF_HIP(hipMemcpyAsync(s->host + kOffResult, s->dev + kOffResult, kScratchBytes - kOffResult,
+                           hipMemcpyDeviceToHost, hs));
+  DTSDF_HIP(hipStreamSynchronize(hs));
+  dtsdf_icp_result r;
+  std::memcpy(&r, s->host + kOffResult, sizeof(r));
+  if (out) *out = r;
+  if (r.status != DTSDF_OK) return DTSDF_E_DEGENERATE;
+  std::memcpy(state, s->host + kOffLm, sizeof(*state));
   return DTSDF_OK;
 }
 

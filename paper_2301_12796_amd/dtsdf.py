@@ -112,6 +112,14 @@ class _IcpReq(ctypes.Structure):
                 ("photo", ctypes.c_void_p)]
 
 
+class _LmState(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double * 16), ("T_acc", ctypes.c_double * 16),
+                ("H", ctypes.c_double * 49), ("g", ctypes.c_double * 7), ("F", ctypes.c_double),
+                ("h", ctypes.c_double * 7), ("mu", ctypes.c_double), ("nu", ctypes.c_double),
+                ("tau", ctypes.c_double), ("started", ctypes.c_int32),
+                ("accepted", ctypes.c_int32)]
+
+
 ICP_RESULT_BYTES = ctypes.sizeof(_IcpResult)
 
 
@@ -130,7 +138,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_render", "dtsdf_render_batch", "dtsdf_export", "dtsdf_import",
             "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
-            "icp_step_rgb", "dtsdf_intensity", "dtsdf_intensity_downsample",
+            "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -153,6 +161,9 @@ _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                               ctypes.POINTER(_Photo), ctypes.c_int32,
                               ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
+_lib.icp_step_lm.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
+                             ctypes.POINTER(_Photo), ctypes.c_int32, ctypes.POINTER(_IcpParams),
+                             ctypes.POINTER(_LmState), ctypes.POINTER(_IcpResult), _V]
 _lib.dtsdf_intensity.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_intensity_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_volume_create.argtypes = [_V, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_V)]
@@ -475,12 +486,8 @@ def intensity_downsample(img: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
-def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
-             model_vertex: torch.Tensor, model_normal: torch.Tensor,
-             model_mask: Optional[torch.Tensor], model_cam, T_model_live, dim: int = 6,
-             params: IcpParams = IcpParams(), stream=None, photo: Optional[Photo] = None):
-    """One ICP Gauss-Newton step (with ``photo``: combined geometric + photometric);
-    returns (status, updated T (4x4), result dict)."""
+def _icp_images(live_vertex, live_normal, live_cam, model_vertex, model_normal, model_mask,
+                model_cam, params):
     Hl, Wl = int(live_cam.height), int(live_cam.width)
     Hm, Wm = int(model_cam.height), int(model_cam.width)
     live = _Image(_dev_ptr(live_vertex, torch.float32, 3 * Hl * Wl),
@@ -491,6 +498,17 @@ def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
                    _intr(model_cam))
     p = _IcpParams(params.max_dist, params.max_angle_deg, params.weight, params.z_min,
                    params.min_inliers_per_dim, int(params.compensated))
+    return live, model, p
+
+
+def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
+             model_vertex: torch.Tensor, model_normal: torch.Tensor,
+             model_mask: Optional[torch.Tensor], model_cam, T_model_live, dim: int = 6,
+             params: IcpParams = IcpParams(), stream=None, photo: Optional[Photo] = None):
+    """One ICP Gauss-Newton step (with ``photo``: combined geometric + photometric);
+    returns (status, updated T (4x4), result dict)."""
+    live, model, p = _icp_images(live_vertex, live_normal, live_cam, model_vertex,
+                                 model_normal, model_mask, model_cam, params)
     T = _pose(T_model_live)
     r = _IcpResult()
     ph = ctypes.byref(photo.c_struct(live_cam)) if photo is not None else None
@@ -501,6 +519,84 @@ def icp_step(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
                g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm,
                photometric=r.photometric)
     return status, np.array(T[:]).reshape(4, 4), res
+
+
+class LmState:
+    """Levenberg-Marquardt state of one registration run (see dtsdf_lm_state): set the prior
+    pose and tau, then call icp_step_lm until the step is small; the result is T_acc."""
+
+    def __init__(self, T0, tau: float = 1e-3):
+        self.c = _LmState()
+        self.c.T[:] = [float(v) for v in np.asarray(T0, np.float64).ravel()]
+        self.c.T_acc[:] = self.c.T[:]
+        self.c.tau = tau
+        self.c.nu = 2.0
+
+    @property
+    def T(self) -> np.ndarray:
+        return np.array(self.c.T[:]).reshape(4, 4)
+
+    @property
+    def T_acc(self) -> np.ndarray:
+        return np.array(self.c.T_acc[:]).reshape(4, 4)
+
+    @property
+    def mu(self) -> float:
+        return self.c.mu
+
+    @property
+    def accepted(self) -> bool:
+        return bool(self.c.accepted)
+
+
+def icp_step_lm(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
+                model_vertex: torch.Tensor, model_normal: torch.Tensor,
+                model_mask: Optional[torch.Tensor], model_cam, state: LmState, dim: int = 7,
+                params: IcpParams = IcpParams(), stream=None, photo: Optional[Photo] = None):
+    """One Levenberg-Marquardt ICP iteration (Sec. 7) at state.T; updates ``state`` and
+    returns (status, result dict)."""
+    live, model, p = _icp_images(live_vertex, live_normal, live_cam, model_vertex,
+                                 model_normal, model_mask, model_cam, params)
+    r = _IcpResult()
+    ph = ctypes.byref(photo.c_struct(live_cam)) if photo is not None else None
+    status = _lib.icp_step_lm(ctypes.byref(live), ctypes.byref(model), ph, dim, ctypes.byref(p),
+                              ctypes.byref(state.c), ctypes.byref(r), _stream(stream))
+    _check(status, "icp_step_lm", allow=(E_DEGENERATE,))
+    res = dict(xi=np.array(r.xi[:dim]), H=np.array(r.H[:dim * dim]).reshape(dim, dim),
+               g=np.array(r.g[:dim]), error=r.error, inliers=r.inliers, step_norm=r.step_norm,
+               photometric=r.photometric)
+    return status, res
+
+
+def icp_lm(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 7,
+           iters=(10, 5, 4), params: IcpParams = IcpParams(), tau: float = 1e-3,
+           min_step: float = 1e-6, depth_scale: float = 1.0, stream=None):
+    """Coarse-to-fine ICP solved by Levenberg-Marquardt with Madsen's damping (Sec. 7); the
+    damping restarts at every level and each level starts from the previous level's
+    accepted pose."""
+    L = len(model_levels)
+    pyr = [live_depth]
+    for _ in range(1, L):
+        pyr.append(depth_downsample(pyr[-1], stream=stream))
+    T = np.array(T0, np.float64)
+    log = []
+    for l in reversed(range(L)):
+        cam_l = level_camera(live_cam, l)
+        v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
+        mv, mn, mm, mcam = model_levels[l]
+        st = LmState(T, tau)
+        for _ in range(iters[l]):
+            status, res = icp_step_lm(v, n, cam_l, mv, mn, mm, mcam, st, dim, params, stream)
+            if status != OK:
+                log.append(dict(level=l, status="degenerate", inliers=res["inliers"],
+                                err=res["error"]))
+                break
+            log.append(dict(level=l, inliers=res["inliers"], err=res["error"],
+                            accepted=st.accepted, mu=st.mu, step=res["step_norm"]))
+            if res["step_norm"] < min_step:
+                break
+        T = st.T_acc
+    return T, log
 
 
 @dataclasses.dataclass
