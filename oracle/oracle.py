@@ -11,8 +11,12 @@ module.  It shares no code with the HIP library; both sides only consume the see
   (eq. ICP_geometric_dx; Sim(3): eq. sim3_derivative), the normal equations
   (eq. ICP_Hessian), the Cholesky solve (eq. ICP_solution) and the left-multiplied update
   (eq. deltaT_update); the photometric terms of combined ICP (eq. combined_icp) against a
-  reference grey image with a keyframe offset (eq. keyframe_icp and its derivative).  The exponential maps are the matrix exponential of the 4x4 generator
-  (scipy.linalg.expm), the plain definition of exp on se(3) and sim(3).
+  reference grey image with a keyframe offset (eq. keyframe_icp and its derivative);
+  Levenberg-Marquardt with Madsen's damping (Sec. 7) and scale anchoring (Sec. 6).  The
+  exponential maps are the matrix exponential of the 4x4 generator (scipy.linalg.expm), the
+  plain definition of exp on se(3) and sim(3).
+* Input preprocessing (Sec. 7, Sec. 8 parameters): the depth support filter and the
+  bilateral depth and normal filters by their definitions; the post-fusion error (Sec. 8).
 
 Parameters are passed as float32-representable values (``f32``) so that both implementations
 compare against exactly the same thresholds.
@@ -420,6 +424,85 @@ def vertex_normal_map(depth: np.ndarray, cam, depth_scale: float = 1.0):
     N[1:-1, 1:-1] = np.where(inner[..., None], n, 0.0)
     ok[1:-1, 1:-1] = inner
     return V, N, ok
+
+
+def _shifted(A: np.ndarray, du: int, dv: int) -> np.ndarray:
+    """A[v + dv, u + du] with zeros outside the image."""
+    H, W = A.shape[:2]
+    out = np.zeros_like(A)
+    ys, yd = (slice(dv, H), slice(0, H - dv)) if dv >= 0 else (slice(0, H + dv), slice(-dv, H))
+    xs, xd = (slice(du, W), slice(0, W - du)) if du >= 0 else (slice(0, W + du), slice(-du, W))
+    out[yd, xd] = A[ys, xs]
+    return out
+
+
+def depth_support_filter(depth: np.ndarray, support_rel: float = 0.02,
+                         min_support: int = 2) -> np.ndarray:
+    """Depth outlier filter (Sec. 7): a pixel keeps its depth only if at least ``min_support``
+    of its eight neighbours hold a depth that supports it, |D(q) - D(p)| <= support_rel D(p);
+    discarded pixels become 0."""
+    D = np.asarray(depth, np.float64)
+    cnt = np.zeros(D.shape, np.int64)
+    for dv in (-1, 0, 1):
+        for du in (-1, 0, 1):
+            if du == 0 and dv == 0:
+                continue
+            Q = _shifted(D, du, dv)
+            cnt += (Q > 0) & (np.abs(Q - D) <= support_rel * D)
+    return np.where((D > 0) & (cnt >= min_support), D, 0.0)
+
+
+def bilateral_depth(depth: np.ndarray, sigma_d: float = 5.0, sigma_r: float = 0.025,
+                    radius: int = 5) -> np.ndarray:
+    """Bilateral depth filter (Sec. 8 parameters; Tomasi and Manduchi's definition): the
+    weighted mean over the valid pixels q of the (2 radius + 1)^2 window of p with weights
+    exp(-|q - p|^2 / (2 sigma_d^2)) exp(-(D(q) - D(p))^2 / (2 sigma_r^2)); invalid pixels
+    (depth 0) stay 0 and contribute nothing."""
+    D = np.asarray(depth, np.float64)
+    num = np.zeros_like(D)
+    den = np.zeros_like(D)
+    for dv in range(-radius, radius + 1):
+        for du in range(-radius, radius + 1):
+            Q = _shifted(D, du, dv)
+            w = (math.exp(-(du * du + dv * dv) / (2.0 * sigma_d ** 2)) *
+                 np.exp(-(Q - D) ** 2 / (2.0 * sigma_r ** 2)) * (Q > 0))
+            num += w * Q
+            den += w
+    return np.where(D > 0, num / np.where(den > 0, den, 1.0), 0.0)
+
+
+def bilateral_normal(N: np.ndarray, sigma_d: float = 2.5, sigma_r_deg: float = 5.0,
+                     radius: int = 5) -> np.ndarray:
+    """Bilateral normal filter (Sec. 7, Sec. 8 parameters): the normalised weighted sum of
+    the valid normals of the window with weights exp(-|q - p|^2 / (2 sigma_d^2))
+    exp(-angle(n_q, n_p)^2 / (2 sigma_r^2)), the angle in degrees; pixels without a normal
+    (all zero) stay zero and contribute nothing."""
+    N = np.asarray(N, np.float64)
+    valid = np.any(N != 0, axis=-1)
+    acc = np.zeros_like(N)
+    for dv in range(-radius, radius + 1):
+        for du in range(-radius, radius + 1):
+            Q = _shifted(N, du, dv)
+            qv = _shifted(valid, du, dv)
+            c = np.clip((N * Q).sum(-1), -1.0, 1.0)
+            ang = np.degrees(np.arccos(c))
+            w = (math.exp(-(du * du + dv * dv) / (2.0 * sigma_d ** 2)) *
+                 np.exp(-ang ** 2 / (2.0 * sigma_r_deg ** 2)) * qv)
+            acc += w[..., None] * Q
+    ln = np.linalg.norm(acc, axis=-1)
+    return np.where((valid & (ln > 0))[..., None], acc / np.where(ln > 0, ln, 1.0)[..., None],
+                    0.0)
+
+
+def post_fusion_mae(rendered: np.ndarray, measured: np.ndarray):
+    """Geometric post-fusion error (Sec. 8): the mean absolute difference between the depth
+    rendered at a pose after fusion and the input depth of that pose, over the pixels where
+    both are valid.  Returns (mean, pixel count)."""
+    r = np.asarray(rendered, np.float64)
+    m = np.asarray(measured, np.float64)
+    both = (r > 0) & (m > 0)
+    n = int(both.sum())
+    return (float(np.abs(r - m)[both].sum() / n) if n else 0.0), n
 
 
 @dataclasses.dataclass
