@@ -389,6 +389,42 @@ typedef struct {
 dtsdf_status dtsdf_recombine_decide(dtsdf_recombine_state* state, const double T_world_cam[16],
                                     int32_t* recombine);
 
+/* ---- Input preprocessing (Sec. 7; parameters of Sec. 8) and the post-fusion error ---- */
+
+typedef struct {
+  float support_rel;    /* a neighbour q supports pixel p if |D(q) - D(p)| <= support_rel * D(p)
+                           (suggested 0.02) */
+  int32_t min_support;  /* p keeps its depth only with >= min_support supporting pixels among
+                           its eight neighbours (Sec. 7: 2); 0 switches the test off; <= 8 */
+  float sigma_d;        /* bilateral depth filter: spatial sigma [px] (Sec. 8: 5.0) */
+  float sigma_r;        /* range sigma [m] (Sec. 8: 0.025) */
+  int32_t radius;       /* window half-size [px], 0..8 (Sec. 8: 5); 0 switches the bilateral
+                           filter off */
+} dtsdf_depth_filter_params;
+
+/* Depth outlier (support) filter followed by the bilateral depth filter: out(p) = 0 where p
+ * has no depth or too little support, else the mean of the supported depths q of the window
+ * weighted by exp(-|q - p|^2 / (2 sigma_d^2)) exp(-(D(q) - D(p))^2 / (2 sigma_r^2)).  Device
+ * H*W float32 images, depth_in != depth_out.  DTSDF_E_INVAL for bad sizes or parameters. */
+dtsdf_status dtsdf_depth_filter(const float* depth_in, int32_t width, int32_t height,
+                                const dtsdf_depth_filter_params* params, float* depth_out,
+                                void* stream);
+
+/* Bilateral normal filter (Sec. 7; Sec. 8: sigma_d 2.5 px, sigma_r 5.0 degrees, radius 5):
+ * normalised sum of the window's normals weighted by exp(-|q - p|^2 / (2 sigma_d^2))
+ * exp(-angle(n_q, n_p)^2 / (2 sigma_r^2)), the angle in degrees.  Device planar (3, H, W)
+ * float32 maps as written by dtsdf_vertex_normal (zero = no normal, stays zero), in != out,
+ * radius 0..8. */
+dtsdf_status dtsdf_normal_filter(const float* normal_in, int32_t width, int32_t height,
+                                 float sigma_d, float sigma_r_deg, int32_t radius,
+                                 float* normal_out, void* stream);
+
+/* Post-fusion error (Sec. 8): out[0] = sum |rendered - measured| and out[1] = the number of
+ * pixels where both depths are > 0 (device float64[2]); the mean absolute error is
+ * out[0] / out[1].  Deterministic (fixed summation order). */
+dtsdf_status dtsdf_depth_error(const float* rendered, const float* measured, int32_t width,
+                               int32_t height, double* out, void* stream);
+
 const char* dtsdf_status_string(dtsdf_status status);
 
 #ifdef __cplusplus

@@ -120,6 +120,12 @@ class _LmState(ctypes.Structure):
                 ("accepted", ctypes.c_int32)]
 
 
+class _DepthFilterParams(ctypes.Structure):
+    _fields_ = [("support_rel", ctypes.c_float), ("min_support", ctypes.c_int32),
+                ("sigma_d", ctypes.c_float), ("sigma_r", ctypes.c_float),
+                ("radius", ctypes.c_int32)]
+
+
 ICP_RESULT_BYTES = ctypes.sizeof(_IcpResult)
 
 
@@ -139,6 +145,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
+            "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -164,6 +171,11 @@ _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
 _lib.icp_step_lm.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                              ctypes.POINTER(_Photo), ctypes.c_int32, ctypes.POINTER(_IcpParams),
                              ctypes.POINTER(_LmState), ctypes.POINTER(_IcpResult), _V]
+_lib.dtsdf_depth_filter.argtypes = [_V, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(_DepthFilterParams), _V, _V]
+_lib.dtsdf_normal_filter.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_int32, _V, _V]
+_lib.dtsdf_depth_error.argtypes = [_V, _V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_intensity.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_intensity_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.dtsdf_volume_create.argtypes = [_V, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_V)]
@@ -466,6 +478,56 @@ class Photo:
         return _Photo(_dev_ptr(self.live_intensity, torch.float32, Hl * Wl),
                       _dev_ptr(self.ref_intensity, torch.float32, Hr * Wr),
                       _intr(self.ref_cam), _pose(self.T_ref_model), self.lam, self.max_error)
+
+
+@dataclasses.dataclass
+class DepthFilterParams:
+    """Depth support filter + bilateral depth filter (see dtsdf_depth_filter_params); the
+    defaults are the values of Sec. 7 and Sec. 8 (support_rel is not given there)."""
+    support_rel: float = 0.02
+    min_support: int = 2
+    sigma_d: float = 5.0
+    sigma_r: float = 0.025
+    radius: int = 5
+
+
+def depth_filter(depth: torch.Tensor, params: DepthFilterParams = DepthFilterParams(),
+                 stream=None) -> torch.Tensor:
+    """Support-filtered and bilaterally filtered copy of an (H, W) float32 device depth."""
+    H, W = int(depth.shape[0]), int(depth.shape[1])
+    out = torch.empty((H, W), dtype=torch.float32, device=depth.device)
+    p = _DepthFilterParams(params.support_rel, params.min_support, params.sigma_d,
+                           params.sigma_r, params.radius)
+    _check(_lib.dtsdf_depth_filter(_dev_ptr(depth, torch.float32, H * W), W, H, ctypes.byref(p),
+                                   _dev_ptr(out, torch.float32), _stream(stream)),
+           "dtsdf_depth_filter")
+    return out
+
+
+def normal_filter(normal: torch.Tensor, sigma_d: float = 2.5, sigma_r_deg: float = 5.0,
+                  radius: int = 5, stream=None) -> torch.Tensor:
+    """Bilaterally filtered copy of a planar (3, H, W) float32 device normal map."""
+    H, W = int(normal.shape[1]), int(normal.shape[2])
+    out = torch.empty_like(normal)
+    _check(_lib.dtsdf_normal_filter(_dev_ptr(normal, torch.float32, 3 * H * W), W, H, sigma_d,
+                                    sigma_r_deg, radius, _dev_ptr(out, torch.float32),
+                                    _stream(stream)), "dtsdf_normal_filter")
+    return out
+
+
+def depth_error(rendered: torch.Tensor, measured: torch.Tensor, stream=None):
+    """Post-fusion error (Sec. 8): (mean |rendered - measured| over pixels where both are
+    valid, that pixel count)."""
+    H, W = int(rendered.shape[0]), int(rendered.shape[1])
+    if tuple(measured.shape) != (H, W):
+        raise ValueError("depth images differ in shape")
+    out = torch.zeros(2, dtype=torch.float64, device=rendered.device)
+    _check(_lib.dtsdf_depth_error(_dev_ptr(rendered, torch.float32, H * W),
+                                  _dev_ptr(measured, torch.float32, H * W), W, H,
+                                  _dev_ptr(out, torch.float64), _stream(stream)),
+           "dtsdf_depth_error")
+    s, n = out.cpu().tolist()
+    return (s / n if n else 0.0), int(n)
 
 
 def intensity(rgb: torch.Tensor, stream=None) -> torch.Tensor:
