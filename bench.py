@@ -9,7 +9,9 @@ colour per direction).  One step renders depth + normal + colour at all 300 traj
 Printed as one JSON line, with the roofline of the render kernel (algorithmic bytes per
 launch from the traced brick / bucket sets, divided by the launch duration measured with HIP
 events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
-Separately timed and reported beside it: integration ms/frame, three-level ICP ms/frame
+Separately timed and reported beside it: integration ms/frame, the geometric post-fusion error
+(render at every fused pose against its input depth), the live-frame preprocessing (depth
+filter, normals, normal filter), three-level ICP ms/frame on preprocessed live frames
 (point-to-plane, and combined with the photometric term against a keyframe), the
 precision forms (f16 / i16 distance with u8 weights, fused from the same frames: rays/s and
 depth against the plain render), the serving workload (p50/p99 latency and capacity of
@@ -22,6 +24,7 @@ scales anchored to the first sensor).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -147,9 +150,13 @@ def main():
     n_bd, n_cd, n_sl = [], [], []
     hits = []
     counts = []
-    for T in poses:
+    mae = []
+    for j, T in enumerate(poses):
         tb.zero_(); tc.zero_(); ts.zero_()
         gm.render(cam, T, out=traced)
+        # geometric post-fusion error (Sec. 8): the render at a fused frame's pose against
+        # that frame's input depth
+        mae.append(dtsdf.depth_error(out["depth"], frames_dev[j][0])[0])
         nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
         n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
         hits.append(int(out["mask"].sum()))
@@ -165,6 +172,32 @@ def main():
     per_ray = dict(zip(["eval", "skip", "absent", "refine"], cnt[0].round(2).tolist()))
     per_wave_max = dict(zip(["eval", "skip", "absent", "refine"], cnt[1].round(2).tolist()))
     log(f"per ray mean {per_ray}; per 8x8 wave, mean of the lane maximum {per_wave_max}")
+    log(f"post-fusion depth MAE {np.mean(mae) * 1e3:.3f} mm (mean over the {n} frames)")
+
+    # ---- input preprocessing (Sec. 7): depth filter, normals, normal filter ------------
+    pre = dtsdf.Preprocess()
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(50)]
+    removed = []
+    for j in range(50):
+        d_ = frames_dev[j][0]
+        pev[j][0].record(stream)
+        fd = dtsdf.depth_filter(d_, pre.depth)
+        pev[j][1].record(stream)
+        _, nn = dtsdf.vertex_normal(fd, cam)
+        pev[j][2].record(stream)
+        dtsdf.normal_filter(nn, pre.normal_sigma_d, pre.normal_sigma_r_deg, pre.normal_radius)
+        pev[j][3].record(stream)
+        removed.append(float(((d_ > 0) & (fd == 0)).float().mean()))
+    torch.cuda.synchronize()
+    preprocess = dict(
+        depth_filter_ms=float(np.mean([e[0].elapsed_time(e[1]) for e in pev])),
+        vertex_normal_ms=float(np.mean([e[1].elapsed_time(e[2]) for e in pev])),
+        normal_filter_ms=float(np.mean([e[2].elapsed_time(e[3]) for e in pev])),
+        removed_fraction=float(np.mean(removed)), frames=50,
+        params=dataclasses.asdict(pre))
+    log(f"preprocess: depth filter {preprocess['depth_filter_ms']:.3f} ms, normals "
+        f"{preprocess['vertex_normal_ms']:.3f} ms, normal filter "
+        f"{preprocess['normal_filter_ms']:.3f} ms, removed {np.mean(removed):.4f}")
 
     if args.copy_probe:
         # a plain elementwise kernel reading and writing 256 MiB each (counter calibration)
@@ -274,7 +307,7 @@ def main():
                 c = dtsdf.level_camera(cam, l)
                 o = gm.render(c, T, outputs=("vertex", "normal", "mask"))
                 levels.append((o["vertex"], o["normal"], o["mask"], c))
-            T_est, _ = dtsdf.icp(live, cam, levels, dT0)
+            T_est, _ = dtsdf.icp(live, cam, levels, dT0, preprocess=pre)
             torch.cuda.synchronize()
             tot += time.perf_counter() - ta
             errs.append(float(np.linalg.norm(T_est[:3, 3])))
@@ -307,7 +340,7 @@ def main():
                 if l < 2:
                     ri = dtsdf.intensity_downsample(ri)
             T_est, _ = dtsdf.icp(live, cam, levels, dT0, live_rgb=live_rgb, ref_levels=refs,
-                                 T_ref_model=np.linalg.inv(T_kf) @ T)
+                                 T_ref_model=np.linalg.inv(T_kf) @ T, preprocess=pre)
             torch.cuda.synchronize()
             tot_rgb += time.perf_counter() - ta
             errs_rgb.append(float(np.linalg.norm(T_est[:3, 3])))
@@ -340,7 +373,7 @@ def main():
                 c = dtsdf.level_camera(cam, l)
                 o = gm.render(c, T, outputs=("vertex", "normal", "mask"))
                 levels.append((o["vertex"], o["normal"], o["mask"], c))
-            T_est, _ = dtsdf.icp_lm(live, cam, levels, dT0, dim=7)
+            T_est, _ = dtsdf.icp_lm(live, cam, levels, dT0, dim=7, preprocess=pre)
             torch.cuda.synchronize()
             tot += time.perf_counter() - ta
             logs[i].append(math.log(float(np.cbrt(np.linalg.det(T_est[:3, :3])))))
@@ -430,6 +463,8 @@ def main():
         "icp_rgb_keyframe_ms_per_frame": icp_rgb_ms,
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
         "multi_sensor": multi,
+        "post_fusion_mae_m": float(np.mean(mae)),
+        "preprocess": preprocess,
         "hit_rate": float(np.mean(hits) / (H * W)),
         "samples_per_ray": per_ray,
         "samples_per_wave_max": per_wave_max,

@@ -494,6 +494,35 @@ def bilateral_normal(N: np.ndarray, sigma_d: float = 2.5, sigma_r_deg: float = 5
                     0.0)
 
 
+@dataclasses.dataclass
+class Preprocess:
+    """Live-frame preprocessing of the registration (Sec. 7, Sec. 8 parameters): the support
+    and bilateral depth filters before the pyramid, the bilateral normal filter on every
+    level's normals (normal_radius 0: none)."""
+    support_rel: float = f32(0.02)
+    min_support: int = 2
+    sigma_d: float = 5.0
+    sigma_r: float = f32(0.025)
+    radius: int = 5
+    normal_sigma_d: float = 2.5
+    normal_sigma_r_deg: float = 5.0
+    normal_radius: int = 5
+
+    def depth(self, depth: np.ndarray) -> np.ndarray:
+        D = np.asarray(depth, np.float64)
+        if self.min_support > 0:
+            D = depth_support_filter(D, self.support_rel, self.min_support)
+        if self.radius > 0:
+            D = bilateral_depth(D, self.sigma_d, self.sigma_r, self.radius)
+        return D
+
+    def normals(self, N: np.ndarray) -> np.ndarray:
+        if self.normal_radius <= 0:
+            return N
+        return bilateral_normal(N, self.normal_sigma_d, self.normal_sigma_r_deg,
+                                self.normal_radius)
+
+
 def post_fusion_mae(rendered: np.ndarray, measured: np.ndarray):
     """Geometric post-fusion error (Sec. 8): the mean absolute difference between the depth
     rendered at a pose after fusion and the input depth of that pose, over the pixels where
@@ -796,18 +825,24 @@ def icp_rgb(live_depth: np.ndarray, live_rgb: np.ndarray, live_cam, model_levels
 
 def icp(live_depth: np.ndarray, live_cam, model_levels, dT0: np.ndarray, dim: int = 6,
         iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
-        depth_scale: float = 1.0, min_inliers_per_dim: int = 64):
+        depth_scale: float = 1.0, min_inliers_per_dim: int = 64,
+        preprocess: Optional[Preprocess] = None):
     """Coarse-to-fine point-to-plane ICP.
 
     model_levels[l] = (V, N, mask, cam) rendered at level l (model camera frame).
     ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine.
+    ``preprocess`` filters the live depth before the pyramid and every level's normals.
     Returns the final live->model transform and a per-iteration log."""
     L = len(model_levels)
+    if preprocess is not None:
+        live_depth = preprocess.depth(live_depth)
     pyr = depth_pyramid(live_depth, L)
     dT = np.array(dT0, np.float64)
     log = []
     for l in reversed(range(L)):
         V, N, ok = vertex_normal_map(pyr[l], live_cam.level(l), depth_scale)
+        if preprocess is not None:
+            N = preprocess.normals(N)
         mV, mN, mM, mcam = model_levels[l]
         for _ in range(iters[l]):
             H, g, err, cnt = associate_reduce(V, N, ok, mV, mN, mM, mcam, dT, dim, params)

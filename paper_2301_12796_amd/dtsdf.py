@@ -515,6 +515,34 @@ def normal_filter(normal: torch.Tensor, sigma_d: float = 2.5, sigma_r_deg: float
     return out
 
 
+@dataclasses.dataclass
+class Preprocess:
+    """Live-frame preprocessing of the registration (Sec. 7): the depth filter before the
+    pyramid and the bilateral normal filter on every level's cross-product normals."""
+    depth: Optional[DepthFilterParams] = dataclasses.field(default_factory=DepthFilterParams)
+    normal_sigma_d: float = 2.5
+    normal_sigma_r_deg: float = 5.0
+    normal_radius: int = 5          # 0: no normal filter
+
+
+def _live_levels(live_depth, live_cam, L, depth_scale, pre, stream):
+    d0 = live_depth
+    if pre is not None and pre.depth is not None:
+        d0 = depth_filter(live_depth, pre.depth, stream=stream)
+    pyr = [d0]
+    for _ in range(1, L):
+        pyr.append(depth_downsample(pyr[-1], stream=stream))
+    out = []
+    for l in range(L):
+        cam_l = level_camera(live_cam, l)
+        v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
+        if pre is not None and pre.normal_radius > 0:
+            n = normal_filter(n, pre.normal_sigma_d, pre.normal_sigma_r_deg, pre.normal_radius,
+                              stream=stream)
+        out.append((cam_l, v, n))
+    return out
+
+
 def depth_error(rendered: torch.Tensor, measured: torch.Tensor, stream=None):
     """Post-fusion error (Sec. 8): (mean |rendered - measured| over pixels where both are
     valid, that pixel count)."""
@@ -632,19 +660,17 @@ def icp_step_lm(live_vertex: torch.Tensor, live_normal: torch.Tensor, live_cam,
 
 def icp_lm(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 7,
            iters=(10, 5, 4), params: IcpParams = IcpParams(), tau: float = 1e-3,
-           min_step: float = 1e-6, depth_scale: float = 1.0, stream=None):
+           min_step: float = 1e-6, depth_scale: float = 1.0, stream=None,
+           preprocess: Optional[Preprocess] = None):
     """Coarse-to-fine ICP solved by Levenberg-Marquardt with Madsen's damping (Sec. 7); the
     damping restarts at every level and each level starts from the previous level's
-    accepted pose."""
+    accepted pose.  ``preprocess`` filters the live frame first (Sec. 7)."""
     L = len(model_levels)
-    pyr = [live_depth]
-    for _ in range(1, L):
-        pyr.append(depth_downsample(pyr[-1], stream=stream))
+    live = _live_levels(live_depth, live_cam, L, depth_scale, preprocess, stream)
     T = np.array(T0, np.float64)
     log = []
     for l in reversed(range(L)):
-        cam_l = level_camera(live_cam, l)
-        v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
+        cam_l, v, n = live[l]
         mv, mn, mm, mcam = model_levels[l]
         st = LmState(T, tau)
         for _ in range(iters[l]):
@@ -724,16 +750,16 @@ def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:
 def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
         iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
         depth_scale: float = 1.0, stream=None, live_rgb: Optional[torch.Tensor] = None,
-        ref_levels=None, T_ref_model=None, lam: float = 0.1, max_error=(0.05, 0.175, 0.175)):
+        ref_levels=None, T_ref_model=None, lam: float = 0.1, max_error=(0.05, 0.175, 0.175),
+        preprocess: Optional[Preprocess] = None):
     """Coarse-to-fine ICP: model_levels[l] = (vertex, normal, mask, cam) at level l.
     ``iters`` lists fine-to-coarse iteration counts; levels run coarse to fine.
     With ``live_rgb`` and ``ref_levels`` ([(grey image, cam)] per level) the steps are
     combined geometric + photometric (Sec. 5.2, 5.3); ``T_ref_model`` maps the model camera to
-    the reference camera (identity: frame-to-frame / frame-to-render)."""
+    the reference camera (identity: frame-to-frame / frame-to-render).  ``preprocess``
+    filters the live frame first (Sec. 7)."""
     L = len(model_levels)
-    pyr = [live_depth]
-    for _ in range(1, L):
-        pyr.append(depth_downsample(pyr[-1], stream=stream))
+    live = _live_levels(live_depth, live_cam, L, depth_scale, preprocess, stream)
     ipyr = None
     if live_rgb is not None:
         ipyr = [intensity(live_rgb, stream=stream)]
@@ -743,8 +769,7 @@ def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
     T = np.array(T0, np.float64)
     log = []
     for l in reversed(range(L)):
-        cam_l = level_camera(live_cam, l)
-        v, n = vertex_normal(pyr[l], cam_l, depth_scale, stream=stream)
+        cam_l, v, n = live[l]
         mv, mn, mm, mcam = model_levels[l]
         photo = None
         if ipyr is not None:
