@@ -529,6 +529,36 @@ int64_t orc_export(void* h, int32_t* keys, float* sdf, float* w, uint8_t* rgb, f
   return (int64_t)order.size();
 }
 
+// Recycling (Sec. 3): every brick none of whose observed voxels (w > 0) holds a value below
+// t_free -- free space after repeated carving, or never observed -- leaves the map.  Returns
+// the number removed; the remaining bricks keep their contents and border flags.
+int64_t orc_recycle(void* h, double t_free) {
+  Map& m = *static_cast<Map*>(h);
+  std::vector<Key> keys;
+  std::deque<Brick> bricks;
+  int64_t removed = 0;
+  for (size_t i = 0; i < m.bricks.size(); ++i) {
+    const Brick& B = m.bricks[i];
+    bool surface = false;
+    for (int l = 0; l < kVox && !surface; ++l) surface = B.w[l] > 0.0 && B.sdf[l] < t_free;
+    if (!surface) {
+      ++removed;
+      continue;
+    }
+    keys.push_back(m.keys[i]);
+    bricks.push_back(B);
+  }
+  m.keys.swap(keys);
+  m.bricks.swap(bricks);
+  m.index.clear();
+  m.blocks.clear();
+  for (size_t i = 0; i < m.keys.size(); ++i) {
+    m.index.emplace(m.keys[i], (int)i);
+    m.blocks.insert(BKey{m.keys[i].x, m.keys[i].y, m.keys[i].z});
+  }
+  return removed;
+}
+
 // Replace the map contents with n bricks (same layout as orc_export; rgb and wc may be NULL).
 void orc_import(void* h, int64_t n, const int32_t* keys, const float* sdf, const float* w,
                 const uint8_t* rgb, const float* wc) {

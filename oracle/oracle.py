@@ -103,6 +103,8 @@ def _declare(L):
     L.orc_requests.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
                                ctypes.c_double, _P, _P, _P, ctypes.c_int64]
+    L.orc_recycle.restype = ctypes.c_int64
+    L.orc_recycle.argtypes = [_P, ctypes.c_double]
     L.orc_export.restype = ctypes.c_int64
     L.orc_export.argtypes = [_P] * 7
     L.orc_import.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
@@ -235,6 +237,11 @@ class OracleMap:
                                _ptr(alloc), cap)
         assert n <= cap
         return keys[:n], border[:n], alloc[:n]
+
+    def recycle(self, t_free: float = 0.9) -> int:
+        """Recycling of bricks without surface (Sec. 3): removes every brick whose observed
+        voxels all hold values >= t_free (or that has none); returns how many."""
+        return int(lib().orc_recycle(self._h, f32(t_free)))
 
     def export(self) -> dict:
         n = self.num_bricks
