@@ -187,6 +187,15 @@ dtsdf_status dtsdf_export(const dtsdf_map* map, dtsdf_blob* blob);
  * be NULL (colour cleared).  DTSDF_E_CAPACITY if the blob does not fit.  Synchronises. */
 dtsdf_status dtsdf_import(dtsdf_map* map, const dtsdf_blob* blob);
 
+/* Recycle bricks that hold no surface (Sec. 3: voxels allocated in error that repeated
+ * carving turned into free space go back to the pool): every (block, D) brick whose observed
+ * voxels (w > 0) all hold values >= t_free (truncation units; carving drives values towards
+ * 1), or that has no observed voxel, is removed from the map, reset and put on a free list
+ * that later allocations use before the pool grows.  *recycled (nullable) receives the
+ * number removed.  Meant to run every few frames, on the stream of the map's other calls;
+ * synchronises it.  DTSDF_E_INVAL for dense or combined-volume maps or t_free <= 0. */
+dtsdf_status dtsdf_recycle(dtsdf_map* map, float t_free, int64_t* recycled, void* stream);
+
 /* Camera-frame points (Sec. 6, eq. reprojection) and cross-product normals (Sec. 7) of a
  * depth image: vertex/normal are 3*H*W planes; the normal of a pixel without depth in
  * itself or one of its four neighbours is written as (0, 0, 0), as is its vertex when the

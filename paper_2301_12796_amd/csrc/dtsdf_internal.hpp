@@ -316,6 +316,10 @@ struct dtsdf_map {
   // combined value with weight 1 (0: no value), rendered without direction weighting
   int regular;
   int64_t mirrored;     // source block count at the last block mirroring (-1: never)
+  // recycled bricks (Sec. 3): pool indices freed by dtsdf_recycle, taken before the pool
+  // grows; counters[10] holds their number on the device, n_free its host mirror
+  int32_t* free_list;
+  int64_t n_free;
   // integration scratch, grown on demand
   int64_t img_cap;
   float* vmap;
@@ -372,4 +376,6 @@ dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st);
 dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st);
 // Enqueues the pool-index assignment of requested (block, D) bricks.
 void launch_assign(dtsdf_map* m, hipStream_t st);
+// rebuild_index with every grid cell cleared first (blocks may have disappeared).
+dtsdf_status rebuild_index_cleared(dtsdf_map* m, hipStream_t st);
 }

@@ -405,4 +405,27 @@ dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st) {
   return launch_index_update(m, st);
 }
 
+dtsdf_status rebuild_index_cleared(dtsdf_map* m, hipStream_t st) {
+  launch_bbox(m, st);
+  int32_t hb[6];
+  DTSDF_HIP(hipMemcpyAsync(hb, m->counters + 4, sizeof(hb), hipMemcpyDeviceToHost, st));
+  DTSDF_HIP(hipStreamSynchronize(st));
+  dtsdf_status s = ensure_grid(m, hb, st);
+  if (s != DTSDF_OK) return s;
+  if (m->grid_dim[0] == 0) return DTSDF_OK;
+  const int64_t cells = (int64_t)m->grid_dim[0] * m->grid_dim[1] * m->grid_dim[2];
+  const int64_t c1 = (int64_t)ceil_div(m->grid_dim[0], 4) * ceil_div(m->grid_dim[1], 4) *
+                     ceil_div(m->grid_dim[2], 4);
+  const int64_t c2 = (int64_t)ceil_div(m->grid_dim[0], 16) * ceil_div(m->grid_dim[1], 16) *
+                     ceil_div(m->grid_dim[2], 16);
+  hipLaunchKernelGGL(grid_clear_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st,
+                     m->grid_slot, m->grid_mask, cells);
+  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c1 + 255) / 256)), dim3(256), 0, st,
+                     m->macro1, c1);
+  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c2 + 255) / 256)), dim3(256), 0, st,
+                     m->macro2, c2);
+  DTSDF_HIP(hipGetLastError());
+  return launch_index_update(m, st);
+}
+
 }  // namespace dtsdf

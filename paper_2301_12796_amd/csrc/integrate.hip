@@ -126,7 +126,11 @@ __global__ __launch_bounds__(256) void request_k(const float* __restrict__ depth
   }
 }
 
+// Pool indices come from the free list of recycled bricks first (counters[10] entries of
+// free_list; a pop below zero falls through to the pool and is clamped afterwards), then
+// from the unused end of the pool (counters[0]).
 __global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* req, int4* bkey,
+                                                const int32_t* __restrict__ free_list,
                                                 uint32_t buckets, uint32_t capacity,
                                                 int32_t* counters) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -138,12 +142,18 @@ __global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* re
   unpack_key(entries[s].key, bx, by, bz);
   for (int d = 0; d < 6; ++d) {
     if (!((r >> d) & 1u) || entries[s].brick[d] >= 0) continue;
-    int idx = atomicAdd(&counters[0], 1);
-    if (idx < (int)capacity) {
+    int idx = -1;
+    const int f = atomicSub(&counters[10], 1) - 1;
+    if (f >= 0) {
+      idx = free_list[f];
+    } else {
+      const int b = atomicAdd(&counters[0], 1);
+      if (b < (int)capacity) idx = b;
+      else atomicAdd(&counters[1], 1);
+    }
+    if (idx >= 0) {
       entries[s].brick[d] = idx;
       bkey[idx] = make_int4(bx, by, bz, d);
-    } else {
-      atomicAdd(&counters[1], 1);
     }
   }
 }
@@ -164,6 +174,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
                                               uint64_t* brick_neg) {
   const int4 key = m.bkey[blockIdx.x];
   const int D = key.w;
+  if (D < 0) return;                      // a recycled brick on the free list
   const size_t HW = (size_t)a.in.W * a.in.H;
   const double tau = (double)m.tau;
   bool upd = false;
@@ -282,9 +293,15 @@ bool valid_intr(const dtsdf_intrinsics* i) {
 
 namespace dtsdf {
 
+__global__ void free_clamp_k(int32_t* counters) {
+  if (threadIdx.x == 0 && counters[10] < 0) counters[10] = 0;
+}
+
 void launch_assign(dtsdf_map* m, hipStream_t st) {
   hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
-                     m->req, m->bkey, m->buckets, m->p.brick_capacity, m->counters);
+                     m->req, m->bkey, m->free_list, m->buckets, m->p.brick_capacity,
+                     m->counters);
+  hipLaunchKernelGGL(free_clamp_k, dim3(1), dim3(64), 0, st, m->counters);
 }
 
 }  // namespace dtsdf
@@ -337,7 +354,7 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
   dim3 blk(16, 16), grd((in.W + 15) / 16, (in.H + 15) / 16);
   hipLaunchKernelGGL(vertex_normal_k, grd, blk, 0, st, depth, in, (double)depth_scale, m->vmap,
                      m->nmap);
-  int64_t before = m->n_bricks;
+  const int64_t before = m->n_bricks - m->n_free;
   int64_t dropped_now = 0;
   if (!m->p.dense) {
     const double voxel = (double)m->p.voxel_size, tau = (double)m->p.truncation;
@@ -348,7 +365,7 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
                        m->counters, max_entries);
     launch_assign(m, st);
     launch_bbox(m, st);
-    int32_t c[10];
+    int32_t c[11];
     DTSDF_HIP(hipMemcpyAsync(c, m->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     DTSDF_HIP(hipStreamSynchronize(st));
     dtsdf_status gs = ensure_grid(m, c + 4, st);
@@ -363,6 +380,7 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
     m->dropped = c[1];
     m->n_bricks = handed;
     m->n_blocks = c[3];
+    m->n_free = c[10];
   }
   if (m->n_bricks > 0) {
     FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
@@ -381,9 +399,9 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
   dtsdf_status is = launch_index_update(m, st);
   if (is != DTSDF_OK) return is;
   if (stats) {
-    stats->new_bricks = m->n_bricks - before;
+    stats->new_bricks = m->n_bricks - m->n_free - before;
     stats->dropped = dropped_now;
-    stats->bricks = m->n_bricks;
+    stats->bricks = m->n_bricks - m->n_free;
     DTSDF_HIP(hipStreamSynchronize(st));
   }
   return dropped_now > 0 ? DTSDF_E_CAPACITY : DTSDF_OK;

@@ -103,6 +103,7 @@ dtsdf_status upload_table(dtsdf_map* m, const std::vector<HostKey>& keys) {
   m->n_bricks = (int64_t)keys.size();
   m->n_blocks = blocks;
   m->dropped = 0;
+  m->n_free = 0;
   return DTSDF_OK;
 }
 
@@ -115,6 +116,7 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->rgb);
   (void)hipFree(m->wc);
   (void)hipFree(m->counters);
+  (void)hipFree(m->free_list);
   (void)hipFree(m->vmap);
   (void)hipFree(m->nmap);
   (void)hipFree(m->sub_min);
@@ -253,7 +255,7 @@ dtsdf_status dtsdf_destroy(dtsdf_map* m) {
 
 dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   if (!m || !out) return DTSDF_E_INVAL;
-  out->bricks = m->n_bricks;
+  out->bricks = m->n_bricks - m->n_free;
   out->capacity = m->p.brick_capacity;
   out->blocks = m->n_blocks;
   out->hash_buckets = m->buckets;
@@ -265,19 +267,22 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
                                 (8 * sizeof(float) + 16 * sizeof(uint64_t) + 64) * m->buckets +
                                 geo_bytes(m->fmt) * nv +
                                 (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
-                                (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap);
+                                (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap +
+                                (m->free_list ? sizeof(int32_t) * m->p.brick_capacity : 0));
   return DTSDF_OK;
 }
 
 dtsdf_status dtsdf_export(const dtsdf_map* m, dtsdf_blob* b) {
   if (!m || !b) return DTSDF_E_INVAL;
   if (hipDeviceSynchronize() != hipSuccess) return DTSDF_E_HIP;
+  // the pool holds n_bricks slots of which n_free are recycled (direction -1)
   int64_t n = m->n_bricks;
+  const int64_t live = m->n_bricks - m->n_free;
   if (!b->keys) {
-    b->n_bricks = n;
+    b->n_bricks = live;
     return DTSDF_OK;
   }
-  if (b->n_bricks < n || !b->sdf || !b->w) return DTSDF_E_INVAL;
+  if (b->n_bricks < live || !b->sdf || !b->w) return DTSDF_E_INVAL;
   std::vector<int4> bk((size_t)n);
   const size_t gb = geo_bytes(m->fmt);
   std::vector<uint8_t> geo((size_t)n * kVox * gb);
@@ -296,8 +301,12 @@ dtsdf_status dtsdf_export(const dtsdf_map* m, dtsdf_blob* b) {
       }
     }
   }
-  std::vector<int64_t> order((size_t)n);
-  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  std::vector<int64_t> order;
+  order.reserve((size_t)live);
+  for (int64_t i = 0; i < n; ++i)
+    if (bk[i].w >= 0) order.push_back(i);
+  if ((int64_t)order.size() != live) return DTSDF_E_HIP;
+  n = live;
   std::sort(order.begin(), order.end(), [&](int64_t a, int64_t c) {
     HostKey ka{bk[a].x, bk[a].y, bk[a].z, bk[a].w}, kc{bk[c].x, bk[c].y, bk[c].z, bk[c].w};
     return key_less(ka, kc);
@@ -386,7 +395,8 @@ dtsdf_status dtsdf_import(dtsdf_map* m, const dtsdf_blob* b) {
   }
   DTSDF_HIP(hipMemset(m->req, 0, sizeof(uint32_t) * m->buckets));
   st = brick_stats(m, nullptr);
-  if (st == DTSDF_OK) st = rebuild_index(m, nullptr);
+  // the previous contents may have covered blocks the new table does not hold
+  if (st == DTSDF_OK) st = rebuild_index_cleared(m, nullptr);
   if (st != DTSDF_OK) return st;
   DTSDF_HIP(hipDeviceSynchronize());
   return DTSDF_OK;

@@ -145,7 +145,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_vertex_normal", "dtsdf_depth_downsample", "icp_step", "icp_step_batch",
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
-            "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error",
+            "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -171,6 +171,7 @@ _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
 _lib.icp_step_lm.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                              ctypes.POINTER(_Photo), ctypes.c_int32, ctypes.POINTER(_IcpParams),
                              ctypes.POINTER(_LmState), ctypes.POINTER(_IcpResult), _V]
+_lib.dtsdf_recycle.argtypes = [_V, ctypes.c_float, ctypes.POINTER(ctypes.c_int64), _V]
 _lib.dtsdf_depth_filter.argtypes = [_V, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(_DepthFilterParams), _V, _V]
 _lib.dtsdf_normal_filter.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
@@ -347,6 +348,13 @@ class Map:
         _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
                                  ctypes.byref(ro), _stream(stream)), "dtsdf_render")
         return out
+
+    def recycle(self, t_free: float = 0.9, stream=None) -> int:
+        """Return bricks without surface to the pool (see dtsdf_recycle); returns how many."""
+        n = ctypes.c_int64(0)
+        _check(_lib.dtsdf_recycle(self._h, t_free, ctypes.byref(n), _stream(stream)),
+               "dtsdf_recycle")
+        return int(n.value)
 
     def export(self) -> dict:
         b = _Blob()
