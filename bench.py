@@ -19,7 +19,8 @@ the continuous-batching server against serial calls) and the view-dependent comb
 (recombination time, one-volume render rate and depth against the direct render, and a
 frame loop under the conditional-recombination policy) and the multi-sensor Sim(3)
 refinement (five sensors with scaled depth registered by Levenberg-Marquardt ICP, their
-scales anchored to the first sensor).
+scales anchored to the first sensor), and map upkeep (recycling of bricks without surface
+on the fused map: bricks freed, time, render and post-fusion error before and after).
 """
 from __future__ import annotations
 
@@ -85,6 +86,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
+    ap.add_argument("--no-recycle", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="leading requests of the 120/s Poisson stream that are served")
     ap.add_argument("--copy-probe", action="store_true",
@@ -387,6 +389,40 @@ def main():
         log(f"multi-sensor LM Sim(3): {multi['lm_sim3_ms_per_frame']:.2f} ms/frame, anchored "
             f"log-scale error max {max(err):.2e}")
 
+    # ---- map upkeep (Sec. 3): recycling of bricks without surface, on the fused map; the
+    # render and the post-fusion error at every 10th pose before and after ---------------
+    upkeep = None
+    if not args.no_recycle:
+        sub = list(range(0, n, 10))
+
+        def render_pass():
+            evs_ = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    for _ in sub]
+            errs = []
+            for (a_, b_), k in zip(evs_, sub):
+                a_.record(stream)
+                gm.render(cam, poses[k], out=out)
+                b_.record(stream)
+                errs.append(dtsdf.depth_error(out["depth"], frames_dev[k][0])[0])
+            torch.cuda.synchronize()
+            return float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs_])), float(np.mean(errs))
+
+        ms0, mae0 = render_pass()
+        upkeep = dict(bricks_before=gm.info()["bricks"], render_ms_before=ms0,
+                      post_fusion_mae_before_m=mae0, passes=[])
+        for t_free in (0.9, 0.5):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            nrec = gm.recycle(t_free)
+            dt = time.perf_counter() - ta
+            ms1, mae1 = render_pass()
+            upkeep["passes"].append(dict(t_free=t_free, recycled=nrec, recycle_ms=1e3 * dt,
+                                         bricks_after=gm.info()["bricks"], render_ms=ms1,
+                                         post_fusion_mae_m=mae1))
+            log(f"recycle t_free={t_free}: {nrec} bricks in {1e3 * dt:.2f} ms, render "
+                f"{ms0:.3f} -> {ms1:.3f} ms, post-fusion MAE {mae0 * 1e3:.3f} -> "
+                f"{mae1 * 1e3:.3f} mm")
+
     # ---- serving: render + Sim(3) ICP requests from four sensors on the tiny map -------
     serving = None
     if not args.no_serve:
@@ -464,6 +500,7 @@ def main():
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
         "multi_sensor": multi,
         "post_fusion_mae_m": float(np.mean(mae)),
+        "upkeep": upkeep,
         "preprocess": preprocess,
         "hit_rate": float(np.mean(hits) / (H * W)),
         "samples_per_ray": per_ray,

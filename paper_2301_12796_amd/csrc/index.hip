@@ -287,9 +287,12 @@ __global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict_
   for (int gy = 0; gy < 4; ++gy) out[gy] = bytes[gy];
 }
 
-__global__ void bbox_reset_k(int32_t* bbox) {
-  if (threadIdx.x < 3) bbox[threadIdx.x] = INT_MAX;
-  else if (threadIdx.x < 6) bbox[threadIdx.x] = INT_MIN;
+// Also clamps the free-list count (counters[10]) at zero: pops by the allocation that ran
+// before may have driven it below.
+__global__ void bbox_reset_k(int32_t* counters) {
+  if (threadIdx.x < 3) counters[4 + threadIdx.x] = INT_MAX;
+  else if (threadIdx.x < 6) counters[4 + threadIdx.x] = INT_MIN;
+  else if (threadIdx.x == 6 && counters[10] < 0) counters[10] = 0;
 }
 
 }  // namespace
@@ -312,7 +315,7 @@ dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st) {
 
 void launch_bbox(dtsdf_map* m, hipStream_t st) {
   int32_t* bbox = m->counters + 4;
-  hipLaunchKernelGGL(bbox_reset_k, dim3(1), dim3(64), 0, st, bbox);
+  hipLaunchKernelGGL(bbox_reset_k, dim3(1), dim3(64), 0, st, m->counters);
   hipLaunchKernelGGL(bbox_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
                      m->buckets, bbox);
 }

@@ -127,8 +127,9 @@ __global__ __launch_bounds__(256) void request_k(const float* __restrict__ depth
 }
 
 // Pool indices come from the free list of recycled bricks first (counters[10] entries of
-// free_list; a pop below zero falls through to the pool and is clamped afterwards), then
-// from the unused end of the pool (counters[0]).
+// free_list; a pop below zero falls through to the pool, and the bounding-box reset that
+// follows every allocation clamps the count at zero), then from the unused end of the pool
+// (counters[0]).
 __global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* req, int4* bkey,
                                                 const int32_t* __restrict__ free_list,
                                                 uint32_t buckets, uint32_t capacity,
@@ -143,7 +144,8 @@ __global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* re
   for (int d = 0; d < 6; ++d) {
     if (!((r >> d) & 1u) || entries[s].brick[d] >= 0) continue;
     int idx = -1;
-    const int f = atomicSub(&counters[10], 1) - 1;
+    const int f = __atomic_load_n(&counters[10], __ATOMIC_RELAXED) > 0
+                      ? atomicSub(&counters[10], 1) - 1 : -1;
     if (f >= 0) {
       idx = free_list[f];
     } else {
@@ -293,15 +295,11 @@ bool valid_intr(const dtsdf_intrinsics* i) {
 
 namespace dtsdf {
 
-__global__ void free_clamp_k(int32_t* counters) {
-  if (threadIdx.x == 0 && counters[10] < 0) counters[10] = 0;
-}
-
+// Every caller runs launch_bbox next, which clamps the free-list count.
 void launch_assign(dtsdf_map* m, hipStream_t st) {
   hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
                      m->req, m->bkey, m->free_list, m->buckets, m->p.brick_capacity,
                      m->counters);
-  hipLaunchKernelGGL(free_clamp_k, dim3(1), dim3(64), 0, st, m->counters);
 }
 
 }  // namespace dtsdf

@@ -162,18 +162,45 @@ __global__ __launch_bounds__(256) void normal_filter_k(NormalFilterArgs a) {
   a.out[2 * HW + p] = o[2];
 }
 
+__device__ inline void err_acc(float a, float b, double& s, double& c) {
+  if (a > 0.f && b > 0.f) {
+    s += fabs((double)a - (double)b);
+    c += 1.0;
+  }
+}
+
+// vec: both images 16-byte aligned; the first n4 = n / 4 groups of four pixels are read as
+// float4 (four groups per thread and pass, so that enough loads are in flight for one
+// workgroup), the tail pixel by pixel.  The assignment of pixels to threads is fixed.
 __global__ __launch_bounds__(1024) void depth_error_k(const float* __restrict__ r,
                                                       const float* __restrict__ m, size_t n,
-                                                      double* out) {
+                                                      int vec, double* out) {
   __shared__ double ss[1024], sc[1024];
   double s = 0.0, c = 0.0;
-  for (size_t i = threadIdx.x; i < n; i += 1024) {
-    const float a = r[i], b = m[i];
-    if (a > 0.f && b > 0.f) {
-      s += fabs((double)a - (double)b);
-      c += 1.0;
+  size_t done = 0;
+  if (vec) {
+    const size_t n4 = n / 4;
+    const float4* r4 = reinterpret_cast<const float4*>(r);
+    const float4* m4 = reinterpret_cast<const float4*>(m);
+    for (size_t base = 0; base < n4; base += 4 * 1024) {
+      float4 a[4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const size_t i = base + k * 1024 + threadIdx.x;
+        a[k] = i < n4 ? r4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        b[k] = i < n4 ? m4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        err_acc(a[k].x, b[k].x, s, c);
+        err_acc(a[k].y, b[k].y, s, c);
+        err_acc(a[k].z, b[k].z, s, c);
+        err_acc(a[k].w, b[k].w, s, c);
+      }
     }
+    done = n4 * 4;
   }
+  for (size_t i = done + threadIdx.x; i < n; i += 1024) err_acc(r[i], m[i], s, c);
   ss[threadIdx.x] = s;
   sc[threadIdx.x] = c;
   __syncthreads();
@@ -243,8 +270,9 @@ dtsdf_status dtsdf_normal_filter(const float* normal_in, int32_t width, int32_t 
 dtsdf_status dtsdf_depth_error(const float* rendered, const float* measured, int32_t width,
                                int32_t height, double* out, void* stream) {
   if (!rendered || !measured || !out || width <= 0 || height <= 0) return DTSDF_E_INVAL;
+  const int vec = (((uintptr_t)rendered | (uintptr_t)measured) & 15u) == 0 ? 1 : 0;
   hipLaunchKernelGGL(depth_error_k, dim3(1), dim3(1024), 0, (hipStream_t)stream, rendered,
-                     measured, (size_t)width * height, out);
+                     measured, (size_t)width * height, vec, out);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

@@ -93,12 +93,20 @@ def test_normal_filter_matches_oracle(dtsdf, radius, sigma_r):
     np.testing.assert_allclose(np.linalg.norm(out[valid], axis=-1), 1.0, atol=1e-6)
 
 
-def test_depth_error_matches_oracle(dtsdf):
-    a = _noisy_depth(seed=4)
-    b = _noisy_depth(seed=5)
-    mae, n = dtsdf.depth_error(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+@pytest.mark.parametrize("shape,offset", [((640, 480), 0), ((203, 157), 0), ((203, 157), 1)])
+def test_depth_error_matches_oracle(dtsdf, shape, offset):
+    """Aligned images take the float4 path (with a ragged tail when W*H is not a multiple
+    of four); an image starting one float in takes the scalar path."""
+    W, H = shape
+    a = _noisy_depth(W, H, seed=4)
+    b = _noisy_depth(W, H, seed=5)
+    ta = torch.zeros(W * H + offset, dtype=torch.float32, device="cuda")
+    tb = torch.zeros(W * H + offset, dtype=torch.float32, device="cuda")
+    ta[offset:] = torch.from_numpy(a.ravel()).cuda()
+    tb[offset:] = torch.from_numpy(b.ravel()).cuda()
+    mae, n = dtsdf.depth_error(ta[offset:].view(H, W), tb[offset:].view(H, W))
     ref, nr = O.post_fusion_mae(a, b)
-    print(f"[depth error] mae {mae:.6e} over {n} pixels", flush=True)
+    print(f"[depth error {shape} +{offset}] mae {mae:.6e} over {n} pixels", flush=True)
     assert n == nr and abs(mae - ref) <= 1e-12 * ref
 
 
