@@ -9,7 +9,8 @@ colour per direction).  One step renders depth + normal + colour at all 300 traj
 Printed as one JSON line, with the roofline of the render kernel (algorithmic bytes per
 launch from the traced brick / bucket sets, divided by the launch duration measured with HIP
 events on the launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
-Separately timed and reported beside it: integration ms/frame, the geometric post-fusion error
+Separately timed and reported beside it: the same views rendered 32 per persistent launch
+(rays/s and that launch's roofline, bricks counted once per launch), integration ms/frame, the geometric post-fusion error
 (render at every fused pose against its input depth), the live-frame preprocessing (depth
 filter, normals, normal filter), three-level ICP ms/frame on preprocessed live frames
 (point-to-plane, and combined with the photometric term against a keyframe), the
@@ -87,6 +88,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-recycle", action="store_true")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="views per launch of the batched render block (1: skip it)")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="leading requests of the 120/s Poisson stream that are served")
     ap.add_argument("--copy-probe", action="store_true",
@@ -238,6 +241,54 @@ def main():
     mean_launch_s = float(launch_ms.mean()) * 1e-3
     achieved = bytes_per_launch / mean_launch_s / 1e9
     traffic = read_traffic(os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip"))
+
+    # ---- the same 300 views rendered several per launch (dtsdf_render_batch, the serving
+    # form's persistent launch): the tails of the views overlap.  Algorithmic bytes of a
+    # launch count the union of the bricks and entries its views touch (traced, untimed) ----
+    batched = None
+    if args.batch > 1:
+        B = args.batch
+        groups = [poses[j:j + B] for j in range(0, n, B)]
+        bouts = [dict(depth=torch.empty((H, W), dtype=torch.float32, device=dev),
+                      normal=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                      rgba=torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+                      mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+                 for _ in range(B)]
+        gbytes = []
+        for g in groups:
+            tb.zero_(); tc.zero_(); ts.zero_()
+            tviews = [(cam, T, 0.2, 10.0, dict(bouts[j], trace_bricks=tb, trace_color=tc,
+                                               trace_slots=ts)) for j, T in enumerate(g)]
+            gm.render_batch(tviews)
+            gbytes.append(int(tb.sum()) * BRICK_MARCH_BYTES + int(tc.sum()) * BRICK_COLOR_BYTES +
+                          int(ts.sum()) * BUCKET_BYTES + len(g) * H * W * OUT_BYTES_PER_RAY)
+        views = [[(cam, T, 0.2, 10.0, bouts[j]) for j, T in enumerate(g)] for g in groups]
+        for _ in range(args.warmup):
+            for vv in views:
+                gm.render_batch(vv)
+        bev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in groups] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for s_ in range(args.steps):
+            for (e0_, e1_), vv in zip(bev[s_], views):
+                e0_.record(stream)
+                gm.render_batch(vv)
+                e1_.record(stream)
+        torch.cuda.synchronize()
+        bwall = time.perf_counter() - tb0
+        bms = np.array([[a_.elapsed_time(b_) for a_, b_ in e] for e in bev])
+        full = [j for j, g in enumerate(groups) if len(g) == B]
+        bach = float(np.mean([gbytes[j] for j in full])) / (float(bms[:, full].mean()) * 1e-3) / 1e9
+        batched = dict(views_per_launch=B, launches_per_step=len(groups),
+                       rays_per_s=n * H * W * args.steps / bwall,
+                       ms_per_view=1e3 * bwall / (n * args.steps),
+                       roofline=dict(bound="hbm", achieved=bach, peak=HBM_PEAK_GBS, unit="GB/s",
+                                     frac=bach / HBM_PEAK_GBS,
+                                     algorithmic_bytes_per_launch=float(np.mean([gbytes[j] for j in full])),
+                                     mean_launch_ms=float(bms[:, full].mean())))
+        log(f"batched ({B} views per launch): {batched['rays_per_s'] / 1e6:.1f} M rays/s, "
+            f"{batched['ms_per_view']:.3f} ms per view, {bach:.0f} GB/s algorithmic")
 
     # ---- precision forms: the same frames fused into f16 / i16 maps ---------------------
     precision = None
@@ -498,6 +549,7 @@ def main():
         "icp_ms_per_frame": icp_ms,
         "icp_rgb_keyframe_ms_per_frame": icp_rgb_ms,
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
+        "batched": batched,
         "multi_sensor": multi,
         "post_fusion_mae_m": float(np.mean(mae)),
         "upkeep": upkeep,

@@ -914,7 +914,12 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
   if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
     rs = DTSDF_E_HIP;
   } else {
-    const int wgs = (int)std::min<int64_t>(total, 2048);
+    // persistent waves: three per SIMD (the kernel's occupancy), four SIMDs per CU
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) !=
+            hipSuccess || cus <= 0)
+      cus = 170;
+    const int wgs = (int)std::min<int64_t>(total, (int64_t)cus * 4 * 3);
     const MapView v = make_view(m);
     const RenderArgs* da = reinterpret_cast<const RenderArgs*>(dev + off_args);
     const int32_t* dp = reinterpret_cast<const int32_t*>(dev + off_prefix);
