@@ -202,6 +202,19 @@ Frame make_frame(const float* depth, int W, int H, double fx, double fy, double 
   return f;
 }
 
+// Replaces the frame's cross-product normals by the caller's (camera frame, three per
+// pixel, all zero = none; Sec. 7 filters the normals before use); a normal counts only where
+// the depth is valid.
+void override_normals(Frame& f, const double* normals) {
+  if (!normals) return;
+  for (size_t i = 0; i < (size_t)f.W * f.H; ++i) {
+    const double* n = normals + 3 * i;
+    const bool ok = f.pv[i] && (n[0] != 0.0 || n[1] != 0.0 || n[2] != 0.0);
+    for (int k = 0; k < 3; ++k) f.N[3 * i + k] = ok ? n[k] : 0.0;
+    f.nv[i] = ok ? 1 : 0;
+  }
+}
+
 void running_average(double& val, double& w, double x, double wx, double w_max) {
   val = (val * w + x * wx) / (w + wx);
   w = std::min(w + wx, w_max);
@@ -323,9 +336,11 @@ static void collect_requests(const Map& m, const Frame& f, const double T[16],
 // Duplicates are kept.
 int64_t orc_requests(void* h, const float* depth, int W, int H, double fx, double fy, double cx,
                      double cy, const double T[16], double depth_scale, int32_t* out_keys,
-                     uint8_t* out_border, uint8_t* out_alloc, int64_t cap) {
+                     uint8_t* out_border, uint8_t* out_alloc, int64_t cap,
+                     const double* normals) {
   Map& m = *static_cast<Map*>(h);
   Frame f = make_frame(depth, W, H, fx, fy, cx, cy, depth_scale);
+  override_normals(f, normals);
   std::vector<Key> req;
   std::vector<uint8_t> border, alloc;
   collect_requests(m, f, T, req, border, alloc);
@@ -345,11 +360,12 @@ int64_t orc_requests(void* h, const float* depth, int W, int H, double fx, doubl
 // depth: HxW float32 metres before depth_scale, 0 = invalid.  rgb: HxWx3 or NULL.
 void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H, double fx,
                    double fy, double cx, double cy, const double T[16], double depth_scale,
-                   OrcStats* st) {
+                   OrcStats* st, const double* normals) {
   Map& m = *static_cast<Map*>(h);
   const Params& p = m.p;
   OrcStats s{};
   Frame f = make_frame(depth, W, H, fx, fy, cx, cy, depth_scale);
+  override_normals(f, normals);
   double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
   double t[3] = {T[3], T[7], T[11]};
 

@@ -98,11 +98,11 @@ def _declare(L):
     L.orc_num_bricks.argtypes = [_P]
     L.orc_integrate.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
-                                ctypes.c_double, ctypes.POINTER(_Stats)]
+                                ctypes.c_double, ctypes.POINTER(_Stats), _P]
     L.orc_requests.restype = ctypes.c_int64
     L.orc_requests.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
-                               ctypes.c_double, _P, _P, _P, ctypes.c_int64]
+                               ctypes.c_double, _P, _P, _P, ctypes.c_int64, _P]
     L.orc_recycle.restype = ctypes.c_int64
     L.orc_recycle.argtypes = [_P, ctypes.c_double]
     L.orc_export.restype = ctypes.c_int64
@@ -215,16 +215,21 @@ class OracleMap:
         return int(lib().orc_num_bricks(self._h))
 
     def integrate(self, depth: np.ndarray, rgb: Optional[np.ndarray], cam, T_wc: np.ndarray,
-                  depth_scale: float = 1.0) -> dict:
+                  depth_scale: float = 1.0, normals: Optional[np.ndarray] = None) -> dict:
+        """Fuse one frame; ``normals`` (H, W, 3 camera frame, zero = none) replaces the
+        cross-product normals (e.g. filtered ones, Sec. 7)."""
         d = np.ascontiguousarray(depth, np.float32)
         c = None if rgb is None else np.ascontiguousarray(rgb, np.uint8)
         T = np.ascontiguousarray(T_wc, np.float64)
+        nrm = None if normals is None else np.ascontiguousarray(normals, np.float64)
         st = _Stats()
         lib().orc_integrate(self._h, _ptr(d), _ptr(c), d.shape[1], d.shape[0], cam.fx, cam.fy,
-                            cam.cx, cam.cy, _ptr(T), f32(depth_scale), ctypes.byref(st))
+                            cam.cx, cam.cy, _ptr(T), f32(depth_scale), ctypes.byref(st),
+                            _ptr(nrm))
         return {k: getattr(st, k) for k, _ in _Stats._fields_}
 
-    def requests(self, depth: np.ndarray, cam, T_wc: np.ndarray, depth_scale: float = 1.0):
+    def requests(self, depth: np.ndarray, cam, T_wc: np.ndarray, depth_scale: float = 1.0,
+                 normals: Optional[np.ndarray] = None):
         """(keys n x 4, borderline flags, allocating flags) of one frame's block requests."""
         d = np.ascontiguousarray(depth, np.float32)
         T = np.ascontiguousarray(T_wc, np.float64)
@@ -232,9 +237,10 @@ class OracleMap:
         keys = np.zeros((cap, 4), np.int32)
         border = np.zeros(cap, np.uint8)
         alloc = np.zeros(cap, np.uint8)
+        nrm = None if normals is None else np.ascontiguousarray(normals, np.float64)
         n = lib().orc_requests(self._h, _ptr(d), d.shape[1], d.shape[0], cam.fx, cam.fy, cam.cx,
                                cam.cy, _ptr(T), f32(depth_scale), _ptr(keys), _ptr(border),
-                               _ptr(alloc), cap)
+                               _ptr(alloc), cap, _ptr(nrm))
         assert n <= cap
         return keys[:n], border[:n], alloc[:n]
 

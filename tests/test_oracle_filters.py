@@ -16,6 +16,8 @@ import math
 import numpy as np
 import scipy.ndimage
 
+import synth
+
 from oracle import oracle as O
 
 
@@ -112,3 +114,59 @@ def test_post_fusion_mae_example():
     m = np.array([[1.1, 1.8, 2.0], [0.0, 0.0, 2.7]])
     mae, n = O.post_fusion_mae(r, m)
     assert n == 3 and math.isclose(mae, (0.1 + 0.2 + 0.3) / 3, rel_tol=1e-12)
+
+
+def _plane_frame(cam, z=0.5):
+    depth = np.full((cam.height, cam.width), z, np.float32)
+    rgb = np.zeros((cam.height, cam.width, 3), np.uint8)
+    rgb[...] = (30, 140, 250)
+    return depth, rgb
+
+
+def test_fusion_with_its_own_normals_is_unchanged():
+    """Caller normals equal to the cross-product normals reproduce the default fusion."""
+    from synth.scenes import TINY_CAMERA as cam
+    frames = synth.tiny_frames(3)
+    a = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    b = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    for f in frames:
+        a.integrate(f["depth"], f["rgb"], cam, f["T_wc"])
+        _, N, _ = O.vertex_normal_map(f["depth"], cam)
+        b.integrate(f["depth"], f["rgb"], cam, f["T_wc"], normals=N)
+    ea, eb = a.export(), b.export()
+    assert np.array_equal(ea["keys"], eb["keys"])
+    assert np.array_equal(ea["sdf"], eb["sdf"]) and np.array_equal(ea["w"], eb["w"])
+
+
+def test_fusion_with_given_normals_closed_form():
+    """A frontal plane fused with the exact normal at every pixel (the image border
+    included, where cross-product normals do not exist) stores the exact signed distance;
+    normals on pixels without depth are ignored."""
+    from synth.scenes import TINY_CAMERA as cam
+    depth, rgb = _plane_frame(cam)
+    N = np.zeros((cam.height, cam.width, 3))
+    N[..., 2] = -1.0
+    m = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    m.integrate(depth, rgb, cam, np.eye(4), normals=N)
+    b = m.export()
+    from tests.test_oracle_pins import _voxel_positions
+    x = _voxel_positions(b, 0.01)
+    d_true = (0.5 - x[..., 2]) / O.f32(0.04)
+    band = (b["w"] > 0) & (np.abs(d_true) <= 1)
+    assert band.sum() > 10000
+    assert np.max(np.abs(b["sdf"][band] - d_true[band])) < 1e-6
+    # voxels seen by the border pixels are fused too (the default path has no normal there)
+    ref = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    ref.integrate(depth, rgb, cam, np.eye(4))
+    assert (b["w"] > 0).sum() > (ref.export()["w"] > 0).sum()
+    # normals where the depth is missing change nothing
+    half = depth.copy()
+    half[:, : cam.width // 2] = 0.0
+    m1 = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    m1.integrate(half, rgb, cam, np.eye(4), normals=N)
+    N2 = N.copy()
+    N2[:, : cam.width // 2] = 0.0
+    m2 = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    m2.integrate(half, rgb, cam, np.eye(4), normals=N2)
+    e1, e2 = m1.export(), m2.export()
+    assert np.array_equal(e1["keys"], e2["keys"]) and np.array_equal(e1["sdf"], e2["sdf"])
