@@ -154,6 +154,17 @@ dtsdf_status dtsdf_integrate(dtsdf_map* map, const float* depth, const uint8_t* 
                              const dtsdf_intrinsics* intr, const double T_world_cam[16],
                              float depth_scale, void* stream, dtsdf_integrate_stats* stats);
 
+/* dtsdf_integrate with the frame's normals given by the caller instead of the cross-product
+ * normals computed from the depth, so that filtered normals (Sec. 7: the cross-product
+ * normals are processed by a bilateral filter, see dtsdf_normal_filter) steer allocation,
+ * direction weights and fusion weights.  normal: device planar (3, H, W) float32 unit
+ * normals in the camera frame facing the camera, all zero = no normal; a pixel without
+ * depth contributes nothing whatever its normal.  DTSDF_E_INVAL if normal is NULL. */
+dtsdf_status dtsdf_integrate_normals(dtsdf_map* map, const float* depth, const float* normal,
+                                     const uint8_t* rgb, const dtsdf_intrinsics* intr,
+                                     const double T_world_cam[16], float depth_scale,
+                                     void* stream, dtsdf_integrate_stats* stats);
+
 /* Render a view of the map (Sec. 4): per pixel, the combined SDF of the six directions
  * (eq. combine_weight, fallback eq. combine_tsdf_weight) is probed at t0 + k * lattice_step
  * from z_near to z_far along the ray; the first step from a positive to a non-positive value

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void request_k(const float* __restrict__ depth
   float nx = nmap[i], ny = nmap[HW + i], nz = nmap[2 * HW + i];
   if (nx == 0.f && ny == 0.f && nz == 0.f) return;
   double z = (double)depth[i] * scale;
+  if (!(z > 0.0) || !isfinite(z)) return;     // a caller normal on a pixel without depth
   double pc[3] = {z * ((double)u - in.cx) / in.fx, z * ((double)v - in.cy) / in.fy, z};
   double len = sqrt(pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]);
   double pw[3], rw[3];
@@ -198,6 +199,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
     const float nx = a.nmap[pi], ny = a.nmap[HW + pi], nz = a.nmap[2 * HW + pi];
     if (nx == 0.f && ny == 0.f && nz == 0.f) continue;
     const double z = (double)a.depth[pi] * a.scale;
+    if (!(z > 0.0) || !isfinite(z)) continue;
     const double pc[3] = {z * ((double)u - a.in.cx) / a.in.fx, z * ((double)v - a.in.cy) / a.in.fy, z};
     // point-to-plane distance (eq. point-to-plane) with the normal facing the camera, so that
     // positive values lie in front of the surface
@@ -329,15 +331,22 @@ dtsdf_status dtsdf_depth_downsample(const float* depth_in, int32_t width, int32_
   return DTSDF_OK;
 }
 
-dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rgb,
-                             const dtsdf_intrinsics* intr, const double T_world_cam[16],
-                             float depth_scale, void* stream, dtsdf_integrate_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// Fusion of one frame; `normal` (device, planar 3 x H x W, camera frame) replaces the
+// cross-product normals when given.
+dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* normal,
+                            const uint8_t* rgb, const dtsdf_intrinsics* intr,
+                            const double T_world_cam[16], float depth_scale, void* stream,
+                            dtsdf_integrate_stats* stats) {
   if (!m || m->regular || !depth || !valid_intr(intr) || !T_world_cam || !(depth_scale > 0))
     return DTSDF_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
   Intr in = make_intr(intr);
   const int64_t HW = (int64_t)in.W * in.H;
-  if (HW > m->img_cap) {
+  if (!normal && HW > m->img_cap) {
     DTSDF_HIP(hipStreamSynchronize(st));
     (void)hipFree(m->vmap);
     (void)hipFree(m->nmap);
@@ -350,15 +359,17 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
   }
   Pose T = make_pose(T_world_cam);
   dim3 blk(16, 16), grd((in.W + 15) / 16, (in.H + 15) / 16);
-  hipLaunchKernelGGL(vertex_normal_k, grd, blk, 0, st, depth, in, (double)depth_scale, m->vmap,
-                     m->nmap);
+  if (!normal)
+    hipLaunchKernelGGL(vertex_normal_k, grd, blk, 0, st, depth, in, (double)depth_scale,
+                       m->vmap, m->nmap);
+  const float* nmap = normal ? normal : m->nmap;
   const int64_t before = m->n_bricks - m->n_free;
   int64_t dropped_now = 0;
   if (!m->p.dense) {
     const double voxel = (double)m->p.voxel_size, tau = (double)m->p.truncation;
     const int J = (int)std::ceil(2.0 * tau / voxel - 1e-9);
     const int32_t max_entries = (int32_t)((uint64_t)m->buckets * 3 / 4);
-    hipLaunchKernelGGL(request_k, grd, blk, 0, st, depth, m->nmap, in, (double)depth_scale, T,
+    hipLaunchKernelGGL(request_k, grd, blk, 0, st, depth, nmap, in, (double)depth_scale, T,
                        voxel, tau, J, m->p.theta, m->entries, m->req, m->buckets - 1,
                        m->counters, max_entries);
     launch_assign(m, st);
@@ -381,7 +392,7 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
     m->n_free = c[10];
   }
   if (m->n_bricks > 0) {
-    FuseArgs fa{depth, rgb, m->nmap, in, (double)depth_scale, T};
+    FuseArgs fa{depth, rgb, nmap, in, (double)depth_scale, T};
     const dim3 grd_b((uint32_t)m->n_bricks);
     if (m->fmt == 0)
       hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
@@ -403,6 +414,24 @@ dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rg
     DTSDF_HIP(hipStreamSynchronize(st));
   }
   return dropped_now > 0 ? DTSDF_E_CAPACITY : DTSDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dtsdf_status dtsdf_integrate(dtsdf_map* m, const float* depth, const uint8_t* rgb,
+                             const dtsdf_intrinsics* intr, const double T_world_cam[16],
+                             float depth_scale, void* stream, dtsdf_integrate_stats* stats) {
+  return integrate_impl(m, depth, nullptr, rgb, intr, T_world_cam, depth_scale, stream, stats);
+}
+
+dtsdf_status dtsdf_integrate_normals(dtsdf_map* m, const float* depth, const float* normal,
+                                     const uint8_t* rgb, const dtsdf_intrinsics* intr,
+                                     const double T_world_cam[16], float depth_scale,
+                                     void* stream, dtsdf_integrate_stats* stats) {
+  if (!normal) return DTSDF_E_INVAL;
+  return integrate_impl(m, depth, normal, rgb, intr, T_world_cam, depth_scale, stream, stats);
 }
 
 }  // extern "C"

@@ -146,6 +146,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
+            "dtsdf_integrate_normals",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -171,6 +172,8 @@ _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
 _lib.icp_step_lm.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                              ctypes.POINTER(_Photo), ctypes.c_int32, ctypes.POINTER(_IcpParams),
                              ctypes.POINTER(_LmState), ctypes.POINTER(_IcpResult), _V]
+_lib.dtsdf_integrate_normals.argtypes = [_V, _V, _V, _V, ctypes.POINTER(_Intr), _D16,
+                                         ctypes.c_float, _V, ctypes.POINTER(_Stats)]
 _lib.dtsdf_recycle.argtypes = [_V, ctypes.c_float, ctypes.POINTER(ctypes.c_int64), _V]
 _lib.dtsdf_depth_filter.argtypes = [_V, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(_DepthFilterParams), _V, _V]
@@ -292,14 +295,22 @@ class Map:
         return {k: getattr(i, k) for k, _ in _Info._fields_}
 
     def integrate(self, depth: torch.Tensor, rgb: Optional[torch.Tensor], cam, T_wc,
-                  depth_scale: float = 1.0, stats: bool = False, stream=None):
+                  depth_scale: float = 1.0, stats: bool = False, stream=None,
+                  normal: Optional[torch.Tensor] = None):
+        """Fuse one frame; ``normal`` (planar (3, H, W) camera-frame unit normals, e.g. from
+        normal_filter) replaces the cross-product normals of the depth."""
         H, W = int(cam.height), int(cam.width)
         st = _Stats() if stats else None
-        status = _lib.dtsdf_integrate(
-            self._h, _dev_ptr(depth, torch.float32, H * W),
-            _dev_ptr(rgb, torch.uint8, H * W * 3) if rgb is not None else None,
-            ctypes.byref(_intr(cam)), _pose(T_wc), depth_scale, _stream(stream),
-            ctypes.byref(st) if st is not None else None)
+        dp = _dev_ptr(depth, torch.float32, H * W)
+        cp = _dev_ptr(rgb, torch.uint8, H * W * 3) if rgb is not None else None
+        sp = ctypes.byref(st) if st is not None else None
+        if normal is None:
+            status = _lib.dtsdf_integrate(self._h, dp, cp, ctypes.byref(_intr(cam)), _pose(T_wc),
+                                          depth_scale, _stream(stream), sp)
+        else:
+            status = _lib.dtsdf_integrate_normals(
+                self._h, dp, _dev_ptr(normal, torch.float32, 3 * H * W), cp,
+                ctypes.byref(_intr(cam)), _pose(T_wc), depth_scale, _stream(stream), sp)
         _check(status, "dtsdf_integrate", allow=(E_CAPACITY,))
         if stats:
             return dict(status=status, new_bricks=st.new_bricks, dropped=st.dropped,

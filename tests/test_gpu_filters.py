@@ -138,3 +138,41 @@ def test_icp_on_preprocessed_frames_matches_oracle(dtsdf):
     print(f"[icp preprocessed] rot {ang:.2e} rad trans {dt:.2e} m, {len(log)} steps, "
           f"|t| {np.linalg.norm(T_g[:3, 3]):.2e} m", flush=True)
     assert ang < 1e-5 and dt < 1e-5
+
+
+def test_fusion_with_given_normals_matches_oracle(dtsdf):
+    """dtsdf_integrate_normals against the oracle fed the same normals: analytic normals of
+    the tiny scene tilted by seeded noise (about 1 degree), float32, on a sparse map; the
+    allocation lies between the oracle's required and allowed sets and the voxels agree at
+    the fusion bars."""
+    cam = synth.scenes.TINY_CAMERA
+    frames = synth.tiny_frames(6)
+    gm = dtsdf.Map(dtsdf.Params(voxel_size=0.01, truncation=0.04, brick_capacity=1 << 15,
+                                hash_buckets=1 << 15))
+    om = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    required, allowed = set(), set()
+    rng = np.random.default_rng(21)
+    for f in frames:
+        N = f["normal"] + rng.normal(scale=0.02, size=f["normal"].shape)
+        N /= np.linalg.norm(N, axis=-1, keepdims=True)
+        N = np.where(f["hit"][..., None], N, 0.0).astype(np.float32)
+        keys, border, alloc = om.requests(f["depth"], cam, f["T_wc"], normals=N)
+        for k, b, a in zip(map(tuple, keys), border, alloc):
+            allowed.add(k)
+            if a and not b:
+                required.add(k)
+        st = gm.integrate(torch.from_numpy(f["depth"]).cuda(), torch.from_numpy(f["rgb"]).cuda(),
+                          cam, f["T_wc"], stats=True,
+                          normal=torch.from_numpy(np.ascontiguousarray(N.transpose(2, 0, 1))).cuda())
+        assert st["dropped"] == 0
+        om.integrate(f["depth"], f["rgb"], cam, f["T_wc"], normals=N.astype(np.float64))
+    gb = gm.export()
+    gset = set(map(tuple, gb["keys"]))
+    print(f"case: fusion with given normals, {len(gset)} bricks, required {len(required)}, "
+          f"allowed {len(allowed)}", flush=True)
+    assert required <= gset and gset <= allowed
+    st = P.compare_maps(gb, om.export(), n_frames=len(frames), name="given normals")
+    assert st["ok"], st
+    with pytest.raises(dtsdf.DtsdfError):
+        dtsdf._check(dtsdf._lib.dtsdf_integrate_normals(gm.handle, None, None, None, None, None,
+                                                         1.0, None, None), "x")
