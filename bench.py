@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-recycle", action="store_true")
+    ap.add_argument("--no-prefuse", action="store_true",
+                    help="skip fusing the frames a second time through the preprocessing")
     ap.add_argument("--batch", type=int, default=32,
                     help="views per launch of the batched render block (1: skip it)")
     ap.add_argument("--serve-requests", type=int, default=600,
@@ -203,6 +205,43 @@ def main():
     log(f"preprocess: depth filter {preprocess['depth_filter_ms']:.3f} ms, normals "
         f"{preprocess['vertex_normal_ms']:.3f} ms, normal filter "
         f"{preprocess['normal_filter_ms']:.3f} ms, removed {np.mean(removed):.4f}")
+    if not args.no_prefuse:
+        # the whole input path of Sec. 7 in fusion: filtered depth, cross-product normals of
+        # it, filtered normals steering a second map; post-fusion error of both maps against
+        # the raw input depth at every 10th pose
+        pm2 = dtsdf.Map(params)
+        e0_, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pre_ms = 0.0
+        for k_, (d_, c_) in enumerate(frames_dev):
+            e0_.record(stream)
+            fd = dtsdf.depth_filter(d_, pre.depth)
+            _, nn = dtsdf.vertex_normal(fd, cam)
+            nf = dtsdf.normal_filter(nn, pre.normal_sigma_d, pre.normal_sigma_r_deg,
+                                     pre.normal_radius)
+            pm2.integrate(fd, c_, cam, poses[k_], normal=nf)
+            e1_.record(stream)
+            e1_.synchronize()
+            pre_ms += e0_.elapsed_time(e1_)
+        m_raw, m_pre, r_raw, r_pre = [], [], [], []
+        for k_ in range(0, n, 10):
+            for mp_, errs_, times_ in ((gm, m_raw, r_raw), (pm2, m_pre, r_pre)):
+                e0_.record(stream)
+                mp_.render(cam, poses[k_], out=out)
+                e1_.record(stream)
+                errs_.append(dtsdf.depth_error(out["depth"], frames_dev[k_][0])[0])
+                e1_.synchronize()
+                times_.append(e0_.elapsed_time(e1_))
+        preprocess["fusion"] = dict(ms_per_frame=pre_ms / n, bricks=pm2.info()["bricks"],
+                                    post_fusion_mae_m=float(np.mean(m_pre)),
+                                    plain_post_fusion_mae_m=float(np.mean(m_raw)),
+                                    render_ms=float(np.mean(r_pre)),
+                                    plain_render_ms=float(np.mean(r_raw)))
+        log(f"preprocessed fusion: {pre_ms / n:.3f} ms/frame (filters + integrate), "
+            f"{pm2.info()['bricks']} bricks, post-fusion MAE {np.mean(m_pre) * 1e3:.3f} mm vs "
+            f"{np.mean(m_raw) * 1e3:.3f} mm plain; render {np.mean(r_pre):.3f} ms vs "
+            f"{np.mean(r_raw):.3f} ms")
+        del pm2
+        torch.cuda.empty_cache()
 
     if args.copy_probe:
         # a plain elementwise kernel reading and writing 256 MiB each (counter calibration)
