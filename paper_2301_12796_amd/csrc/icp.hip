@@ -27,6 +27,7 @@ using namespace dtsdf;
 namespace {
 
 constexpr int kChunks = 128;          // fixed pixel chunks per request (reduction order)
+static_assert(kChunks % 16 == 0, "the solve sums chunks sixteen at a time");
 constexpr int kReduceThreads = 256;
 
 template <int DIM>
@@ -331,6 +332,23 @@ __device__ void exp_sim3(const double* xi, int dim, double* E) {
   E[15] = 1.0;
 }
 
+// Sum of partial sum `k` over the chunks, in chunk order (the fixed reduction order); the
+// loads of 16 chunks are issued before their additions, which keep that order.
+__device__ inline double sum_chunks(const float* __restrict__ partials, int k) {
+  double v = 0.0;
+  for (int c0 = 0; c0 < kChunks; c0 += 16) {
+    float a[16], b[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      a[q] = partials[((size_t)(c0 + q) * kNSMax + k) * 2];
+      b[q] = partials[((size_t)(c0 + q) * kNSMax + k) * 2 + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v += (double)a[q] + (double)b[q];
+  }
+  return v;
+}
+
 // Solves (A) xi = -g by Cholesky (A symmetric DIM x DIM); false if A is not positive definite.
 template <int DIM>
 __device__ bool cholesky_solve(const double* A, const double* g, double* xi) {
@@ -369,13 +387,7 @@ __device__ void solve_lm_one(const float* __restrict__ partials, const IcpJob& j
   constexpr int NS = Sizes<DIM>::NS;
   constexpr int NH = Sizes<DIM>::NH;
   __shared__ double sums[kNSMax];
-  if (threadIdx.x < NS) {
-    double v = 0.0;
-    for (int c = 0; c < kChunks; ++c)
-      v += (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2] +
-           (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2 + 1];
-    sums[threadIdx.x] = v;
-  }
+  if (threadIdx.x < NS) sums[threadIdx.x] = sum_chunks(partials, threadIdx.x);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double H[DIM * DIM], g[DIM], h[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -468,16 +480,13 @@ __device__ void solve_one(const float* __restrict__ partials, const IcpJob& j) {
   constexpr int NS = Sizes<DIM>::NS;
   constexpr int NH = Sizes<DIM>::NH;
   __shared__ double sums[kNSMax];
-  if (threadIdx.x < NS) {
-    double v = 0.0;
-    for (int c = 0; c < kChunks; ++c)
-      v += (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2] +
-           (double)partials[((size_t)c * kNSMax + threadIdx.x) * 2 + 1];
-    sums[threadIdx.x] = v;
-  }
+  if (threadIdx.x < NS) sums[threadIdx.x] = sum_chunks(partials, threadIdx.x);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double H[DIM * DIM], g[DIM], L[DIM * DIM], y[DIM], xi[7] = {0, 0, 0, 0, 0, 0, 0};
+  // the lone solving lane keeps the factorisation in LDS (as private arrays indexed in
+  // loops they would live in scratch memory)
+  __shared__ double H[DIM * DIM], L[DIM * DIM];
+  double g[DIM], y[DIM], xi[7] = {0, 0, 0, 0, 0, 0, 0};
   int s = 0;
   for (int r = 0; r < DIM; ++r)
     for (int c = r; c < DIM; ++c) {
