@@ -610,7 +610,10 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     against the direct six-direction render, and a frame loop in which every frame is fused,
     the conditional-recombination policy (boot up 5, stale 50 frames, 5 cm, 0.05 pi/2 rad)
     decides between a recombination and a fill of the voxels seen for the first time, and
-    the volume is rendered at the frame's pose."""
+    the volume is rendered at the frame's pose.  Frames 100 .. 159 are first registered
+    (three-level ICP, preprocessed live frame, 2 cm / 2 degree offsets) against renders of the
+    volume and, for comparison, of the map.  Timings include the model renders, not the
+    recombination."""
     H, W = cam.height, cam.width
     ev = lambda: torch.cuda.Event(enable_timing=True)
     vol = dtsdf.Volume(gm, brick_capacity=1 << 18, hash_buckets=1 << 18)
@@ -656,8 +659,27 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     pol = dtsdf.RecombinePolicy()
     n_re, loop_ms, direct_ms = 0, [], []
     last = None
+    # tracking inside the loop (frames 100 .. 159, before each is fused): three-level ICP of
+    # the frame against renders of the combined volume and, separately, of the map itself
+    track = dict(volume_ms=[], direct_ms=[], volume_err=[], direct_err=[])
+    rng = np.random.default_rng(17)
+    pre = dtsdf.Preprocess()
     for k, (d_, c_) in enumerate(frames_dev):
         T = poses[k]
+        if 100 <= k < 160 and last is not None:
+            dT0 = synth.perturb_pose(0.02, math.radians(2.0), rng)
+            for name, src in (("volume", fv), ("direct", fm)):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                levels = []
+                for l in range(3):
+                    c = dtsdf.level_camera(cam, l)
+                    o = src.render(c, T, outputs=("vertex", "normal", "mask"))
+                    levels.append((o["vertex"], o["normal"], o["mask"], c))
+                T_est, _ = dtsdf.icp(d_, cam, levels, dT0, preprocess=pre)
+                torch.cuda.synchronize()
+                track[name + "_ms"].append(1e3 * (time.perf_counter() - ta))
+                track[name + "_err"].append(float(np.linalg.norm(T_est[:3, 3])))
         fm.integrate(d_, c_, cam, T)
         torch.cuda.synchronize()
         a_, b_ = ev(), ev()
@@ -693,13 +715,22 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
         volume_device_bytes=vinfo["device_bytes"], volume_blocks=vinfo["blocks"],
         loop_frames=len(frames_dev), loop_recombined=n_re,
         loop_ms_per_frame=float(np.mean(loop_ms)),
-        loop_direct_render_ms=float(np.mean(direct_ms)))
+        loop_direct_render_ms=float(np.mean(direct_ms)),
+        tracking=dict(frames=len(track["volume_ms"]),
+                      volume_icp_ms_per_frame=float(np.mean(track["volume_ms"])),
+                      direct_icp_ms_per_frame=float(np.mean(track["direct_ms"])),
+                      volume_translation_median_m=float(np.median(track["volume_err"])),
+                      direct_translation_median_m=float(np.median(track["direct_err"]))))
     log(f"volume: combine {res['combine_ms']:.2f} ms, render {res['render_ms']:.2f} ms "
         f"({res['render_rays_per_s'] / 1e6:.1f} M rays/s), depth vs direct median "
         f"{res['vs_direct_depth_median_m']:.2e} m, >1 cm {res['vs_direct_depth_over_1cm']:.4f}, "
         f"mask mismatch {res['vs_direct_mask_mismatch']:.4f}; loop: {n_re}/{len(frames_dev)} "
         f"recombined, {res['loop_ms_per_frame']:.2f} ms/frame (combine or fill + render) vs "
         f"direct render {res['loop_direct_render_ms']:.2f} ms")
+    tr_ = res["tracking"]
+    log(f"tracking against the volume: {tr_['volume_icp_ms_per_frame']:.2f} ms/frame, residual "
+        f"{tr_['volume_translation_median_m']:.2e} m; against the map: "
+        f"{tr_['direct_icp_ms_per_frame']:.2f} ms/frame, {tr_['direct_translation_median_m']:.2e} m")
     return res
 
 
