@@ -320,6 +320,12 @@ struct dtsdf_map {
   // grows; counters[10] holds their number on the device, n_free its host mirror
   int32_t* free_list;
   int64_t n_free;
+  // bricks whose voxels may project into the frame being fused (counters[11] of them)
+  int32_t* vis_list;
+  // per pixel of the frame being fused: 1 if no valid depth within two pixels differs from
+  // the pixel's by more than tau (the carving guard of Sec. 3)
+  uint8_t* carve_ok;
+  int64_t carve_cap;
   // integration scratch, grown on demand
   int64_t img_cap;
   float* vmap;

@@ -287,12 +287,13 @@ __global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict_
   for (int gy = 0; gy < 4; ++gy) out[gy] = bytes[gy];
 }
 
-// Also clamps the free-list count (counters[10]) at zero: pops by the allocation that ran
-// before may have driven it below.
+// Also clamps the free-list count (counters[10]) at zero (pops by the allocation that ran
+// before may have driven it below) and clears the visible-brick count (counters[11]).
 __global__ void bbox_reset_k(int32_t* counters) {
   if (threadIdx.x < 3) counters[4 + threadIdx.x] = INT_MAX;
   else if (threadIdx.x < 6) counters[4 + threadIdx.x] = INT_MIN;
   else if (threadIdx.x == 6 && counters[10] < 0) counters[10] = 0;
+  else if (threadIdx.x == 7) counters[11] = 0;
 }
 
 }  // namespace

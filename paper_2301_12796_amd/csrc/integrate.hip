@@ -6,7 +6,9 @@
 //   2. request_k         (sparse maps) block requests along p +/- tau r for every direction
 //                        with w_dir > 0, inserted into the spatial hash by CAS
 //   3. assign_k          pool indices for newly requested (block, D) bricks
-//   4. fuse_k            voxel-projection fusion of every allocated brick, one workgroup per
+//   4. carve_guard_k     the carving guard of every pixel (depth jumps within two pixels)
+//   5. cull_k            conservative frustum test per brick: the list of bricks to visit
+//   6. fuse_k            voxel-projection fusion of every listed brick, one workgroup per
 //                        brick, 256 threads x 2 voxels: HBM streaming of (sdf, w) (+ colour)
 // Geometry (projection, point-to-plane distance) is evaluated in float64 so that the
 // discrete decisions (pixel association, band tests) match an exact evaluation except on
@@ -161,21 +163,96 @@ __global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* re
   }
 }
 
+// The carving guard of Sec. 3 per pixel: carving through pixel p is allowed unless a valid
+// depth within a radius of two pixels differs from p's by more than tau.  It depends on the
+// pixel only, so it is taken once per pixel instead of once per carved voxel.
+__global__ __launch_bounds__(256) void carve_guard_k(const float* __restrict__ depth, Intr in,
+                                                     double scale, double tau, int enabled,
+                                                     uint8_t* __restrict__ ok_out) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y * blockDim.y + threadIdx.y;
+  if (u >= in.W || v >= in.H) return;
+  const double z = (double)depth[(size_t)v * in.W + u] * scale;
+  bool ok = enabled != 0;
+  for (int dv = -2; dv <= 2 && ok; ++dv)
+    for (int du = -2; du <= 2; ++du) {
+      int uu = u + du, vv = v + dv;
+      if (uu < 0 || vv < 0 || uu >= in.W || vv >= in.H) continue;
+      double z1 = (double)depth[(size_t)vv * in.W + uu] * scale;
+      if (!(z1 > 0.0)) continue;
+      if (fabs(z1 - z) > tau) {
+        ok = false;
+        break;
+      }
+    }
+  ok_out[(size_t)v * in.W + u] = ok ? 1 : 0;
+}
+
 struct FuseArgs {
   const float* depth;
   const uint8_t* rgb;
   const float* nmap;
+  const uint8_t* carve_ok;
   Intr in;
   double scale;
   Pose T;
 };
 
+__global__ void vis_reset_k(int32_t* counters) {
+  if (threadIdx.x == 0) counters[11] = 0;
+}
+
+// Conservative frustum test of every brick in the pool, one thread per brick: a brick is
+// listed unless all its voxel centres provably project outside the image or lie behind the
+// camera (the centres lie in the box of its eight corner centres, whose projection bounds
+// theirs when every corner is in front of the camera).  Fusion then visits the listed
+// bricks only; a brick left out would have had no voxel updated.
+__global__ __launch_bounds__(256) void cull_k(const int4* __restrict__ bkey, int n, Pose T,
+                                              Intr in, double voxel, int32_t* list,
+                                              int32_t* counters) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  const int4 key = bkey[b];
+  if (key.w < 0) return;
+  double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+  int front = 0;
+  for (int c = 0; c < 8; ++c) {
+    const double x[3] = {(double)(key.x * kB + ((c & 1) ? kB - 1 : 0)) * voxel,
+                         (double)(key.y * kB + ((c & 2) ? kB - 1 : 0)) * voxel,
+                         (double)(key.z * kB + ((c & 4) ? kB - 1 : 0)) * voxel};
+    const double xr[3] = {x[0] - T.t[0], x[1] - T.t[1], x[2] - T.t[2]};
+    double xc[3];
+    for (int k = 0; k < 3; ++k)
+      xc[k] = T.R[k] * xr[0] + T.R[3 + k] * xr[1] + T.R[6 + k] * xr[2];
+    if (!(xc[2] > 0.0)) continue;
+    ++front;
+    const double uf = in.fx * xc[0] / xc[2] + in.cx, vf = in.fy * xc[1] / xc[2] + in.cy;
+    umin = fmin(umin, uf);
+    umax = fmax(umax, uf);
+    vmin = fmin(vmin, vf);
+    vmax = fmax(vmax, vf);
+  }
+  if (front == 0) return;                 // every voxel behind the camera
+  if (front == 8) {
+    // a voxel is used when floor(uf + 0.5) lies in [0, W), i.e. uf in [-0.5, W - 0.5)
+    constexpr double kMargin = 1e-3;      // pixels, for rounding between the two evaluations
+    if (umax < -0.5 - kMargin || vmax < -0.5 - kMargin || umin > in.W - 0.5 + kMargin ||
+        vmin > in.H - 0.5 + kMargin)
+      return;
+  }
+  list[atomicAdd(&counters[11], 1)] = b;
+}
+
 // Voxel-projection fusion (Sec. 3) of one brick per workgroup.  A brick with any updated
 // voxel refreshes its sub-block minima (sdf over voxels with w > 0) for the render index.
 template <int F>
 __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min,
-                                              uint64_t* brick_neg) {
-  const int4 key = m.bkey[blockIdx.x];
+                                              uint64_t* brick_neg,
+                                              const int32_t* __restrict__ list,
+                                              const int32_t* __restrict__ counters) {
+  if ((int)blockIdx.x >= counters[11]) return;   // the grid covers the whole pool
+  const int b = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
+  const int4 key = m.bkey[b];
   const int D = key.w;
   if (D < 0) return;                      // a recycled brick on the free list
   const size_t HW = (size_t)a.in.W * a.in.H;
@@ -204,23 +281,11 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
     // point-to-plane distance (eq. point-to-plane) with the normal facing the camera, so that
     // positive values lie in front of the surface
     const double dd = ((xc[0] - pc[0]) * nx + (xc[1] - pc[1]) * ny + (xc[2] - pc[2]) * nz) / tau;
-    const size_t vi = (size_t)blockIdx.x * kVox + l;
+    const size_t vi = (size_t)b * kVox + l;
     if (dd > 1.0) {
       // free space: value 1 with a constant weight unless a depth jump above tau lies within
-      // two pixels (Sec. 3)
-      bool ok = m.w_carve > 0.f;
-      for (int dv = -2; dv <= 2 && ok; ++dv)
-        for (int du = -2; du <= 2; ++du) {
-          int uu = u + du, vv = v + dv;
-          if (uu < 0 || vv < 0 || uu >= a.in.W || vv >= a.in.H) continue;
-          double z1 = (double)a.depth[(size_t)vv * a.in.W + uu] * a.scale;
-          if (!(z1 > 0.0)) continue;
-          if (fabs(z1 - z) > tau) {
-            ok = false;
-            break;
-          }
-        }
-      if (ok) {
+      // two pixels (Sec. 3; carve_guard_k)
+      if (a.carve_ok[pi]) {
         float sd, w;
         Vox<F>::load(m.geo, vi, sd, w);
         const float nw = w + m.w_carve;
@@ -271,8 +336,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
     }
   }
   if (__syncthreads_or(upd))
-    brick_sub_min<F>(m.geo, blockIdx.x, sub_min + (size_t)blockIdx.x * 8,
-                     brick_neg + (size_t)blockIdx.x * 16);
+    brick_sub_min<F>(m.geo, b, sub_min + (size_t)b * 8, brick_neg + (size_t)b * 16);
 }
 
 Intr make_intr(const dtsdf_intrinsics* i) {
@@ -391,18 +455,34 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
     m->n_blocks = c[3];
     m->n_free = c[10];
   }
+  if (m->n_bricks > 0 && HW > m->carve_cap) {
+    DTSDF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(m->carve_ok);
+    m->carve_ok = nullptr;
+    m->carve_cap = 0;
+    if (hipMalloc(&m->carve_ok, (size_t)HW) != hipSuccess) return DTSDF_E_NOMEM;
+    m->carve_cap = HW;
+  }
   if (m->n_bricks > 0) {
-    FuseArgs fa{depth, rgb, nmap, in, (double)depth_scale, T};
-    const dim3 grd_b((uint32_t)m->n_bricks);
+    hipLaunchKernelGGL(carve_guard_k, grd, blk, 0, st, depth, in, (double)depth_scale,
+                       (double)m->p.truncation, m->p.w_carve > 0.f ? 1 : 0, m->carve_ok);
+    // the visible-brick count starts at zero: cleared by the bounding-box reset of the
+    // sparse path above, here for dense maps
+    if (m->p.dense) hipLaunchKernelGGL(vis_reset_k, dim3(1), dim3(64), 0, st, m->counters);
+    const int n = (int)m->n_bricks;
+    hipLaunchKernelGGL(cull_k, dim3((n + 255) / 256), dim3(256), 0, st, m->bkey, n, T, in,
+                       (double)m->p.voxel_size, m->vis_list, m->counters);
+    FuseArgs fa{depth, rgb, nmap, m->carve_ok, in, (double)depth_scale, T};
+    const dim3 grd_b((uint32_t)n);
     if (m->fmt == 0)
       hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
-                         m->brick_neg);
+                         m->brick_neg, m->vis_list, m->counters);
     else if (m->fmt == 1)
       hipLaunchKernelGGL(fuse_k<1>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
-                         m->brick_neg);
+                         m->brick_neg, m->vis_list, m->counters);
     else
       hipLaunchKernelGGL(fuse_k<2>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
-                         m->brick_neg);
+                         m->brick_neg, m->vis_list, m->counters);
   }
   DTSDF_HIP(hipGetLastError());
   dtsdf_status is = launch_index_update(m, st);

@@ -117,6 +117,8 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->wc);
   (void)hipFree(m->counters);
   (void)hipFree(m->free_list);
+  (void)hipFree(m->vis_list);
+  (void)hipFree(m->carve_ok);
   (void)hipFree(m->vmap);
   (void)hipFree(m->nmap);
   (void)hipFree(m->sub_min);
@@ -210,6 +212,7 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
             hipMalloc(&m->bkey, sizeof(int4) * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->geo, geo_bytes(m->fmt) * nv) == hipSuccess &&
             hipMalloc(&m->counters, sizeof(int32_t) * 16) == hipSuccess &&
+            hipMalloc(&m->vis_list, sizeof(int32_t) * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess &&
             hipMalloc(&m->brick_neg, sizeof(uint64_t) * 16 * p->brick_capacity) == hipSuccess &&
@@ -268,7 +271,8 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
                                 geo_bytes(m->fmt) * nv +
                                 (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
                                 (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap +
-                                (m->free_list ? sizeof(int32_t) * m->p.brick_capacity : 0));
+                                (m->free_list ? sizeof(int32_t) * m->p.brick_capacity : 0) +
+                                sizeof(int32_t) * m->p.brick_capacity);
   return DTSDF_OK;
 }
 
