@@ -1,4 +1,5 @@
 // Per-brick summaries and the dense render index (see dtsdf_internal.hpp).
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -25,16 +26,21 @@ __device__ inline bool slot_present(const HashEntry& e) {
 
 // Bounding box of the occupied blocks: min/max folded across the wave with xor shuffles and
 // across the workgroup in LDS, so each workgroup issues six atomics.
+// A fixed grid strides over the table, so that few workgroups contend for the six atomics.
+constexpr int kBboxBlocks = 512;
 __global__ __launch_bounds__(256) void bbox_k(const HashEntry* __restrict__ e, uint32_t buckets,
                                               int32_t* bbox) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   int v[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
-  if (s < buckets) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < buckets;
+       s += gridDim.x * blockDim.x) {
     const HashEntry ent = e[s];
     if (slot_present(ent)) {
       int b[3];
       unpack_key(ent.key, b[0], b[1], b[2]);
-      for (int k = 0; k < 3; ++k) v[k] = v[3 + k] = b[k];
+      for (int k = 0; k < 3; ++k) {
+        v[k] = min(v[k], b[k]);
+        v[3 + k] = max(v[3 + k], b[k]);
+      }
     }
   }
 #pragma unroll
@@ -317,8 +323,8 @@ dtsdf_status brick_stats(dtsdf_map* m, hipStream_t st) {
 void launch_bbox(dtsdf_map* m, hipStream_t st) {
   int32_t* bbox = m->counters + 4;
   hipLaunchKernelGGL(bbox_reset_k, dim3(1), dim3(64), 0, st, m->counters);
-  hipLaunchKernelGGL(bbox_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
-                     m->buckets, bbox);
+  const uint32_t blocks = std::min<uint32_t>((m->buckets + 255) / 256, kBboxBlocks);
+  hipLaunchKernelGGL(bbox_k, dim3(blocks), dim3(256), 0, st, m->entries, m->buckets, bbox);
 }
 
 dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st) {
