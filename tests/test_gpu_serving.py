@@ -189,3 +189,24 @@ def test_server_memory_budget_limits_admission(dtsdf, tiny_map):
     assert len(done) == 4 and srv.peak_bytes <= big
     with pytest.raises(ValueError):
         serve.Server(tiny_map, sensors, slots=2, budget_bytes=big - 1)
+
+
+def test_render_batch_room_views_match_single_renders(dtsdf):
+    """Eight 640x480 views of a room map fused from 20 frames rendered in one persistent
+    launch (the bench's batched form) equal the one-view launches bitwise."""
+    cam = P.ROOM_CAM
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf))
+    for f in synth.room_frames(range(0, 300, 15), device="cuda"):
+        gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), cam, f["T_wc"])
+    poses = [synth.room_pose(k) for k in range(7, 300, 37)]
+    outs = [_alloc(cam) for _ in poses]
+    gm.render_batch([(cam, T, 0.2, 10.0, o) for T, o in zip(poses, outs)])
+    hits = 0
+    for T, o in zip(poses, outs):
+        ref = P.to_numpy_out(gm.render(cam, T))
+        got = P.to_numpy_out(o)
+        for k in ("depth", "vertex", "normal", "rgba", "mask"):
+            assert np.array_equal(got[k], ref[k]), k
+        hits += int(ref["mask"].sum())
+    print(f"case: batched room views, {len(poses)} views, {hits} hits", flush=True)
+    assert hits > 0.9 * len(poses) * cam.width * cam.height
