@@ -380,10 +380,12 @@ def main():
                               frames_dev)
 
     # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
-    icp_ms = icp_rgb_ms = icp_rgb_err = None
+    icp_ms = icp_dev_ms = icp_rgb_ms = icp_rgb_err = None
+    same = None
     if not args.no_icp:
         icp_frames = list(range(5, n, max(1, n // 10)))[:10]
-        tot = 0.0
+        tot = tot_dev = 0.0
+        same = True
         errs = []
         rng = np.random.default_rng(3)
         for k in icp_frames:
@@ -403,8 +405,19 @@ def main():
             torch.cuda.synchronize()
             tot += time.perf_counter() - ta
             errs.append(float(np.linalg.norm(T_est[:3, 3])))
+            # the same registration with the model pyramid rendered in one batched launch and
+            # every level's iterations enqueued on the device
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            levels = dtsdf.render_levels(gm, cam, T)
+            T_dev = dtsdf.icp_device(live, cam, levels, dT0, preprocess=pre)
+            torch.cuda.synchronize()
+            tot_dev += time.perf_counter() - ta
+            same = same and bool(np.array_equal(T_dev, T_est))
         icp_ms = 1e3 * tot / len(icp_frames)
-        log(f"icp: {icp_ms:.2f} ms/frame, residual translation median {np.median(errs):.2e} m")
+        icp_dev_ms = 1e3 * tot_dev / len(icp_frames)
+        log(f"icp: {icp_ms:.2f} ms/frame, residual translation median {np.median(errs):.2e} m; "
+            f"device loop {icp_dev_ms:.2f} ms/frame, same pose: {same}")
         # combined geometric + photometric ICP against a keyframe (the textured frame of the
         # last multiple of 10, Sec. 5.3), three levels, same offsets
         tot_rgb, errs_rgb = 0.0, []
@@ -586,6 +599,8 @@ def main():
         "cpu_baseline": cpu,
         "integrate_ms_per_frame": integ_ms / n,
         "icp_ms_per_frame": icp_ms,
+        "icp_device_loop_ms_per_frame": icp_dev_ms,
+        "icp_device_loop_same_pose": same,
         "icp_rgb_keyframe_ms_per_frame": icp_rgb_ms,
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
         "batched": batched,
@@ -611,8 +626,9 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     the conditional-recombination policy (boot up 5, stale 50 frames, 5 cm, 0.05 pi/2 rad)
     decides between a recombination and a fill of the voxels seen for the first time, and
     the volume is rendered at the frame's pose.  Frames 100 .. 159 are first registered
-    (three-level ICP, preprocessed live frame, 2 cm / 2 degree offsets) against renders of the
-    volume and, for comparison, of the map.  Timings include the model renders, not the
+    (three-level ICP, preprocessed live frame, 2 cm / 2 degree offsets; model pyramid in one
+    batched launch, iterations enqueued on the device) against renders of the volume and,
+    for comparison, of the map.  Timings include the model renders, not the
     recombination."""
     H, W = cam.height, cam.width
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -671,12 +687,8 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
             for name, src in (("volume", fv), ("direct", fm)):
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
-                levels = []
-                for l in range(3):
-                    c = dtsdf.level_camera(cam, l)
-                    o = src.render(c, T, outputs=("vertex", "normal", "mask"))
-                    levels.append((o["vertex"], o["normal"], o["mask"], c))
-                T_est, _ = dtsdf.icp(d_, cam, levels, dT0, preprocess=pre)
+                levels = dtsdf.render_levels(src, cam, T)
+                T_est = dtsdf.icp_device(d_, cam, levels, dT0, preprocess=pre)
                 torch.cuda.synchronize()
                 track[name + "_ms"].append(1e3 * (time.perf_counter() - ta))
                 track[name + "_err"].append(float(np.linalg.norm(T_est[:3, 3])))

@@ -347,6 +347,14 @@ typedef struct {
  * identical to stepping it alone.  Enqueues on `stream`; does not synchronise. */
 dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream);
 
+/* `iterations` steps of icp_step_batch enqueued from one upload of the requests: every step
+ * continues from the poses the previous one wrote in device memory, and a request whose
+ * flag dropped to 0 (converged or degenerate) is skipped on the device, so a coarse-to-fine
+ * level runs with no host wait (Sec. 5: the iterations of one pyramid level).  Equal, per
+ * request, to that many icp_step_batch calls.  1 <= iterations <= 1000. */
+dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* reqs, int32_t iterations,
+                                  void* stream);
+
 /* ---- View-dependent combined ("rendering") TSDF (Sec. 4) -------------------------------
  * For a fixed camera position the six directional TSDFs can be merged into one conflict-free
  * regular TSDF (Sec. 4, Lemma positional_unambiguity); ray casting that volume from (near)

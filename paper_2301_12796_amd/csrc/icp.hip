@@ -801,8 +801,17 @@ extern "C" dtsdf_status icp_step_lm(const dtsdf_image* live, const dtsdf_image* 
   return DTSDF_OK;
 }
 
+extern "C" dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* reqs,
+                                             int32_t iterations, void* stream);
+
 extern "C" dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream) {
-  if (n < 0 || (n > 0 && !reqs) || n > 65535) return DTSDF_E_INVAL;
+  return icp_step_batch_iters(n, reqs, 1, stream);
+}
+
+extern "C" dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* reqs,
+                                             int32_t iterations, void* stream) {
+  if (n < 0 || (n > 0 && !reqs) || n > 65535 || iterations < 1 || iterations > 1000)
+    return DTSDF_E_INVAL;
   if (n == 0) return DTSDF_OK;
   std::vector<IcpJob> jobs((size_t)n);
   for (int r = 0; r < n; ++r)
@@ -820,8 +829,12 @@ extern "C" dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, voi
   } else {
     const IcpJob* dj = reinterpret_cast<const IcpJob*>(dev);
     float* part = reinterpret_cast<float*>(dev + jb);
-    hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
-    hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+    // the descriptors hold device pointers to each request's pose and flag, so the same
+    // launches repeated continue from the poses the previous ones wrote
+    for (int it = 0; it < iterations; ++it) {
+      hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
+      hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+    }
     if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
   }
   if (hipFreeAsync(dev, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;

@@ -146,7 +146,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
-            "dtsdf_integrate_normals",
+            "dtsdf_integrate_normals", "icp_step_batch_iters",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -166,6 +166,7 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
                           ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
+_lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), ctypes.c_int32, _V]
 _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                               ctypes.POINTER(_Photo), ctypes.c_int32,
                               ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
@@ -807,6 +808,63 @@ def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
             if res["step_norm"] < min_step:
                 break
     return T, log
+
+
+def render_levels(src, cam, T_wc, levels: int = 3, z_near: float = 0.2, z_far: float = 10.0,
+                  stream=None):
+    """Model pyramid for ICP: vertex, normal and mask of ``src`` (a Map or a Volume) at pose
+    T_wc for pyramid levels 0 .. levels-1, all rendered in one batched launch (the levels'
+    tails overlap); each level equals src.render of that level bitwise.  Returns
+    [(vertex, normal, mask, cam_l)]."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    views, out = [], []
+    for l in range(levels):
+        c = level_camera(cam, l)
+        H, W = int(c.height), int(c.width)
+        o = dict(vertex=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                 normal=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                 mask=torch.empty((H, W), dtype=torch.uint8, device=dev))
+        views.append((c, T_wc, z_near, z_far, o))
+        out.append((o["vertex"], o["normal"], o["mask"], c))
+    src.render_batch(views, stream=stream)
+    return out
+
+
+def icp_device(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
+               iters=(10, 5, 4), params: IcpParams = IcpParams(), min_step: float = 1e-6,
+               depth_scale: float = 1.0, stream=None, preprocess: Optional[Preprocess] = None,
+               live_rgb: Optional[torch.Tensor] = None, ref_levels=None, T_ref_model=None,
+               lam: float = 0.1, max_error=(0.05, 0.175, 0.175)):
+    """The coarse-to-fine ICP of icp() with the pose, the convergence flag and the sums kept
+    in device memory: each level's iterations are enqueued by one icp_step_batch_iters call
+    without a host wait (a converged or degenerate level skips its remaining iterations on
+    the device), and the pose is copied back once.  Same steps, same result as icp()."""
+    L = len(model_levels)
+    live = _live_levels(live_depth, live_cam, L, depth_scale, preprocess, stream)
+    ipyr = None
+    if live_rgb is not None:
+        ipyr = [intensity(live_rgb, stream=stream)]
+        for _ in range(1, L):
+            ipyr.append(intensity_downsample(ipyr[-1], stream=stream))
+    Tref = np.eye(4) if T_ref_model is None else np.asarray(T_ref_model, np.float64)
+    dev = live_depth.device
+    pose = torch.tensor(np.asarray(T0, np.float64), dtype=torch.float64, device=dev)
+    active = torch.ones(1, dtype=torch.int32, device=dev)
+    for l in reversed(range(L)):
+        cam_l, v, n = live[l]
+        mv, mn, mm, mcam = model_levels[l]
+        active.fill_(1)
+        st = icp_request_struct(IcpRequest(v, n, cam_l, mv, mn, mm, mcam, pose, active, None,
+                                           dim, params, min_step))
+        ph = None
+        if ipyr is not None:
+            ri, rcam = ref_levels[l]
+            ph = Photo(ipyr[l], ri, rcam, Tref, lam, max_error[l]).c_struct(cam_l)
+            st.photo = ctypes.addressof(ph)
+        reqs = (_IcpReq * 1)(st)
+        _check(_lib.icp_step_batch_iters(1, reqs, int(iters[l]), _stream(stream)),
+               "icp_step_batch_iters")
+    return pose.cpu().numpy()
 
 
 @dataclasses.dataclass(frozen=True)

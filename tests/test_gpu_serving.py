@@ -210,3 +210,48 @@ def test_render_batch_room_views_match_single_renders(dtsdf):
         hits += int(ref["mask"].sum())
     print(f"case: batched room views, {len(poses)} views, {hits} hits", flush=True)
     assert hits > 0.9 * len(poses) * cam.width * cam.height
+
+
+@pytest.mark.parametrize("dim,photo", [(6, False), (7, False), (6, True)])
+def test_device_loop_icp_equals_host_loop(dtsdf, dim, photo):
+    """icp_device (every iteration enqueued through icp_step_batch, pose and convergence flag
+    on the device) gives bitwise the pose of the host loop icp(), on a preprocessed room
+    frame, in SE(3), Sim(3) and combined with the photometric term."""
+    sc = synth.room_scene()
+    cam = P.ROOM_CAM
+    T = synth.room_pose(70)
+    s = 1.0 if dim == 6 else 1.03
+    f = synth.render_frame(sc, cam, T, noise="quadratic", sigma=0.0012, seed=9, depth_scale=s,
+                           texture_period=0.25)
+    dT0 = synth.perturb_pose(0.02, math.radians(2.0), np.random.default_rng(11))
+    levels, refs = [], []
+    ri = dtsdf.intensity(_dev(synth.render_frame(sc, cam, T, texture_period=0.25)["rgb"]))
+    for l in range(3):
+        c = cam.level(l)
+        g = synth.render_frame(sc, c, T)
+        V = (c.pixel_rays() * g["true_depth"][..., None]).astype(np.float32)
+        levels.append((_dev(V.transpose(2, 0, 1)), _dev(g["normal"].astype(np.float32).transpose(2, 0, 1)),
+                       _dev(g["hit"].astype(np.uint8)), c))
+        refs.append((ri, c))
+        if l < 2:
+            ri = dtsdf.intensity_downsample(ri)
+    kw = dict(dim=dim, preprocess=dtsdf.Preprocess())
+    if photo:
+        kw.update(live_rgb=_dev(f["rgb"]), ref_levels=refs)
+    T_host, log = dtsdf.icp(_dev(f["depth"]), cam, levels, dT0, **kw)
+    T_dev = dtsdf.icp_device(_dev(f["depth"]), cam, levels, dT0, **kw)
+    print(f"case: device-loop icp dim={dim} photo={photo}: {len(log)} host steps, "
+          f"|t| {np.linalg.norm(T_dev[:3, 3]):.2e} m", flush=True)
+    assert np.array_equal(T_host, T_dev)
+
+
+def test_render_levels_equal_single_renders(dtsdf, tiny_map):
+    """The model pyramid in one batched launch equals the three single renders bitwise."""
+    cam = synth.scenes.Camera(320, 240, 240.0, 240.0, 159.5, 119.5)
+    T = synth.tiny_render_pose(0.7)
+    lv = dtsdf.render_levels(tiny_map, cam, T)
+    for v, n, m, c in lv:
+        ref = tiny_map.render(c, T, outputs=("vertex", "normal", "mask"))
+        assert torch.equal(v, ref["vertex"]) and torch.equal(n, ref["normal"])
+        assert torch.equal(m, ref["mask"])
+    assert int(lv[0][2].sum()) > 1000
