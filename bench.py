@@ -380,8 +380,8 @@ def main():
                               frames_dev)
 
     # ---- ICP: three-level point-to-plane SE(3) per frame (10/5/4 iterations) -----------
-    icp_ms = icp_dev_ms = icp_rgb_ms = icp_rgb_err = None
-    same = None
+    icp_ms = icp_dev_ms = icp_rgb_ms = icp_rgb_dev_ms = icp_rgb_err = None
+    same = same_rgb = None
     if not args.no_icp:
         icp_frames = list(range(5, n, max(1, n // 10)))[:10]
         tot = tot_dev = 0.0
@@ -420,7 +420,7 @@ def main():
             f"device loop {icp_dev_ms:.2f} ms/frame, same pose: {same}")
         # combined geometric + photometric ICP against a keyframe (the textured frame of the
         # last multiple of 10, Sec. 5.3), three levels, same offsets
-        tot_rgb, errs_rgb = 0.0, []
+        tot_rgb, tot_rgb_dev, errs_rgb, same_rgb = 0.0, 0.0, [], True
         rng = np.random.default_rng(3)
         for k in icp_frames:
             T = poses[k]
@@ -449,10 +449,27 @@ def main():
             torch.cuda.synchronize()
             tot_rgb += time.perf_counter() - ta
             errs_rgb.append(float(np.linalg.norm(T_est[:3, 3])))
+            # the fast path: model pyramid in one batched launch, iterations on the device
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ri = dtsdf.intensity(kf_rgb)
+            refs = []
+            for l in range(3):
+                refs.append((ri, dtsdf.level_camera(cam, l)))
+                if l < 2:
+                    ri = dtsdf.intensity_downsample(ri)
+            levels = dtsdf.render_levels(gm, cam, T)
+            T_dev = dtsdf.icp_device(live, cam, levels, dT0, live_rgb=live_rgb, ref_levels=refs,
+                                     T_ref_model=np.linalg.inv(T_kf) @ T, preprocess=pre)
+            torch.cuda.synchronize()
+            tot_rgb_dev += time.perf_counter() - ta
+            same_rgb = same_rgb and bool(np.array_equal(T_dev, T_est))
         icp_rgb_ms = 1e3 * tot_rgb / len(icp_frames)
+        icp_rgb_dev_ms = 1e3 * tot_rgb_dev / len(icp_frames)
         icp_rgb_err = float(np.median(errs_rgb))
         log(f"combined icp (keyframe): {icp_rgb_ms:.2f} ms/frame, residual translation "
-            f"median {icp_rgb_err:.2e} m")
+            f"median {icp_rgb_err:.2e} m; fast path {icp_rgb_dev_ms:.2f} ms/frame, same pose: "
+            f"{same_rgb}")
 
     # ---- multi-sensor Sim(3) refinement: five sensors with scaled depth, taking turns
     # frame by frame, each frame registered by Levenberg-Marquardt Sim(3) ICP (10/5/4) from a
@@ -602,6 +619,8 @@ def main():
         "icp_device_loop_ms_per_frame": icp_dev_ms,
         "icp_device_loop_same_pose": same,
         "icp_rgb_keyframe_ms_per_frame": icp_rgb_ms,
+        "icp_rgb_keyframe_device_loop_ms_per_frame": icp_rgb_dev_ms,
+        "icp_rgb_keyframe_device_loop_same_pose": same_rgb,
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
         "batched": batched,
         "multi_sensor": multi,
