@@ -490,11 +490,7 @@ def main():
             dT0[:3, :3] *= 1.01 / scales[i]
             torch.cuda.synchronize()
             ta = time.perf_counter()
-            levels = []
-            for l in range(3):
-                c = dtsdf.level_camera(cam, l)
-                o = gm.render(c, T, outputs=("vertex", "normal", "mask"))
-                levels.append((o["vertex"], o["normal"], o["mask"], c))
+            levels = dtsdf.render_levels(gm, cam, T)      # model pyramid in one launch
             T_est, _ = dtsdf.icp_lm(live, cam, levels, dT0, dim=7, preprocess=pre)
             torch.cuda.synchronize()
             tot += time.perf_counter() - ta
