@@ -37,3 +37,44 @@ def test_status_strings_without_device():
 def test_binding_declares_the_same_symbols():
     from paper_2301_12796_amd import dtsdf
     assert sorted(dtsdf.EXPORTED) == declared_functions()
+
+
+def test_argument_validation_without_device():
+    """Entry points reject malformed arguments on the host, before any device call."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2301_12796_amd", "libdtsdf.so"))
+    V = ctypes.c_void_p
+    E_INVAL = 1
+    for f in ("icp_step_batch_iters", "icp_step_batch", "dtsdf_depth_filter",
+              "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
+              "dtsdf_integrate_normals", "icp_step_lm"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, V, ctypes.c_int32, V]
+    assert lib.icp_step_batch_iters(1, None, 3, None) == E_INVAL          # no requests
+    assert lib.icp_step_batch_iters(0, None, 0, None) == E_INVAL          # no iterations
+    assert lib.icp_step_batch_iters(0, None, 1001, None) == E_INVAL
+    assert lib.icp_step_batch_iters(0, None, 4, None) == 0                # nothing to do
+    lib.icp_step_batch.argtypes = [ctypes.c_int32, V, V]
+    assert lib.icp_step_batch(-1, None, None) == E_INVAL
+
+    class DF(ctypes.Structure):
+        _fields_ = [("support_rel", ctypes.c_float), ("min_support", ctypes.c_int32),
+                    ("sigma_d", ctypes.c_float), ("sigma_r", ctypes.c_float),
+                    ("radius", ctypes.c_int32)]
+    lib.dtsdf_depth_filter.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(DF), V, V]
+    a, b = V(16), V(32)              # never dereferenced: every call below is rejected first
+    assert lib.dtsdf_depth_filter(a, 64, 48, ctypes.byref(DF(0.02, 2, 5.0, 0.025, 9)), b, None) == E_INVAL
+    assert lib.dtsdf_depth_filter(a, 64, 48, ctypes.byref(DF(0.02, 9, 5.0, 0.025, 5)), b, None) == E_INVAL
+    assert lib.dtsdf_depth_filter(a, 64, 48, ctypes.byref(DF(0.02, 2, 5.0, 0.0, 5)), b, None) == E_INVAL
+    assert lib.dtsdf_depth_filter(a, 64, 48, ctypes.byref(DF(0.02, 2, 5.0, 0.025, 5)), a, None) == E_INVAL
+    lib.dtsdf_normal_filter.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                        ctypes.c_float, ctypes.c_int32, V, V]
+    assert lib.dtsdf_normal_filter(a, 64, 48, 2.5, 5.0, 9, b, None) == E_INVAL
+    assert lib.dtsdf_normal_filter(a, 64, 48, 0.0, 5.0, 5, b, None) == E_INVAL
+    lib.dtsdf_depth_error.argtypes = [V, V, ctypes.c_int32, ctypes.c_int32, V, V]
+    assert lib.dtsdf_depth_error(a, b, 0, 48, b, None) == E_INVAL
+    lib.dtsdf_recycle.argtypes = [V, ctypes.c_float, V, V]
+    assert lib.dtsdf_recycle(None, 0.9, None, None) == E_INVAL
+    lib.dtsdf_integrate_normals.argtypes = [V] * 6 + [ctypes.c_float, V, V]
+    assert lib.dtsdf_integrate_normals(None, a, None, None, None, None, 1.0, None, None) == E_INVAL
+    lib.icp_step_lm.argtypes = [V] * 3 + [ctypes.c_int32] + [V] * 4
+    assert lib.icp_step_lm(None, None, None, 7, None, None, None, None) == E_INVAL
