@@ -281,27 +281,6 @@ def main():
     achieved = bytes_per_launch / mean_launch_s / 1e9
     traffic = read_traffic(os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip"))
 
-    # ---- the same 300 views, one per launch, with the tile dispatch order learnt from the
-    # previous view (dtsdf_render_scheduled: the costliest tiles of the last launch start
-    # first; outputs identical) -------------------------------------------------------------
-    sch = dtsdf.RenderSchedule(cam)
-    for T in poses[:30]:
-        gm.render_scheduled(cam, T, sch, out)
-    torch.cuda.synchronize()
-    sevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in poses]
-    ts0 = time.perf_counter()
-    for (a_, b_), T in zip(sevs, poses):
-        a_.record(stream)
-        gm.render_scheduled(cam, T, sch, out)
-        b_.record(stream)
-    torch.cuda.synchronize()
-    swall = time.perf_counter() - ts0
-    scheduled = dict(rays_per_s=n * H * W / swall, ms_per_view=1e3 * swall / n,
-                     mean_launch_ms=float(np.mean([a_.elapsed_time(b_) for a_, b_ in sevs])))
-    log(f"scheduled: {scheduled['rays_per_s'] / 1e6:.1f} M rays/s, "
-        f"{scheduled['mean_launch_ms']:.3f} ms per view (render + order)")
-
     # ---- the same 300 views rendered several per launch (dtsdf_render_batch, the serving
     # form's persistent launch): the tails of the views overlap.  Algorithmic bytes of a
     # launch count the union of the bricks and entries its views touch (traced, untimed) ----
@@ -639,7 +618,6 @@ def main():
         "icp_rgb_keyframe_device_loop_ms_per_frame": icp_rgb_dev_ms,
         "icp_rgb_keyframe_device_loop_same_pose": same_rgb,
         "icp_rgb_keyframe_translation_median_m": icp_rgb_err,
-        "scheduled": scheduled,
         "batched": batched,
         "multi_sensor": multi,
         "post_fusion_mae_m": float(np.mean(mae)),

@@ -182,19 +182,6 @@ typedef struct {
   dtsdf_render_out out;
 } dtsdf_render_req;
 
-/* dtsdf_render with a caller-owned tile schedule, for renders of consecutive poses (a
- * tracking loop).  cost: device uint32[tiles] receiving each 8x8 tile's wave duration;
- * order: device int32[tiles], read as the dispatch order when use_order != 0 (it must then
- * hold what the previous scheduled call of the same image size wrote) and rewritten for the
- * next call: tiles at least a quarter as costly as the costliest first, then the others.
- * tiles = ceil(W / 8) * ceil(H / 8).  The outputs equal dtsdf_render's bitwise; only the order
- * in which the hardware starts the tiles changes, so that the long tiles do not start last.
- * Calls sharing cost / order must be ordered on one stream.  No trace outputs. */
-dtsdf_status dtsdf_render_scheduled(const dtsdf_map* map, const dtsdf_intrinsics* intr,
-                                    const double T_world_cam[16], float z_near, float z_far,
-                                    const dtsdf_render_out* out, uint32_t* cost, int32_t* order,
-                                    int32_t use_order, void* stream);
-
 /* Render n views (any sizes, any poses) of one map in a single persistent launch that hands
  * (view, 8x8 tile) work items to waves as they free up.  Every pixel is computed exactly as
  * by dtsdf_render, so each view is bitwise identical to rendering it alone.  Serves many

@@ -49,8 +49,6 @@ struct RenderArgs {
   uint8_t* trace_color;
   uint8_t* trace_slots;
   int32_t* trace_counts;
-  const int32_t* order;     // dispatch order of the tiles (scheduled renders), else null
-  uint32_t* cost;           // per-tile wave durations written back (scheduled renders)
 };
 
 struct Trace {
@@ -789,26 +787,13 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
 template <int F, bool TRACE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_k(
     MapView m, RenderArgs a) {
-  // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band.
-  // A scheduled render takes the order it is given (the costliest tiles of the previous
-  // launch first) and records each tile's duration.
-  int tile;
-  if (a.order) {
-    if ((int)blockIdx.x >= a.tiles) return;
-    tile = a.order[blockIdx.x];
-  } else {
-    const int per = (a.tiles + 7) >> 3;
-    tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  }
-  if (tile < 0 || tile >= a.tiles) return;
-  const uint64_t c0 = a.cost ? wall_clock64() : 0;
+  // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
+  const int per = (a.tiles + 7) >> 3;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= a.tiles) return;
   const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
   const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
   render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
-  if (a.cost && threadIdx.x == 0) {
-    const uint64_t d = wall_clock64() - c0;
-    a.cost[tile] = d > 0xffffffffull ? 0xffffffffu : (uint32_t)d;
-  }
 }
 
 // Views of different sizes in one persistent launch: every wave takes the next (view, tile)
@@ -834,50 +819,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
     const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
     render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
-  }
-}
-
-// The next dispatch order of a scheduled render: tiles whose measured duration is at least a
-// quarter of the longest go first, then the others, each group in the plain band order (a
-// permutation of the tiles).  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void order_k(const uint32_t* __restrict__ cost, int tiles,
-                                                int32_t* __restrict__ order) {
-  __shared__ uint32_t red[1024];
-  __shared__ int scan[1024];
-  __shared__ int base;
-  const int tid = threadIdx.x;
-  const int per = (tiles + 7) >> 3;
-  const int n = per * 8;                        // band positions (some beyond the tiles)
-  uint32_t mx = 0;
-  for (int t = tid; t < tiles; t += 1024) mx = max(mx, cost[t]);
-  red[tid] = mx;
-  __syncthreads();
-  for (int h = 512; h > 0; h >>= 1) {
-    if (tid < h) red[tid] = max(red[tid], red[tid + h]);
-    __syncthreads();
-  }
-  const uint32_t thr = red[0] / 4u;
-  if (tid == 0) base = 0;
-  __syncthreads();
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j0 = 0; j0 < n; j0 += 1024) {
-      const int j = j0 + tid;
-      const int t = j < n ? (j & 7) * per + (j >> 3) : tiles;
-      const bool heavy = t < tiles && cost[t] >= thr && thr > 0u;
-      const int take = t < tiles && (pass == 0 ? heavy : !heavy) ? 1 : 0;
-      scan[tid] = take;
-      __syncthreads();
-      for (int off = 1; off < 1024; off <<= 1) {   // inclusive prefix sum
-        const int add = tid >= off ? scan[tid - off] : 0;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
-      }
-      if (take) order[base + scan[tid] - 1] = t;
-      __syncthreads();
-      if (tid == 0) base += scan[1023];
-      __syncthreads();
-    }
   }
 }
 
@@ -911,8 +852,6 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
   a.trace_color = out->trace_color;
   a.trace_slots = out->trace_slots;
   a.trace_counts = out->trace_counts;
-  a.order = nullptr;
-  a.cost = nullptr;
   return true;
 }
 
@@ -940,30 +879,6 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
     else if (m->fmt == 1) hipLaunchKernelGGL((render_k<1, false>), grd, dim3(64), 0, st, v, a);
     else hipLaunchKernelGGL((render_k<2, false>), grd, dim3(64), 0, st, v, a);
   }
-  DTSDF_HIP(hipGetLastError());
-  return DTSDF_OK;
-}
-
-extern "C" dtsdf_status dtsdf_render_scheduled(const dtsdf_map* m,
-                                               const dtsdf_intrinsics* intr, const double T[16],
-                                               float z_near, float z_far,
-                                               const dtsdf_render_out* out, uint32_t* cost,
-                                               int32_t* order, int32_t use_order,
-                                               void* stream) {
-  RenderArgs a;
-  if (!m || !cost || !order || !fill_args(intr, T, z_near, z_far, out, a)) return DTSDF_E_INVAL;
-  if (a.trace_bricks || a.trace_color || a.trace_slots || a.trace_counts) return DTSDF_E_INVAL;
-  a.cost = cost;
-  a.order = use_order ? order : nullptr;
-  const int per = (a.tiles + 7) / 8;
-  const dim3 grd(use_order ? a.tiles : per * 8);
-  const MapView v = make_view(m);
-  hipStream_t st = (hipStream_t)stream;
-  if (m->regular) hipLaunchKernelGGL((render_k<kRegularVolume, false>), grd, dim3(64), 0, st, v, a);
-  else if (m->fmt == 0) hipLaunchKernelGGL((render_k<0, false>), grd, dim3(64), 0, st, v, a);
-  else if (m->fmt == 1) hipLaunchKernelGGL((render_k<1, false>), grd, dim3(64), 0, st, v, a);
-  else hipLaunchKernelGGL((render_k<2, false>), grd, dim3(64), 0, st, v, a);
-  hipLaunchKernelGGL(order_k, dim3(1), dim3(1024), 0, st, cost, a.tiles, order);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }

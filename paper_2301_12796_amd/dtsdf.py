@@ -146,7 +146,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "dtsdf_volume_create", "dtsdf_combine", "dtsdf_recombine_decide",
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
-            "dtsdf_integrate_normals", "icp_step_batch_iters", "dtsdf_render_scheduled",
+            "dtsdf_integrate_normals", "icp_step_batch_iters",
             "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
@@ -164,9 +164,6 @@ _lib.dtsdf_vertex_normal.argtypes = [_V, ctypes.POINTER(_Intr), ctypes.c_float, 
 _lib.dtsdf_depth_downsample.argtypes = [_V, ctypes.c_int32, ctypes.c_int32, _V, _V]
 _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes.c_int32,
                           ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
-_lib.dtsdf_render_scheduled.argtypes = [_V, ctypes.POINTER(_Intr), _D16, ctypes.c_float,
-                                        ctypes.c_float, ctypes.POINTER(_RenderOut), _V, _V,
-                                        ctypes.c_int32, _V]
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 _lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), ctypes.c_int32, _V]
@@ -362,19 +359,6 @@ class Map:
         ro = self._render_out(cam, out)
         _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
                                  ctypes.byref(ro), _stream(stream)), "dtsdf_render")
-        return out
-
-    def render_scheduled(self, cam, T_wc, schedule: "RenderSchedule", out: dict,
-                         z_near: float = 0.2, z_far: float = 10.0, stream=None) -> dict:
-        """render() with the tile dispatch order learnt from the previous call (see
-        dtsdf_render_scheduled); same outputs bitwise."""
-        ro = self._render_out(cam, out)
-        use = 1 if schedule.ready else 0
-        _check(_lib.dtsdf_render_scheduled(
-            self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far, ctypes.byref(ro),
-            _dev_ptr(schedule.cost, torch.int32), _dev_ptr(schedule.order, torch.int32), use,
-            _stream(stream)), "dtsdf_render_scheduled")
-        schedule.ready = True
         return out
 
     def recycle(self, t_free: float = 0.9, stream=None) -> int:
@@ -721,18 +705,6 @@ def icp_lm(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 7,
                 break
         T = st.T_acc
     return T, log
-
-
-class RenderSchedule:
-    """Caller-owned tile schedule of render_scheduled for one image size: per-tile costs and
-    the dispatch order (int32 device tensors); the first call renders in the plain order."""
-
-    def __init__(self, cam, device=None):
-        dev = device or torch.device("cuda", torch.cuda.current_device())
-        tiles = ((int(cam.width) + 7) // 8) * ((int(cam.height) + 7) // 8)
-        self.cost = torch.zeros(tiles, dtype=torch.int32, device=dev)
-        self.order = torch.zeros(tiles, dtype=torch.int32, device=dev)
-        self.ready = False
 
 
 @dataclasses.dataclass

@@ -255,18 +255,3 @@ def test_render_levels_equal_single_renders(dtsdf, tiny_map):
         assert torch.equal(v, ref["vertex"]) and torch.equal(n, ref["normal"])
         assert torch.equal(m, ref["mask"])
     assert int(lv[0][2].sum()) > 1000
-
-
-def test_scheduled_render_equals_plain_render(dtsdf, tiny_map):
-    """dtsdf_render_scheduled over consecutive poses (dispatch order learnt from the previous
-    call) gives the outputs of dtsdf_render bitwise, and its order is a permutation."""
-    cam = P.TINY_CAM
-    sch = dtsdf.RenderSchedule(cam)
-    for phi in np.linspace(0.2, 0.9, 6):
-        T = synth.tiny_render_pose(float(phi))
-        ref = P.to_numpy_out(tiny_map.render(cam, T))
-        got = P.to_numpy_out(tiny_map.render_scheduled(cam, T, sch, _alloc(cam)))
-        for k in ("depth", "vertex", "normal", "rgba", "mask"):
-            assert np.array_equal(got[k], ref[k]), k
-    o = sch.order.cpu().numpy()
-    assert np.array_equal(np.sort(o), np.arange(o.size))
