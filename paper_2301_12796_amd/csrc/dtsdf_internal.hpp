@@ -30,28 +30,34 @@
 //   brick_neg u64[capacity*16]      per brick, word z, bit x + 8 y: the voxel has w > 0 and
 //                                   sdf <= kSkipMin; words 8 + z: the voxel has w > 0
 //   block_neg u64[buckets*8]        per hash entry: OR of brick_neg over the block's bricks
-//   cell_mask u64[buckets*8]        per hash entry, word z, bit x + 8 y: no corner of the cell
-//                                   based at voxel (x, y, z) (corners in the +x/+y/+z
-//                                   neighbours included) is set in block_neg, so every
-//                                   direction defined there interpolates positive values
-//                                   and the combined SDF is positive wherever defined
-//   dir_groups u8[buckets*64]       per hash entry and 2x2x2 group of cells (byte
-//                                   gx + 4 gy + 16 gz): bit D set if direction D has all 8
-//                                   corners observed (w > 0) at some cell of the group; a
-//                                   direction whose bit is clear is undefined at every cell
-//                                   of the group and contributes nothing there
+//                                   (input of the positive-cell words below)
 //
 // Render index (updated after every integrate / import): a dense grid over the bounding box
-// of the occupied blocks.  288 GB of HBM make a dense block grid affordable for room- and
-// building-scale maps (~6 bytes per 4 cm block), and it replaces hash probing in the ray
-// march by direct loads:
-//   grid_slot int32[gx*gy*gz]       hash slot of the block, -1 if absent
-//   grid_mask uint8[gx*gy*gz]       bit s set: every cell based in sub-block s has all corner
-//                                   values > kSkipMin in every direction, so the combined SDF
-//                                   is positive wherever defined there and no crossing can end
-//                                   in that sub-block
-//   macro1   uint8[ceil(g/4)^3]     1 if any block of the 4^3-block cell is present
-//   macro2   uint8[ceil(g/16)^3]    1 if any block of the 16^3-block cell is present
+// of the occupied blocks.  288 GB of HBM make a dense block grid affordable for room-scale
+// maps (160 bytes per 4 cm block at 5 mm voxels), and it turns every block the ray march
+// enters into one round of independent loads (record, cell words and group bytes), with no
+// hash probing and no chain of dependent lookups:
+//   grid_rec  GridRec[gx*gy*gz]     per block: the six brick indices (-1: not allocated), its
+//                                   hash slot (-1: absent block) and the info word: bits 0-7
+//                                   sub-block skip bits (bit s set: every cell based in
+//                                   sub-block s has all corner values > kSkipMin in every
+//                                   direction, so the combined SDF is positive wherever
+//                                   defined there and no crossing can end in that
+//                                   sub-block), bits 8-10 empty level e of an absent block
+//                                   (the aligned cell of 2^e blocks per edge containing it
+//                                   holds no present block), bit 15 present
+//   grid_cell u64[gx*gy*gz*8]       per block, word z, bit x + 8 y: no corner of the cell
+//                                   based at voxel (x, y, z) (corners in the +x/+y/+z
+//                                   neighbours included) is non-positive in any direction,
+//                                   so every direction defined there interpolates positive
+//                                   values and the combined SDF is positive wherever defined
+//   grid_group u8[gx*gy*gz*64]      per block and 2x2x2 group of cells (byte gx + 4 gy +
+//                                   16 gz): bit D set if direction D has all 8 corners
+//                                   observed (w > 0) at some cell of the group; a direction
+//                                   whose bit is clear is undefined at every cell of the
+//                                   group and contributes nothing there
+//   mip      uint8[levels 1..6]     occupancy of the aligned cells of 2^l blocks per edge
+//                                   (input of the empty levels)
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -74,6 +80,16 @@ struct alignas(32) HashEntry {
   int32_t brick[6];
 };
 static_assert(sizeof(HashEntry) == 32, "hash entries are 32 bytes");
+
+// Render-index record of one grid block (see the layout notes above).
+struct alignas(32) GridRec {
+  int32_t brick[6];
+  uint32_t info;
+  int32_t slot;
+};
+static_assert(sizeof(GridRec) == 32, "grid records are 32 bytes");
+constexpr uint32_t kRecPresent = 1u << 15;
+constexpr int kMipLevels = 6;   // aligned empty cells up to 64 blocks per edge
 
 __host__ __device__ inline bool key_in_range(int bx, int by, int bz) {
   return bx >= -kKeyBias && bx < kKeyBias && by >= -kKeyBias && by < kKeyBias &&
@@ -200,12 +216,9 @@ struct MapView {
   float* wc;
   const int4* bkey;
   uint32_t capacity;
-  const int32_t* grid_slot;
-  const uint8_t* grid_mask;
-  const uint8_t* macro1;
-  const uint8_t* macro2;
-  const uint64_t* cell_mask;
-  const uint8_t* dir_groups;
+  const GridRec* grid_rec;
+  const uint64_t* grid_cell;
+  const uint8_t* grid_group;
   int gx0, gy0, gz0;        // grid origin (block coordinates)
   int gx, gy, gz;           // grid dimensions (blocks)
   double voxel, inv_voxel;
@@ -303,15 +316,14 @@ struct dtsdf_map {
   float* slot_min;
   uint64_t* brick_neg;
   uint64_t* block_neg;
-  uint64_t* cell_mask;
-  uint8_t* dir_groups;
-  int32_t* grid_slot;
-  uint8_t* grid_mask;
-  uint8_t* macro1;
-  uint8_t* macro2;
+  dtsdf::GridRec* grid_rec;
+  uint64_t* grid_cell;
+  uint8_t* grid_group;
+  uint8_t* mip;         // occupancy levels 1..kMipLevels, level l at mip_off[l]
+  int64_t mip_off[dtsdf::kMipLevels + 2];
   int32_t grid_lo[3], grid_dim[3];
   int64_t grid_cap;     // allocated grid cells
-  int64_t macro_cap;    // allocated bytes of each macro grid
+  int64_t mip_cap;      // allocated mip bytes
   // 1: a regular (single-volume) TSDF written by dtsdf_combine: direction slot 0 holds the
   // combined value with weight 1 (0: no value), rendered without direction weighting
   int regular;

@@ -63,11 +63,14 @@ __global__ __launch_bounds__(256) void bbox_k(const HashEntry* __restrict__ e, u
   }
 }
 
-__global__ __launch_bounds__(256) void grid_clear_k(int32_t* slot, uint8_t* mask, int64_t n) {
+__global__ __launch_bounds__(256) void grid_clear_k(GridRec* rec, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  slot[i] = -1;
-  mask[i] = 0;
+  GridRec r;
+  for (int d = 0; d < 6; ++d) r.brick[d] = -1;
+  r.info = 0;
+  r.slot = -1;
+  rec[i] = r;
 }
 
 __global__ __launch_bounds__(256) void bytes_clear_k(uint8_t* p, int64_t n) {
@@ -77,17 +80,23 @@ __global__ __launch_bounds__(256) void bytes_clear_k(uint8_t* p, int64_t n) {
 
 struct Grid {
   int x0, y0, z0, nx, ny, nz;
-  int m1x, m1y, m2x, m2y;   // macro grid dimensions (x, y)
+  int64_t mip_off[kMipLevels + 2];   // byte offset of occupancy level l (1 .. kMipLevels)
   __device__ int64_t index(int bx, int by, int bz) const {
     int ix = bx - x0, iy = by - y0, iz = bz - z0;
     if (ix < 0 || iy < 0 || iz < 0 || ix >= nx || iy >= ny || iz >= nz) return -1;
     return ((int64_t)iz * ny + iy) * nx + ix;
   }
+  // cell of occupancy level l holding grid block (ix, iy, iz)
+  __device__ int64_t mip_index(int l, int ix, int iy, int iz) const {
+    const int mx = (nx + (1 << l) - 1) >> l, my = (ny + (1 << l) - 1) >> l;
+    return mip_off[l] + ((int64_t)(iz >> l) * my + (iy >> l)) * mx + (ix >> l);
+  }
 };
 
+// Records of the present blocks (bricks and hash slot) and their occupancy at every level.
 __global__ __launch_bounds__(256) void grid_scatter_k(const HashEntry* __restrict__ e,
-                                                      uint32_t buckets, Grid g, int32_t* slot,
-                                                      uint8_t* macro1, uint8_t* macro2) {
+                                                      uint32_t buckets, Grid g, GridRec* rec,
+                                                      uint8_t* mip) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= buckets) return;
   const HashEntry ent = e[s];
@@ -96,10 +105,26 @@ __global__ __launch_bounds__(256) void grid_scatter_k(const HashEntry* __restric
   unpack_key(ent.key, b[0], b[1], b[2]);
   int64_t i = g.index(b[0], b[1], b[2]);
   if (i < 0) return;
-  slot[i] = (int32_t)s;
+  for (int d = 0; d < 6; ++d) rec[i].brick[d] = ent.brick[d];
+  rec[i].slot = (int32_t)s;
   const int ix = b[0] - g.x0, iy = b[1] - g.y0, iz = b[2] - g.z0;
-  macro1[((int64_t)(iz >> 2) * g.m1y + (iy >> 2)) * g.m1x + (ix >> 2)] = 1;
-  macro2[((int64_t)(iz >> 4) * g.m2y + (iy >> 4)) * g.m2x + (ix >> 4)] = 1;
+  for (int l = 1; l <= kMipLevels; ++l) mip[g.mip_index(l, ix, iy, iz)] = 1;
+}
+
+// Empty level of every absent block: the largest l <= kMipLevels whose aligned cell of 2^l
+// blocks per edge holds no present block (0: only the block itself is known empty).
+__global__ __launch_bounds__(256) void empty_level_k(Grid g, GridRec* rec,
+                                                     const uint8_t* __restrict__ mip) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)g.nx * g.ny * g.nz) return;
+  if (rec[i].slot >= 0) return;
+  const int ix = (int)(i % g.nx), iy = (int)((i / g.nx) % g.ny), iz = (int)(i / ((int64_t)g.nx * g.ny));
+  uint32_t e = 0;
+  for (int l = 1; l <= kMipLevels; ++l) {
+    if (mip[g.mip_index(l, ix, iy, iz)]) break;
+    e = (uint32_t)l;
+  }
+  rec[i].info = e << 8;
 }
 
 // Per entry and sub-block: min over the block's directions of the sub-block minima.
@@ -126,10 +151,8 @@ __global__ __launch_bounds__(256) void slot_min_k(const HashEntry* __restrict__ 
 // those sub-blocks hold every corner a cell based in sub-block q can reach.  Absent
 // neighbours make the cells that need them undefined and do not constrain the mask.
 __global__ __launch_bounds__(256) void grid_mask_k(const HashEntry* __restrict__ e,
-                                                   uint32_t buckets, Grid g,
-                                                   const int32_t* __restrict__ slot,
-                                                   const float* __restrict__ slot_min,
-                                                   uint8_t* mask) {
+                                                   uint32_t buckets, Grid g, GridRec* rec,
+                                                   const float* __restrict__ slot_min) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= buckets) return;
   const HashEntry ent = e[s];
@@ -141,9 +164,9 @@ __global__ __launch_bounds__(256) void grid_mask_k(const HashEntry* __restrict__
   int nslot[8];
   for (int o = 0; o < 8; ++o) {
     int64_t j = o == 0 ? i : g.index(b[0] + (o & 1), b[1] + ((o >> 1) & 1), b[2] + ((o >> 2) & 1));
-    nslot[o] = j < 0 ? -1 : slot[j];
+    nslot[o] = o == 0 ? (int)s : (j < 0 ? -1 : rec[j].slot);
   }
-  uint8_t bits = 0;
+  uint32_t bits = 0;
   for (int q = 0; q < 8; ++q) {
     const int qs[3] = {q & 1, (q >> 1) & 1, q >> 2};
     float mn = INFINITY;
@@ -154,9 +177,9 @@ __global__ __launch_bounds__(256) void grid_mask_k(const HashEntry* __restrict__
       const int sl = nslot[o];
       if (sl >= 0) mn = fminf(mn, slot_min[(size_t)sl * 8 + sub]);
     }
-    if (mn > kSkipMin) bits |= (uint8_t)(1u << q);
+    if (mn > kSkipMin) bits |= 1u << q;
   }
-  mask[i] = bits;
+  rec[i].info = bits | kRecPresent;
 }
 
 // Per entry and slice z: OR of the non-positive voxel masks of the block's bricks.
@@ -195,9 +218,9 @@ __device__ inline uint64_t or_xy(uint64_t w, uint64_t nx, uint64_t ny, uint64_t 
 // direction that lacks a corner, so they do not constrain the mask.
 __global__ __launch_bounds__(256) void cell_mask_k(const HashEntry* __restrict__ e,
                                                    uint32_t buckets, Grid g,
-                                                   const int32_t* __restrict__ slot,
+                                                   const GridRec* __restrict__ rec,
                                                    const uint64_t* __restrict__ block_neg,
-                                                   uint64_t* cell_mask) {
+                                                   uint64_t* grid_cell) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t s = (uint32_t)(t >> 3);
   const int z = (int)(t & 7);
@@ -206,6 +229,8 @@ __global__ __launch_bounds__(256) void cell_mask_k(const HashEntry* __restrict__
   if (!slot_present(ent)) return;
   int b[3];
   unpack_key(ent.key, b[0], b[1], b[2]);
+  const int64_t i = g.index(b[0], b[1], b[2]);
+  if (i < 0) return;
   // slices z and z + 1 of the blocks at offsets 0, +x, +y, +xy (z + 1 = 8: slice 0 of the
   // blocks one further in z)
   uint64_t w[2][4];
@@ -219,14 +244,14 @@ __global__ __launch_bounds__(256) void cell_mask_k(const HashEntry* __restrict__
         sl = (int)s;
       } else {
         const int64_t j = g.index(b[0] + ox, b[1] + oy, b[2] + oz);
-        sl = j < 0 ? -1 : slot[j];
+        sl = j < 0 ? -1 : rec[j].slot;
       }
       w[h][q] = sl < 0 ? 0ull : block_neg[(size_t)sl * 8 + (zz & 7)];
     }
   }
   const uint64_t neg = or_xy(w[0][0], w[0][1], w[0][2], w[0][3]) |
                        or_xy(w[1][0], w[1][1], w[1][2], w[1][3]);
-  cell_mask[(size_t)s * 8 + z] = ~neg;
+  grid_cell[(size_t)i * 8 + z] = ~neg;
 }
 
 // AND of a voxel slice over x and x + 1, and over (x, x + 1) x (y, y + 1) (see or_x).
@@ -246,9 +271,9 @@ __device__ inline uint64_t and_xy(uint64_t w, uint64_t nx, uint64_t ny, uint64_t
 // leaves the block) are observed in D.
 __global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict__ e,
                                                     uint32_t buckets, Grid g,
-                                                    const int32_t* __restrict__ slot,
+                                                    const GridRec* __restrict__ rec,
                                                     const uint64_t* __restrict__ brick_bits,
-                                                    uint8_t* dir_groups) {
+                                                    uint8_t* grid_group) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t s = (uint32_t)(t >> 2);
   const int gz = (int)(t & 3);
@@ -257,18 +282,19 @@ __global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict_
   if (!slot_present(ent)) return;
   int b[3];
   unpack_key(ent.key, b[0], b[1], b[2]);
-  // slots of the blocks at offsets (ox, oy, oz), index ox + 2 oy + 4 oz
-  int nb[8];
-  nb[0] = (int)s;
-  for (int o = 1; o < 8; ++o) {
-    const int64_t j = g.index(b[0] + (o & 1), b[1] + ((o >> 1) & 1), b[2] + ((o >> 2) & 1));
-    nb[o] = j < 0 ? -1 : slot[j];
-  }
+  const int64_t i = g.index(b[0], b[1], b[2]);
+  if (i < 0) return;
+  // grid records of the blocks at offsets (ox, oy, oz), index ox + 2 oy + 4 oz (-1: outside)
+  int64_t nb[8];
+  nb[0] = i;
+  for (int o = 1; o < 8; ++o)
+    nb[o] = g.index(b[0] + (o & 1), b[1] + ((o >> 1) & 1), b[2] + ((o >> 2) & 1));
   uint32_t bytes[4] = {0u, 0u, 0u, 0u};   // 16 group bytes of the slab
   for (int d = 0; d < 6; ++d) {
     if (ent.brick[d] < 0) continue;
     int br[8];
-    for (int o = 0; o < 8; ++o) br[o] = nb[o] < 0 ? -1 : e[nb[o]].brick[d];
+    br[0] = ent.brick[d];
+    for (int o = 1; o < 8; ++o) br[o] = nb[o] < 0 ? -1 : rec[nb[o]].brick[d];
     // observed words of slices 2 gz .. 2 gz + 2 for the blocks at (0,0), (+x), (+y), (+xy)
     uint64_t w[3][4];
     for (int h = 0; h < 3; ++h) {
@@ -289,7 +315,7 @@ __global__ __launch_bounds__(256) void dir_groups_k(const HashEntry* __restrict_
         if ((u >> (2 * gx + 16 * gy)) & 0x0303ull)
           bytes[gy] |= (1u << d) << (8 * gx);
   }
-  uint32_t* out = reinterpret_cast<uint32_t*>(dir_groups + (size_t)s * 64 + 16 * gz);
+  uint32_t* out = reinterpret_cast<uint32_t*>(grid_group + (size_t)i * 64 + 16 * gz);
   for (int gy = 0; gy < 4; ++gy) out[gy] = bytes[gy];
 }
 
@@ -327,6 +353,42 @@ void launch_bbox(dtsdf_map* m, hipStream_t st) {
   hipLaunchKernelGGL(bbox_k, dim3(blocks), dim3(256), 0, st, m->entries, m->buckets, bbox);
 }
 
+namespace {
+
+Grid grid_of(const dtsdf_map* m) {
+  Grid g{m->grid_lo[0], m->grid_lo[1], m->grid_lo[2], m->grid_dim[0], m->grid_dim[1],
+         m->grid_dim[2], {}};
+  for (int l = 0; l < kMipLevels + 2; ++l) g.mip_off[l] = m->mip_off[l];
+  return g;
+}
+
+// Byte offsets of the occupancy levels 1 .. kMipLevels for a grid of `dim` blocks; returns
+// the total size.
+int64_t mip_layout(const int dim[3], int64_t off[kMipLevels + 2]) {
+  int64_t total = 0;
+  off[0] = 0;
+  for (int l = 1; l <= kMipLevels; ++l) {
+    off[l] = total;
+    total += (int64_t)ceil_div(dim[0], 1 << l) * ceil_div(dim[1], 1 << l) * ceil_div(dim[2], 1 << l);
+  }
+  off[kMipLevels + 1] = total;
+  return total;
+}
+
+// Clears every record and the occupancy levels of the current grid.
+dtsdf_status clear_grid(dtsdf_map* m, hipStream_t st) {
+  const int64_t cells = (int64_t)m->grid_dim[0] * m->grid_dim[1] * m->grid_dim[2];
+  const int64_t mb = m->mip_off[kMipLevels + 1];
+  hipLaunchKernelGGL(grid_clear_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st,
+                     m->grid_rec, cells);
+  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((mb + 255) / 256)), dim3(256), 0, st,
+                     m->mip, mb);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+}  // namespace
+
 dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st) {
   const bool empty = hb[0] > hb[3];
   if (empty) {
@@ -347,60 +409,60 @@ dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st) {
     cells *= dim[k];
   }
   if (cells > kMaxGridBlocks) return DTSDF_E_CAPACITY;
-  const int64_t c1 = (int64_t)ceil_div(dim[0], 4) * ceil_div(dim[1], 4) * ceil_div(dim[2], 4);
-  const int64_t c2 = (int64_t)ceil_div(dim[0], 16) * ceil_div(dim[1], 16) * ceil_div(dim[2], 16);
-  if (cells > m->grid_cap || c1 > m->macro_cap) {
+  int64_t off[kMipLevels + 2];
+  const int64_t mb = mip_layout(dim, off);
+  if (cells > m->grid_cap || mb > m->mip_cap) {
     DTSDF_HIP(hipStreamSynchronize(st));
-    (void)hipFree(m->grid_slot);
-    (void)hipFree(m->grid_mask);
-    (void)hipFree(m->macro1);
-    (void)hipFree(m->macro2);
-    m->grid_slot = nullptr;
-    m->grid_mask = m->macro1 = m->macro2 = nullptr;
+    (void)hipFree(m->grid_rec);
+    (void)hipFree(m->grid_cell);
+    (void)hipFree(m->grid_group);
+    (void)hipFree(m->mip);
+    m->grid_rec = nullptr;
+    m->grid_cell = nullptr;
+    m->grid_group = nullptr;
+    m->mip = nullptr;
     m->grid_cap = 0;
-    m->macro_cap = 0;
+    m->mip_cap = 0;
     for (int k = 0; k < 3; ++k) m->grid_dim[k] = 0;
     const int64_t want = cells + cells / 4;
-    const int64_t want1 = c1 + c1 / 4;   // c2 <= c1
-    if (hipMalloc(&m->grid_slot, sizeof(int32_t) * want) != hipSuccess ||
-        hipMalloc(&m->grid_mask, want) != hipSuccess ||
-        hipMalloc(&m->macro1, want1) != hipSuccess || hipMalloc(&m->macro2, want1) != hipSuccess)
+    const int64_t wantm = mb + mb / 4 + 64;
+    if (hipMalloc(&m->grid_rec, sizeof(GridRec) * want) != hipSuccess ||
+        hipMalloc(&m->grid_cell, sizeof(uint64_t) * 8 * want) != hipSuccess ||
+        hipMalloc(&m->grid_group, (size_t)64 * want) != hipSuccess ||
+        hipMalloc(&m->mip, wantm) != hipSuccess)
       return DTSDF_E_NOMEM;
     m->grid_cap = want;
-    m->macro_cap = want1;
+    m->mip_cap = wantm;
   }
   for (int k = 0; k < 3; ++k) {
     m->grid_lo[k] = lo[k];
     m->grid_dim[k] = dim[k];
   }
-  hipLaunchKernelGGL(grid_clear_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st,
-                     m->grid_slot, m->grid_mask, cells);
-  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c1 + 255) / 256)), dim3(256), 0, st, m->macro1, c1);
-  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c2 + 255) / 256)), dim3(256), 0, st, m->macro2, c2);
-  DTSDF_HIP(hipGetLastError());
-  return DTSDF_OK;
+  for (int l = 0; l < kMipLevels + 2; ++l) m->mip_off[l] = off[l];
+  return clear_grid(m, st);
 }
 
 dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st) {
   if (m->grid_dim[0] == 0) return DTSDF_OK;
-  Grid g{m->grid_lo[0], m->grid_lo[1], m->grid_lo[2], m->grid_dim[0], m->grid_dim[1], m->grid_dim[2],
-         ceil_div(m->grid_dim[0], 4), ceil_div(m->grid_dim[1], 4),
-         ceil_div(m->grid_dim[0], 16), ceil_div(m->grid_dim[1], 16)};
+  const Grid g = grid_of(m);
+  const int64_t cells = (int64_t)m->grid_dim[0] * m->grid_dim[1] * m->grid_dim[2];
   const dim3 grd((m->buckets + 255) / 256);
   hipLaunchKernelGGL(grid_scatter_k, grd, dim3(256), 0, st, m->entries, m->buckets, g,
-                     m->grid_slot, m->macro1, m->macro2);
+                     m->grid_rec, m->mip);
+  hipLaunchKernelGGL(empty_level_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st, g,
+                     m->grid_rec, m->mip);
   hipLaunchKernelGGL(slot_min_k, grd, dim3(256), 0, st, m->entries, m->buckets, m->sub_min,
                      m->slot_min);
   hipLaunchKernelGGL(grid_mask_k, grd, dim3(256), 0, st, m->entries, m->buckets, g,
-                     m->grid_slot, m->slot_min, m->grid_mask);
+                     m->grid_rec, m->slot_min);
   const dim3 grd8((uint32_t)(((uint64_t)m->buckets * 8 + 255) / 256));
   hipLaunchKernelGGL(block_neg_k, grd8, dim3(256), 0, st, m->entries, m->buckets, m->brick_neg,
                      m->block_neg);
   hipLaunchKernelGGL(cell_mask_k, grd8, dim3(256), 0, st, m->entries, m->buckets, g,
-                     m->grid_slot, m->block_neg, m->cell_mask);
+                     m->grid_rec, m->block_neg, m->grid_cell);
   const dim3 grd4((uint32_t)(((uint64_t)m->buckets * 4 + 255) / 256));
   hipLaunchKernelGGL(dir_groups_k, grd4, dim3(256), 0, st, m->entries, m->buckets, g,
-                     m->grid_slot, m->brick_neg, m->dir_groups);
+                     m->grid_rec, m->brick_neg, m->grid_group);
   DTSDF_HIP(hipGetLastError());
   return DTSDF_OK;
 }
@@ -423,18 +485,8 @@ dtsdf_status rebuild_index_cleared(dtsdf_map* m, hipStream_t st) {
   dtsdf_status s = ensure_grid(m, hb, st);
   if (s != DTSDF_OK) return s;
   if (m->grid_dim[0] == 0) return DTSDF_OK;
-  const int64_t cells = (int64_t)m->grid_dim[0] * m->grid_dim[1] * m->grid_dim[2];
-  const int64_t c1 = (int64_t)ceil_div(m->grid_dim[0], 4) * ceil_div(m->grid_dim[1], 4) *
-                     ceil_div(m->grid_dim[2], 4);
-  const int64_t c2 = (int64_t)ceil_div(m->grid_dim[0], 16) * ceil_div(m->grid_dim[1], 16) *
-                     ceil_div(m->grid_dim[2], 16);
-  hipLaunchKernelGGL(grid_clear_k, dim3((uint32_t)((cells + 255) / 256)), dim3(256), 0, st,
-                     m->grid_slot, m->grid_mask, cells);
-  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c1 + 255) / 256)), dim3(256), 0, st,
-                     m->macro1, c1);
-  hipLaunchKernelGGL(bytes_clear_k, dim3((uint32_t)((c2 + 255) / 256)), dim3(256), 0, st,
-                     m->macro2, c2);
-  DTSDF_HIP(hipGetLastError());
+  s = clear_grid(m, st);
+  if (s != DTSDF_OK) return s;
   return launch_index_update(m, st);
 }
 

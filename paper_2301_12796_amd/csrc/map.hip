@@ -21,12 +21,9 @@ MapView make_view(const dtsdf_map* m) {
   v.wc = m->wc;
   v.bkey = m->bkey;
   v.capacity = m->p.brick_capacity;
-  v.grid_slot = m->grid_slot;
-  v.grid_mask = m->grid_mask;
-  v.macro1 = m->macro1;
-  v.macro2 = m->macro2;
-  v.cell_mask = m->cell_mask;
-  v.dir_groups = m->dir_groups;
+  v.grid_rec = m->grid_rec;
+  v.grid_cell = m->grid_cell;
+  v.grid_group = m->grid_group;
   v.gx0 = m->grid_lo[0];
   v.gy0 = m->grid_lo[1];
   v.gz0 = m->grid_lo[2];
@@ -125,12 +122,10 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->slot_min);
   (void)hipFree(m->brick_neg);
   (void)hipFree(m->block_neg);
-  (void)hipFree(m->cell_mask);
-  (void)hipFree(m->dir_groups);
-  (void)hipFree(m->grid_slot);
-  (void)hipFree(m->grid_mask);
-  (void)hipFree(m->macro1);
-  (void)hipFree(m->macro2);
+  (void)hipFree(m->grid_rec);
+  (void)hipFree(m->grid_cell);
+  (void)hipFree(m->grid_group);
+  (void)hipFree(m->mip);
   delete m;
 }
 
@@ -216,9 +211,7 @@ dtsdf_status dtsdf_create(const dtsdf_params* p, dtsdf_map** out) {
             hipMalloc(&m->sub_min, sizeof(float) * 8 * p->brick_capacity) == hipSuccess &&
             hipMalloc(&m->slot_min, sizeof(float) * 8 * (size_t)m->buckets) == hipSuccess &&
             hipMalloc(&m->brick_neg, sizeof(uint64_t) * 16 * p->brick_capacity) == hipSuccess &&
-            hipMalloc(&m->block_neg, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess &&
-            hipMalloc(&m->cell_mask, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess &&
-            hipMalloc(&m->dir_groups, 64 * (size_t)m->buckets) == hipSuccess;
+            hipMalloc(&m->block_neg, sizeof(uint64_t) * 8 * (size_t)m->buckets) == hipSuccess;
   if (ok && p->with_color) {
     ok = hipMalloc(&m->rgb, sizeof(uint32_t) * nv) == hipSuccess;
     if (ok && m->fmt == 0) ok = hipMalloc(&m->wc, sizeof(float) * nv) == hipSuccess;
@@ -267,10 +260,11 @@ dtsdf_status dtsdf_get_info(const dtsdf_map* m, dtsdf_info* out) {
   out->device_bytes = (int64_t)(sizeof(HashEntry) * m->buckets + sizeof(uint32_t) * m->buckets +
                                 (sizeof(int4) + 8 * sizeof(float) + 16 * sizeof(uint64_t)) *
                                     m->p.brick_capacity +
-                                (8 * sizeof(float) + 16 * sizeof(uint64_t) + 64) * m->buckets +
+                                (8 * sizeof(float) + 8 * sizeof(uint64_t)) * m->buckets +
                                 geo_bytes(m->fmt) * nv +
                                 (m->p.with_color ? (sizeof(uint32_t) + (m->fmt == 0 ? sizeof(float) : 0)) * nv : 0) +
-                                (sizeof(int32_t) + 1) * m->grid_cap + 2 * m->macro_cap +
+                                (sizeof(GridRec) + 8 * sizeof(uint64_t) + 64) * m->grid_cap +
+                                m->mip_cap +
                                 (m->free_list ? sizeof(int32_t) * m->p.brick_capacity : 0) +
                                 sizeof(int32_t) * m->p.brick_capacity);
   return DTSDF_OK;

@@ -75,37 +75,49 @@ __device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
   return ((int64_t)iz * m.gy + iy) * m.gx + ix;
 }
 
-// Hash slot of a block via the render index, -1 if absent.
+// Enters grid block `gi` (-1: outside the grid): its record, positive-cell words and group
+// bytes are loaded in one round of independent loads (an absent block's words are read too
+// and ignored, so that no load waits for the record) and kept in the lane's LDS columns:
+// brick indices of direction d at row[d * 64], cell word z at cw[z * 64], group word w at
+// gw[w * 64].  Returns the record's info word (0 outside the grid) and the present-direction
+// mask in `pm`.  Bit kRecInGrid of the returned word marks a block inside the grid.
+constexpr uint32_t kRecInGrid = 1u << 16;
 template <bool TRACE>
-__device__ inline int block_slot(const MapView& m, int bx, int by, int bz, const Trace& tr) {
-  const int64_t i = grid_index(m, bx, by, bz);
-  const int s = i < 0 ? -1 : m.grid_slot[i];
-  if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
-  return s;
-}
-
-// The six brick indices of a block (-1: direction not allocated), from its hash entry, kept
-// in LDS at row[d * 64] (one column per lane, so that the per-lane direction index selects
-// a row without a dynamically indexed private array); returns the present-direction mask.
-__device__ inline uint32_t load_bricks(const MapView& m, int slot, int* row) {
-  int b[6] = {-1, -1, -1, -1, -1, -1};
-  if (slot >= 0) {
-    const int2 lo = *reinterpret_cast<const int2*>(&m.entries[slot].brick[0]);
-    const int4 hi = *reinterpret_cast<const int4*>(&m.entries[slot].brick[2]);
-    b[0] = lo.x;
-    b[1] = lo.y;
-    b[2] = hi.x;
-    b[3] = hi.y;
-    b[4] = hi.z;
-    b[5] = hi.w;
+__device__ inline uint32_t enter_block(const MapView& m, int64_t gi, int* row, uint64_t* cw,
+                                       uint64_t* gw, uint32_t& pm, const Trace& tr) {
+  pm = 0;
+  if (gi < 0) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) row[d * 64] = -1;
+    return 0;
   }
-  uint32_t pm = 0;
+  const uint4* rp = reinterpret_cast<const uint4*>(m.grid_rec + gi);
+  const uint4* cp = reinterpret_cast<const uint4*>(m.grid_cell + (size_t)gi * 8);
+  const uint4* gp = reinterpret_cast<const uint4*>(m.grid_group + (size_t)gi * 64);
+  const uint4 r0 = rp[0], r1 = rp[1];
+  uint4 q[4], qg[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    q[h] = cp[h];
+    qg[h] = gp[h];
+  }
+  const int b[6] = {(int)r0.x, (int)r0.y, (int)r0.z, (int)r0.w, (int)r1.x, (int)r1.y};
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     row[d * 64] = b[d];
     pm |= b[d] >= 0 ? 1u << d : 0u;
   }
-  return pm;
+  if (TRACE && tr.slots && (int)r1.w >= 0) tr.slots[(int)r1.w] = 1;
+  if (r1.z & kRecPresent) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      cw[(2 * h) * 64] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
+      cw[(2 * h + 1) * 64] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
+      gw[(2 * h) * 64] = (uint64_t)qg[h].x | ((uint64_t)qg[h].y << 32);
+      gw[(2 * h + 1) * 64] = (uint64_t)qg[h].z | ((uint64_t)qg[h].w << 32);
+    }
+  }
+  return r1.z | kRecInGrid;
 }
 
 struct CellPos {
@@ -155,12 +167,35 @@ struct Eval {
   bool color_ok;
 };
 
+// Raw voxel word of the (sdf, w) field as it sits in memory: float2 in the plain layout, one
+// 32-bit code word in the packed layouts (decoded only when used, so that a group of
+// directions keeps half the registers in flight).
+template <int F>
+struct GeoRaw {
+  using T = uint32_t;
+  __device__ static void decode(T v, float& s, float& w) { Vox<F>::decode(v, s, w); }
+};
+template <>
+struct GeoRaw<0> {
+  using T = float2;
+  __device__ static void decode(T v, float& s, float& w) {
+    s = v.x;
+    w = v.y;
+  }
+};
+template <>
+struct GeoRaw<kRegularVolume> : GeoRaw<0> {};
+
 // Combined SDF (and, FULL, normal and colour) in the cell `cp` whose base block has bricks
-// `bb`.  Directions are taken per lane in ascending order of D, so every lane pays only for
-// the directions allocated in its own block.
+// `brow` (grid records for the neighbour blocks at the cell's +x/+y/+z faces).  Directions are taken per lane in ascending order of D, so every lane pays only for
+// the directions allocated in its own block.  They are processed in groups of G: the
+// neighbour-brick lookups of a whole group are issued together, then the 8 G corner loads,
+// and only then is any of them used, so that a group costs one chain of dependent loads
+// instead of one per direction.  The sums are accumulated in ascending D, as one direction
+// at a time would, so the result does not depend on G.
 // NP points of one cell are evaluated together: point 0 at cp, point j > 0 at the
 // fractional position pa[j - 1] of the same cell; the corner values are loaded once.
-template <int F, bool FULL, bool TRACE, int NP>
+template <int F, bool FULL, bool TRACE, int NP, int G>
 __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, const int* brow,
                           const float r[3], float inv_band, Eval* ev, const Trace& tr,
                           const float (*pa)[3] = nullptr) {
@@ -168,6 +203,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   // a regular volume: one value per voxel, weight 1, so f is the interpolant itself, the
   // normal its gradient and the colour its colour
   constexpr bool REG = F == kRegularVolume;
+  using Raw = typename GeoRaw<F>::T;
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
     ev[j].defined = false;
@@ -184,10 +220,10 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   const int lx = cp.lo[0], ly = cp.lo[1], lz = cp.lo[2];
   // corners leaving the base block: x when lx == 7, y when ly == 7, z when lz == 7
   const int need = (lx == 7 ? 1 : 0) | (ly == 7 ? 2 : 0) | (lz == 7 ? 4 : 0);
-  // hash slots of the blocks at offset o (o & need == o), else -1.  Every load is issued
-  // unconditionally (absent ones read cell 0) so that they overlap instead of queueing
-  // behind one another.
-  int ns[8];
+  // grid indices of the blocks at offset o (o & need == o), else -1; their records are read
+  // per direction below, every load issued unconditionally (absent ones read record 0) so
+  // that they overlap instead of queueing behind one another
+  int64_t ns[8];
 #pragma unroll
   for (int o = 0; o < 8; ++o) ns[o] = -1;
   if (need) {
@@ -195,10 +231,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
     for (int o = 1; o < 8; ++o) {
       const int64_t gi = grid_index(m, cp.bl[0] + (o & 1), cp.bl[1] + ((o >> 1) & 1),
                                     cp.bl[2] + ((o >> 2) & 1));
-      const bool use = (o & need) == o && gi >= 0;
-      const int sl = m.grid_slot[use ? gi : 0];
-      ns[o] = use ? sl : -1;
-      if (TRACE && tr.slots && ns[o] >= 0) tr.slots[ns[o]] = 1;
+      ns[o] = (o & need) == o ? gi : -1;
+      if (TRACE && tr.slots && ns[o] >= 0 && m.grid_rec[ns[o]].slot >= 0)
+        tr.slots[m.grid_rec[ns[o]].slot] = 1;
     }
   }
   const float ax = cp.a[0], ay = cp.a[1], az = cp.a[2];
@@ -216,6 +251,7 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   const int y1 = (ly + 1) & 7, z1 = (lz + 1) & 7;
   const uint32_t rq[4] = {(uint32_t)(8 * ly + 64 * lz), (uint32_t)(8 * y1 + 64 * lz),
                           (uint32_t)(8 * ly + 64 * z1), (uint32_t)(8 * y1 + 64 * z1)};
+  const bool xin = lx < 7;
   float so = 0.f, sop = 0.f;   // gradient combination weights
   float fo = 0.f, fop = 0.f;   // fallback weights
   bool any = false;
@@ -223,169 +259,194 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   float cg0 = 0.f, cg1 = 0.f, cg2 = 0.f, cgo = 0.f;     // colour weights of the colour blend
   float cgg0 = 0.f, cgg1 = 0.f, cgg2 = 0.f, cggo = 0.f; // geometric weights, gradient branch
   float cgf0 = 0.f, cgf1 = 0.f, cgf2 = 0.f, cgfo = 0.f; // geometric weights, fallback branch
-  for (; pm; pm &= pm - 1) {
-    const int d = __builtin_ctz(pm);
-    const int b0 = brow[d * 64];
-    int br[8];
-    bool ok = true;
+  while (pm) {
+    // ---- the next G present directions, ascending --------------------------------------
+    int dg[G];
+    bool ok[G];
+    int br[G][8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) br[c] = b0;
+    for (int g = 0; g < G; ++g) {
+      ok[g] = pm != 0;
+      dg[g] = ok[g] ? __builtin_ctz(pm) : 0;
+      pm &= pm - 1;
+      const int b0 = brow[dg[g] * 64];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) br[g][c] = b0;
+    }
     if (need) {
-      // corner c lies in the block at offset c & need
-      int nbr[8];
+      // corner c lies in the block at offset c & need; the lookups of the whole group are
+      // issued before any is used
+      int nbr[G][8];
 #pragma unroll
-      for (int o = 1; o < 8; ++o) {
-        const int so = ns[o];
-        const int bo = m.entries[so >= 0 ? so : 0].brick[d];
-        nbr[o] = so >= 0 ? bo : -1;
+      for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int o = 1; o < 8; ++o) {
+          const int64_t so_ = ns[o];
+          const int bo = m.grid_rec[so_ >= 0 ? so_ : 0].brick[dg[g]];
+          nbr[g][o] = so_ >= 0 ? bo : -1;
+        }
       }
 #pragma unroll
-      for (int o = 1; o < 8; ++o) {
-        if ((o & need) != o) continue;
+      for (int g = 0; g < G; ++g) {
 #pragma unroll
-        for (int c = 1; c < 8; ++c)
-          if ((c & o) == o) br[c] = (c & need) == o ? nbr[o] : br[c];
+        for (int o = 1; o < 8; ++o) {
+          if ((o & need) != o) continue;
+#pragma unroll
+          for (int c = 1; c < 8; ++c)
+            if ((c & o) == o) br[g][c] = (c & need) == o ? nbr[g][o] : br[g][c];
+        }
+#pragma unroll
+        for (int c = 1; c < 8; ++c) ok[g] = ok[g] && br[g][c] >= 0;
       }
-#pragma unroll
-      for (int c = 1; c < 8; ++c) ok = ok && br[c] >= 0;
     }
-    if (!ok) continue;
+    // ---- all corner loads of the group --------------------------------------------------
     // corner 2q at x = lx and corner 2q + 1 at x = lx + 1 of row q (x = 0 of the brick at +x
-    // when lx == 7); all eight loads are issued before any is used
-    float sv[8], wv[8];
-    const bool xin = lx < 7;
+    // when lx == 7); a direction that is not evaluated reads voxel 0 of brick 0 instead
+    Raw raw[G][8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t ia = (uint32_t)br[2 * q] * kVox + rq[q] + (uint32_t)lx;
-      const uint32_t ib = xin ? ia + 1u : (uint32_t)br[2 * q + 1] * kVox + rq[q];
-      Vox<F>::load(m.geo, ia, sv[2 * q], wv[2 * q]);
-      Vox<F>::load(m.geo, ib, sv[2 * q + 1], wv[2 * q + 1]);
-      if (TRACE && tr.bricks) {
-        tr.bricks[br[2 * q]] = 1;
-        tr.bricks[br[2 * q + 1]] = 1;
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t ia = (uint32_t)br[g][2 * q] * kVox + rq[q] + (uint32_t)lx;
+        const uint32_t ib = xin ? ia + 1u : (uint32_t)br[g][2 * q + 1] * kVox + rq[q];
+        raw[g][2 * q] = static_cast<const Raw*>(m.geo)[ok[g] ? ia : 0u];
+        raw[g][2 * q + 1] = static_cast<const Raw*>(m.geo)[ok[g] ? ib : 0u];
+        if (TRACE && tr.bricks && ok[g]) {
+          tr.bricks[br[g][2 * q]] = 1;
+          tr.bricks[br[g][2 * q + 1]] = 1;
+        }
       }
     }
-    // defined only if every corner has W > 0; evaluated regardless (then dropped by
-    // zero weights) so that the distance loads need not wait for the weight test
-    bool wok = true;
+    // ---- contributions, in ascending D ----------------------------------------------
 #pragma unroll
-    for (int c = 0; c < 8; ++c) wok = wok && (wv[c] > 0.f);
-    any = any || wok;
-    float phi = 0.f, W = 0.f;
+    for (int g = 0; g < G; ++g) {
+      if (!ok[g]) continue;
+      const int d = dg[g];
+      float sv[8], wv[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      phi = fmaf(tw[c], sv[c], phi);
-      W = fmaf(tw[c], wv[c], W);
-    }
-    // analytic gradient of the interpolant (per voxel)
-    const float gx = (sv[1] - sv[0]) * by * bz + (sv[3] - sv[2]) * ay * bz +
-                     (sv[5] - sv[4]) * by * az + (sv[7] - sv[6]) * ay * az;
-    const float gy = (sv[2] - sv[0]) * bx * bz + (sv[3] - sv[1]) * ax * bz +
-                     (sv[6] - sv[4]) * bx * az + (sv[7] - sv[5]) * ax * az;
-    const float gz = (sv[4] - sv[0]) * bx * by + (sv[5] - sv[1]) * ax * by +
-                     (sv[6] - sv[2]) * bx * ay + (sv[7] - sv[3]) * ax * ay;
-    const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
-    float om = 0.f, wdc = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-    if (REG) {
-      if (gl >= 1e-6f) {
+      for (int c = 0; c < 8; ++c) GeoRaw<F>::decode(raw[g][c], sv[c], wv[c]);
+      // defined only if every corner has W > 0; evaluated regardless (then dropped by
+      // zero weights) so that the distance loads need not wait for the weight test
+      bool wok = true;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) wok = wok && (wv[c] > 0.f);
+      any = any || wok;
+      float phi = 0.f, W = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        phi = fmaf(tw[c], sv[c], phi);
+        W = fmaf(tw[c], wv[c], W);
+      }
+      // analytic gradient of the interpolant (per voxel)
+      const float gx = (sv[1] - sv[0]) * by * bz + (sv[3] - sv[2]) * ay * bz +
+                       (sv[5] - sv[4]) * by * az + (sv[7] - sv[6]) * ay * az;
+      const float gy = (sv[2] - sv[0]) * bx * bz + (sv[3] - sv[1]) * ax * bz +
+                       (sv[6] - sv[4]) * bx * az + (sv[7] - sv[5]) * ax * az;
+      const float gz = (sv[4] - sv[0]) * bx * by + (sv[5] - sv[1]) * ax * by +
+                       (sv[6] - sv[2]) * bx * ay + (sv[7] - sv[3]) * ax * ay;
+      const float gl = sqrtf(gx * gx + gy * gy + gz * gz);
+      float om = 0.f, wdc = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+      if (REG) {
+        if (gl >= 1e-6f) {
+          const float il = 1.f / gl;
+          n0 = gx * il;
+          n1 = gy * il;
+          n2 = gz * il;
+        }
+        wdc = 1.f;
+        om = 1.f;
+      } else if (gl >= 1e-6f) {
         const float il = 1.f / gl;
         n0 = gx * il;
         n1 = gy * il;
         n2 = gz * il;
+        const float wd = w_dir_fast(axis_dot(n0, n1, n2, d), m.theta, inv_band);
+        wdc = wd * fmaxf(0.f, n0 * mr[0] + n1 * mr[1] + n2 * mr[2]);
+        om = wdc * W;
       }
-      wdc = 1.f;
-      om = 1.f;
-    } else if (gl >= 1e-6f) {
-      const float il = 1.f / gl;
-      n0 = gx * il;
-      n1 = gy * il;
-      n2 = gz * il;
-      const float wd = w_dir_fast(axis_dot(n0, n1, n2, d), m.theta, inv_band);
-      wdc = wd * fmaxf(0.f, n0 * mr[0] + n1 * mr[1] + n2 * mr[2]);
-      om = wdc * W;
-    }
-    om = wok ? om : 0.f;
-    wdc = wok ? wdc : 0.f;
-    so += om;
-    sop += om * phi;
-    const float fb = wok ? W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
-    fo += fb;
-    fop += fb * phi;
+      om = wok ? om : 0.f;
+      wdc = wok ? wdc : 0.f;
+      so += om;
+      sop += om * phi;
+      const float fb = wok ? W * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
+      fo += fb;
+      fop += fb * phi;
 #pragma unroll
-    for (int j = 0; j + 1 < NP; ++j) {
-      const float px = pa[j][0], py = pa[j][1], pz = pa[j][2];
-      const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
-      const float uw[8] = {qx * qy * qz, px * qy * qz, qx * py * qz, px * py * qz,
-                           qx * qy * pz, px * qy * pz, qx * py * pz, px * py * pz};
-      float phj = 0.f, Wj = 0.f;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        phj = fmaf(uw[c], sv[c], phj);
-        Wj = fmaf(uw[c], wv[c], Wj);
-      }
-      const float hx = (sv[1] - sv[0]) * qy * qz + (sv[3] - sv[2]) * py * qz +
-                       (sv[5] - sv[4]) * qy * pz + (sv[7] - sv[6]) * py * pz;
-      const float hy = (sv[2] - sv[0]) * qx * qz + (sv[3] - sv[1]) * px * qz +
-                       (sv[6] - sv[4]) * qx * pz + (sv[7] - sv[5]) * px * pz;
-      const float hz = (sv[4] - sv[0]) * qx * qy + (sv[5] - sv[1]) * px * qy +
-                       (sv[6] - sv[2]) * qx * py + (sv[7] - sv[3]) * px * py;
-      const float hl = sqrtf(hx * hx + hy * hy + hz * hz);
-      float omj = 0.f;
-      if (REG) {
-        omj = 1.f;
-      } else if (hl >= 1e-6f) {
-        const float il = 1.f / hl;
-        const float m0 = hx * il, m1 = hy * il, m2 = hz * il;
-        const float wd = w_dir_fast(axis_dot(m0, m1, m2, d), m.theta, inv_band);
-        omj = wd * fmaxf(0.f, m0 * mr[0] + m1 * mr[1] + m2 * mr[2]) * Wj;
-      }
-      omj = wok ? omj : 0.f;
-      so2[j] += omj;
-      sop2[j] += omj * phj;
-      const float fbj = wok ? Wj * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
-      fo2[j] += fbj;
-      fop2[j] += fbj * phj;
-    }
-    if (FULL) {
-      ng0 += om * n0;
-      ng1 += om * n1;
-      ng2 += om * n2;
-      const float sfb = (d & 1) ? -fb : fb;
-      nf0 += d < 2 ? sfb : 0.f;
-      nf1 += (d >> 1) == 1 ? sfb : 0.f;
-      nf2 += d >= 4 ? sfb : 0.f;
-      if (m.with_color && wok) {
-        float wsum = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-        bool cok = true;
+      for (int j = 0; j + 1 < NP; ++j) {
+        const float px = pa[j][0], py = pa[j][1], pz = pa[j][2];
+        const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
+        const float uw[8] = {qx * qy * qz, px * qy * qz, qx * py * qz, px * py * qz,
+                             qx * qy * pz, px * qy * pz, qx * py * pz, px * py * pz};
+        float phj = 0.f, Wj = 0.f;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
-                          64 * ((lz + ((c >> 2) & 1)) & 7);
-          const size_t vi = (size_t)br[c] * kVox + loc;
-          if (TRACE && tr.color) tr.color[br[c]] = 1;
-          float w;
-          uint32_t code;
-          Vox<F>::load_color(m.rgb, m.wc, vi, code, w);
-          cok = cok && (w > 0.f);
-          wsum = fmaf(tw[c], w, wsum);
-          c0 = fmaf(tw[c], (float)(code & 0xFFu), c0);
-          c1 = fmaf(tw[c], (float)((code >> 8) & 0xFFu), c1);
-          c2 = fmaf(tw[c], (float)((code >> 16) & 0xFFu), c2);
+          phj = fmaf(uw[c], sv[c], phj);
+          Wj = fmaf(uw[c], wv[c], Wj);
         }
-        if (cok) {
-          const float oc = wdc * wsum;   // w_dir(n^D) max(0, <n^D, -r>) W_c^D
-          cg0 += oc * c0;
-          cg1 += oc * c1;
-          cg2 += oc * c2;
-          cgg0 += om * c0;
-          cgg1 += om * c1;
-          cgg2 += om * c2;
-          cgf0 += fb * c0;
-          cgf1 += fb * c1;
-          cgf2 += fb * c2;
-          cgo += oc;
-          cggo += om;
-          cgfo += fb;
+        const float hx = (sv[1] - sv[0]) * qy * qz + (sv[3] - sv[2]) * py * qz +
+                         (sv[5] - sv[4]) * qy * pz + (sv[7] - sv[6]) * py * pz;
+        const float hy = (sv[2] - sv[0]) * qx * qz + (sv[3] - sv[1]) * px * qz +
+                         (sv[6] - sv[4]) * qx * pz + (sv[7] - sv[5]) * px * pz;
+        const float hz = (sv[4] - sv[0]) * qx * qy + (sv[5] - sv[1]) * px * qy +
+                         (sv[6] - sv[2]) * qx * py + (sv[7] - sv[3]) * px * py;
+        const float hl = sqrtf(hx * hx + hy * hy + hz * hz);
+        float omj = 0.f;
+        if (REG) {
+          omj = 1.f;
+        } else if (hl >= 1e-6f) {
+          const float il = 1.f / hl;
+          const float m0 = hx * il, m1 = hy * il, m2 = hz * il;
+          const float wd = w_dir_fast(axis_dot(m0, m1, m2, d), m.theta, inv_band);
+          omj = wd * fmaxf(0.f, m0 * mr[0] + m1 * mr[1] + m2 * mr[2]) * Wj;
+        }
+        omj = wok ? omj : 0.f;
+        so2[j] += omj;
+        sop2[j] += omj * phj;
+        const float fbj = wok ? Wj * fmaxf(0.f, axis_dot(mr[0], mr[1], mr[2], d)) : 0.f;
+        fo2[j] += fbj;
+        fop2[j] += fbj * phj;
+      }
+      if (FULL) {
+        ng0 += om * n0;
+        ng1 += om * n1;
+        ng2 += om * n2;
+        const float sfb = (d & 1) ? -fb : fb;
+        nf0 += d < 2 ? sfb : 0.f;
+        nf1 += (d >> 1) == 1 ? sfb : 0.f;
+        nf2 += d >= 4 ? sfb : 0.f;
+        if (m.with_color && wok) {
+          float wsum = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+          bool cok = true;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int loc = ((lx + (c & 1)) & 7) + 8 * ((ly + ((c >> 1) & 1)) & 7) +
+                            64 * ((lz + ((c >> 2) & 1)) & 7);
+            const size_t vi = (size_t)br[g][c] * kVox + loc;
+            if (TRACE && tr.color) tr.color[br[g][c]] = 1;
+            float w;
+            uint32_t code;
+            Vox<F>::load_color(m.rgb, m.wc, vi, code, w);
+            cok = cok && (w > 0.f);
+            wsum = fmaf(tw[c], w, wsum);
+            c0 = fmaf(tw[c], (float)(code & 0xFFu), c0);
+            c1 = fmaf(tw[c], (float)((code >> 8) & 0xFFu), c1);
+            c2 = fmaf(tw[c], (float)((code >> 16) & 0xFFu), c2);
+          }
+          if (cok) {
+            const float oc = wdc * wsum;   // w_dir(n^D) max(0, <n^D, -r>) W_c^D
+            cg0 += oc * c0;
+            cg1 += oc * c1;
+            cg2 += oc * c2;
+            cgg0 += om * c0;
+            cgg1 += om * c1;
+            cgg2 += om * c2;
+            cgf0 += fb * c0;
+            cgf1 += fb * c1;
+            cgf2 += fb * c2;
+            cgo += oc;
+            cggo += om;
+            cgfo += fb;
+          }
         }
       }
     }
@@ -438,6 +499,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
   }
 }
 
+// Directions per group of the march's evaluations (see eval_cell).
+constexpr int march_group(int) { return 1; }
+
 // Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step a
 // bisection, until the bracket is shorter than kRefineTol (metres along the ray) or after
 // kRefineMaxIter evaluations.
@@ -449,22 +513,30 @@ constexpr int kRefineMaxIter = 24;
 // pass inside = false and write nothing).
 //
 // Each pass of the outer loop evaluates the combined SDF once per lane.  Before it, every
-// lane advances on its own through the cheap steps (jumps over absent space and positive
-// sub-blocks, steps through positive cells, refinement bookkeeping) until it holds its next
-// evaluation point, so that the lanes of a wave evaluate together instead of taking turns.
-template <int F, bool TRACE>
+// lane advances on its own through the cheap steps (jumps over absent space, positive
+// sub-blocks and positive cells, refinement bookkeeping) until it holds its next evaluation
+// point, so that the lanes of a wave evaluate together instead of taking turns.  A lattice
+// point whose successor lies in the same cell is evaluated together with it (the corner
+// values are loaded once), so a ray crossing the band at a grazing angle needs about half
+// the passes.
+template <int F, bool TRACE, int G>
 __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v, bool inside) {
   const size_t i = (size_t)v * a.W + u;
   const size_t HW = (size_t)a.W * a.H;
   const float inv_band = 1.0f / (2.0f * m.theta - 1.5707963267948966f);
-  double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
-  const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
-  const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
   double r[3];
-  for (int k = 0; k < 3; ++k) r[k] = a.R[3 * k] * rc[0] + a.R[3 * k + 1] * rc[1] + a.R[3 * k + 2] * rc[2];
+  double t0, tmax;
+  {
+    const double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
+    const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
+    const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
+    for (int k = 0; k < 3; ++k)
+      r[k] = a.R[3 * k] * rc[0] + a.R[3 * k + 1] * rc[1] + a.R[3 * k + 2] * rc[2];
+    t0 = a.z_near / rc[2];
+    tmax = a.z_far / rc[2];
+  }
   const float rf[3] = {(float)r[0], (float)r[1], (float)r[2]};
   const double o[3] = {a.t[0], a.t[1], a.t[2]};
-  const double t0 = a.z_near / rc[2], tmax = a.z_far / rc[2];
   const double step = m.step;
   const Trace tr{a.trace_bricks, a.trace_color, a.trace_slots};
   int n_eval = 0, n_skip = 0, n_absent = 0, n_refine = 0;
@@ -472,19 +544,19 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
                         r[2] != 0.0 ? 1.0 / r[2] : 0.0};
   const double inv_step = 1.0 / step;
   const double bw = kB * m.voxel;          // block edge [m]
-  int cb0 = 0x7fffffff, cb1 = 0, cb2 = 0;  // block of the cached entry
-  // brick indices of each lane's current block, direction d at [d * 64 + lane]
+  int cb0 = 0x7fffffff, cb1 = 0, cb2 = 0;  // block of the cached record
+  // per lane (column `lane`): brick indices of the current block, direction d at row d;
+  // its positive-cell words, slice z at row z; its group bytes, bytes 8 w .. 8 w + 7 at row w
   __shared__ int brick_rows[6 * 64];
-  int* const brow = brick_rows + (threadIdx.x & 63);
-  uint32_t cpm = 0;                // present directions of the current block
-  bool cpresent = false;
-  uint32_t cmask = 0;
-  int pos_last = -1;              // last lattice point of the current positive run
-  // positive-cell words of each lane's current block, slice z at [z * 64 + lane], and its
-  // defined-direction group bytes, bytes 8 w .. 8 w + 7 at [w * 64 + lane]
   __shared__ uint64_t cell_words[8 * 64];
   __shared__ uint64_t group_words[8 * 64];
   const int lane = (int)(threadIdx.x & 63);
+  int* const brow = brick_rows + lane;
+  uint64_t* const cwl = cell_words + lane;
+  uint64_t* const gwl = group_words + lane;
+  uint32_t cpm = 0;               // present directions of the current block
+  uint32_t cinfo = 0;             // record info word of the current block (see enter_block)
+  int pos_last = -1;              // last lattice point of the current positive run
   bool prev_def = false, hit = false, refining = false, done = !inside;
   float prev_f = 0.f, fa = 0.f, fb = 0.f;
   double ta = 0.0, tb = 0.0;
@@ -492,9 +564,9 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   int it = 0, side = 0;
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
-  double te2 = 0.0;       // refinement: second point of the pending pair
-  bool lattice = false;   // the pending point is lattice point k of a sub-block that may
-                          // hold a crossing
+  double te2 = 0.0;       // second point evaluated with it (refinement pair, or lattice k + 1)
+  bool lattice = false;   // the pending point is lattice point k, not a deferred one
+  bool lpair = false;     // lattice: k + 1 is evaluated together with k
   int next_k = 0;         // lattice index after the pending point
   for (;;) {
     // ---- advance to the next evaluation point ---------------------------------------
@@ -527,43 +599,15 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         cb0 = cp.bl[0];
         cb1 = cp.bl[1];
         cb2 = cp.bl[2];
-        const int64_t gi = grid_index(m, cb0, cb1, cb2);
-        const int s = gi < 0 ? -1 : m.grid_slot[gi];
-        cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
-        cpresent = s >= 0;
-        if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
-        cpm = load_bricks(m, s, brow);
-        if (s >= 0) {
-          const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
-          const uint4* gw = reinterpret_cast<const uint4*>(m.dir_groups + (size_t)s * 64);
-          uint4 q[4], qg[4];
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            q[h] = cw[h];
-            qg[h] = gw[h];
-          }
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
-            cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
-            group_words[(2 * h) * 64 + lane] = (uint64_t)qg[h].x | ((uint64_t)qg[h].y << 32);
-            group_words[(2 * h + 1) * 64 + lane] = (uint64_t)qg[h].z | ((uint64_t)qg[h].w << 32);
-          }
-        }
+        cinfo = enter_block<TRACE>(m, grid_index(m, cb0, cb1, cb2), brow, cwl, gwl, cpm, tr);
       }
-      if (!cpresent) {
-        const int g[3] = {cb0 - m.gx0, cb1 - m.gy0, cb2 - m.gz0};
-        const bool inside = g[0] >= 0 && g[1] >= 0 && g[2] >= 0 && g[0] < m.gx && g[1] < m.gy &&
-                            g[2] < m.gz;
+      if (!(cinfo & kRecPresent)) {
         const int gg[3] = {m.gx0, m.gy0, m.gz0};
         double texit;
-        if (inside) {
-          // absent block: leave the largest empty cell of the hierarchy that contains it
-          int sh = 0;   // log2 of the cell edge in blocks
-          const int m1x = (m.gx + 3) >> 2, m1y = (m.gy + 3) >> 2;
-          const int m2x = (m.gx + 15) >> 4, m2y = (m.gy + 15) >> 4;
-          if (!m.macro2[((int64_t)(g[2] >> 4) * m2y + (g[1] >> 4)) * m2x + (g[0] >> 4)]) sh = 4;
-          else if (!m.macro1[((int64_t)(g[2] >> 2) * m1y + (g[1] >> 2)) * m1x + (g[0] >> 2)]) sh = 2;
+        if (cinfo & kRecInGrid) {
+          // absent block: leave the largest aligned empty cell containing it
+          const int sh = (int)((cinfo >> 8) & 7u);   // log2 of its edge in blocks
+          const int g[3] = {cb0 - m.gx0, cb1 - m.gy0, cb2 - m.gz0};
           double lo[3], hi[3];
 #pragma unroll
           for (int ax = 0; ax < 3; ++ax) {
@@ -599,16 +643,19 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         continue;
       }
       const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
-      if ((cmask >> sub) & 1u) {
-        // positive sub-block: no crossing can end in it; jump past it, remembering its last
-        // lattice point (evaluated only if the point after it is)
+      const bool pos_sub = (cinfo >> sub) & 1u;
+      const bool pos_cell =
+          pos_sub || ((cwl[cp.lo[2] * 64] >> (cp.lo[0] + 8 * cp.lo[1])) & 1ull);
+      if (pos_cell) {
+        // positive sub-block or cell: no crossing can end in it; jump to its last lattice
+        // point (evaluated only if the point after it is)
         double lo[3], hi[3];
         const int cbv[3] = {cb0, cb1, cb2};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const int v0 = cbv[ax] * kB + ((sub >> ax) & 1) * 4;
+          const int v0 = pos_sub ? cbv[ax] * kB + ((sub >> ax) & 1) * 4 : cbv[ax] * kB + cp.lo[ax];
           lo[ax] = (double)v0 * m.voxel;
-          hi[ax] = (double)(v0 + 4) * m.voxel;
+          hi[ax] = (double)(v0 + (pos_sub ? 4 : 1)) * m.voxel;
         }
         const double texit = box_exit(o, ir, lo, hi);
         const double jn = ceil((texit - 1e-6 - t0) * inv_step);
@@ -622,12 +669,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         k = last + 1;
         continue;
       }
-      if ((cell_words[cp.lo[2] * 64 + lane] >> (cp.lo[0] + 8 * cp.lo[1])) & 1ull) {
-        // positive cell: the same, one lattice point
-        pos_last = k;
-        k = k + 1;
-        continue;
-      }
+      lpair = false;
       if (pos_last == k - 1 && k >= 1) {
         // the crossing test at k needs the value at k - 1, skipped so far
         te = t0 + (double)(k - 1) * step;
@@ -639,7 +681,16 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         te = tk;
         lattice = true;
         next_k = k + 1;
-        if (TRACE) ++n_eval;
+        // lattice point k + 1 in the same cell: evaluated in the same pass
+        te2 = t0 + (double)(k + 1) * step;
+        if (te2 <= tmax) {
+          const double x2[3] = {o[0] + te2 * r[0], o[1] + te2 * r[1], o[2] + te2 * r[2]};
+          CellPos cp2;
+          locate(m, x2, cp2);
+          lpair = cp2.bl[0] == cp.bl[0] && cp2.bl[1] == cp.bl[1] && cp2.bl[2] == cp.bl[2] &&
+                  cp2.lo[0] == cp.lo[0] && cp2.lo[1] == cp.lo[1] && cp2.lo[2] == cp.lo[2];
+        }
+        if (TRACE) n_eval += lpair ? 2 : 1;
       }
       pending = true;
     }
@@ -654,34 +705,13 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       cb0 = cp.bl[0];
       cb1 = cp.bl[1];
       cb2 = cp.bl[2];
-      const int64_t gi = grid_index(m, cb0, cb1, cb2);
-      const int s = gi < 0 ? -1 : m.grid_slot[gi];
-      cmask = gi < 0 ? 0u : (uint32_t)m.grid_mask[gi];
-      cpresent = s >= 0;
-      if (TRACE && tr.slots && s >= 0) tr.slots[s] = 1;
-      cpm = load_bricks(m, s, brow);
-      if (s >= 0) {
-        const uint4* cw = reinterpret_cast<const uint4*>(m.cell_mask + (size_t)s * 8);
-        const uint4* gw = reinterpret_cast<const uint4*>(m.dir_groups + (size_t)s * 64);
-        uint4 q[4], qg[4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          q[h] = cw[h];
-          qg[h] = gw[h];
-        }
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          cell_words[(2 * h) * 64 + lane] = (uint64_t)q[h].x | ((uint64_t)q[h].y << 32);
-          cell_words[(2 * h + 1) * 64 + lane] = (uint64_t)q[h].z | ((uint64_t)q[h].w << 32);
-          group_words[(2 * h) * 64 + lane] = (uint64_t)qg[h].x | ((uint64_t)qg[h].y << 32);
-          group_words[(2 * h + 1) * 64 + lane] = (uint64_t)qg[h].z | ((uint64_t)qg[h].w << 32);
-        }
-      }
+      cinfo = enter_block<TRACE>(m, grid_index(m, cb0, cb1, cb2), brow, cwl, gwl, cpm, tr);
     }
-    // a refinement pair is evaluated together when both points share the cell
-    bool pair = false;
+    // a second point is evaluated with the first when both share the cell: the refinement
+    // pair, or lattice point k + 1
+    bool pair = lattice && lpair;
     float pa1[1][3] = {{cp.a[0], cp.a[1], cp.a[2]}};
-    if (refining) {
+    if (refining || pair) {
       const double x2[3] = {o[0] + te2 * r[0], o[1] + te2 * r[1], o[2] + te2 * r[2]};
       CellPos cp2;
       locate(m, x2, cp2);
@@ -694,9 +724,8 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     Eval ev[2];
     // only the directions defined somewhere in the cell's 2x2x2 group can contribute
     const int grp = (cp.lo[0] >> 1) + 4 * (cp.lo[1] >> 1) + 16 * (cp.lo[2] >> 1);
-    const uint32_t gdef =
-        (uint32_t)(group_words[(grp >> 3) * 64 + lane] >> (8 * (grp & 7))) & 0x3Fu;
-    eval_cell<F, false, TRACE, 2>(m, cp, cpm & gdef, brow, rf, inv_band, ev, tr, pa1);
+    const uint32_t gdef = (uint32_t)(gwl[(grp >> 3) * 64] >> (8 * (grp & 7))) & 0x3Fu;
+    eval_cell<F, false, TRACE, 2, G>(m, cp, cpm & gdef, brow, rf, inv_band, ev, tr, pa1);
     const Eval& e = ev[0];
     if (refining) {
       if (TRACE) ++n_refine;
@@ -732,6 +761,22 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       fb = e.f;
       continue;
     }
+    if (pair) {
+      // lattice point k + 1, with f(k) from the first point
+      if (ev[1].defined && e.defined && e.f > 0.f && ev[1].f <= 0.f) {
+        hit = true;
+        refining = true;
+        ta = te;
+        tb = te2;
+        fa = e.f;
+        fb = ev[1].f;
+        continue;
+      }
+      prev_def = ev[1].defined;
+      prev_f = ev[1].f;
+      k = next_k + 1;
+      continue;
+    }
     prev_def = e.defined;
     prev_f = e.f;
     k = next_k;
@@ -743,9 +788,14 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
     CellPos cp;
     locate(m, x, cp);
-    const uint32_t pm = load_bricks(m, block_slot<TRACE>(m, cp.bl[0], cp.bl[1], cp.bl[2], tr), brow);
+    uint32_t pm = 0;
+    enter_block<TRACE>(m, grid_index(m, cp.bl[0], cp.bl[1], cp.bl[2]), brow, cwl, gwl, pm, tr);
     Eval e;
-    eval_cell<F, true, TRACE, 1>(m, cp, pm, brow, rf, inv_band, &e, tr);
+    eval_cell<F, true, TRACE, 1, 1>(m, cp, pm, brow, rf, inv_band, &e, tr);
+    // the camera-frame ray again (not kept live through the march)
+    const double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
+    const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
+    const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
     out_depth = (float)(ts * rc[2]);
     for (int k = 0; k < 3; ++k) out_v[k] = (float)(ts * rc[k]);
     const float nl = sqrtf(e.n[0] * e.n[0] + e.n[1] * e.n[1] + e.n[2] * e.n[2]);
@@ -784,7 +834,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
 }
 
 // Three waves per SIMD (at most 168 VGPRs): the march is latency-bound and needs the waves.
-template <int F, bool TRACE>
+template <int F, bool TRACE, int G = march_group(F)>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_k(
     MapView m, RenderArgs a) {
   // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
@@ -793,13 +843,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
   if (tile >= a.tiles) return;
   const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
   const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
-  render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
+  render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
 }
 
 // Views of different sizes in one persistent launch: every wave takes the next (view, tile)
 // work item from a counter until all are done.  Each pixel is computed exactly as by
 // render_k, so a view's output does not depend on the batch it is rendered in.
-template <int F, bool TRACE>
+template <int F, bool TRACE, int G = march_group(F)>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_batch_k(MapView m, const RenderArgs* __restrict__ reqs,
                                                      const int32_t* __restrict__ prefix, int n,
                                                      int total, int32_t* counter) {
@@ -814,11 +864,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
       if (prefix[mid] <= item) lo = mid;
       else hi = mid;
     }
-    const RenderArgs a = reqs[lo];
+    const RenderArgs& a = reqs[lo];
     const int tile = item - prefix[lo];
     const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
     const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
-    render_pixel<F, TRACE>(m, a, u, v, u < a.W && v < a.H);
+    render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
   }
 }
 
