@@ -801,7 +801,8 @@ enum {
   kBranch = 4,        // a lattice sample up to the hit changes definedness, branch (gradient
                       // weights or fallback) or sign when every thresholded factor is moved
                       // by +/- eps_s
-  kAmbiguous = 8,     // the bracket holds more than one sign change or an undefined point
+  kAmbiguous = 8,     // the bracket holds more than one sign change (undefined points count
+                      // as free space)
   kRootFace = 16,     // the root lies inside a cell but within eps_root metres of one of its
                       // faces: a refinement with that tolerance may take the outputs from
                       // the neighbouring cell (normal, colour)
@@ -896,18 +897,16 @@ void orc_render(void* h, int64_t n, const int32_t* us, const int32_t* vs, double
           *def = S.defined;
           return S.f;
         };
-        // ambiguity: more than one sign change or an undefined point among 64 samples
+        // ambiguity: more than one sign change among 64 samples of the bracket, undefined
+        // points counting as free space as in the refinement below (an undefined stretch
+        // between the positive and the negative end leaves the root unique)
         if (cfg->classify) {
           int changes = 0;
           bool lastpos = true;
           for (int j = 0; j <= 64; ++j) {
             bool def;
             double fv = f_at(ta + (tb - ta) * j / 64.0, &def);
-            if (!def) {
-              fl |= kAmbiguous;
-              continue;
-            }
-            bool pos = fv > 0;
+            bool pos = !def || fv > 0;
             if (j > 0 && pos != lastpos) changes++;
             lastpos = pos;
           }

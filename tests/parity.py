@@ -39,9 +39,25 @@ def room_gpu_params(dtsdf, capacity=1 << 19, buckets=1 << 20, **kw):
                         hash_buckets=buckets, **kw)
 
 
+# Flags that exempt a pixel from a comparison.  The hit decision depends only on the lattice
+# samples up to the hit (near-zero value, cell-face, thresholded weight factor); an
+# ambiguous bracket can move the root (depth, normal, colour); a root within eps_root of a
+# cell face can take normal and colour from the neighbouring cell.
+MASK_FLAGS = O.NEAR_ZERO | O.NEAR_FACE | O.BRANCH
+DEPTH_FLAGS = MASK_FLAGS | O.AMBIGUOUS
+SHADE_FLAGS = DEPTH_FLAGS | O.ROOT_FACE
+# Upper bound on the share of compared pixels that any flag exempts (the exception is meant
+# for rays that graze a zero crossing, not for a sizeable part of the image)
+MAX_FLAGGED_SHARE = 0.01
+
+
 def compare_render(gpu: dict, ref, pixels=None, *, W=None, name=""):
     """Compares GPU render outputs (dict of CPU numpy arrays, full images) with oracle
-    outputs for `pixels` ((n,2) u,v; None: all).  Returns a stats dict; raises on failure."""
+    outputs for `pixels` ((n,2) u,v; None: all).  Returns a stats dict; raises on failure.
+
+    The hit mask must be equal except where a lattice sample up to the hit is flagged
+    (MASK_FLAGS); depth is compared where both hit outside DEPTH_FLAGS, normal and colour
+    outside SHADE_FLAGS.  At most MAX_FLAGGED_SHARE of the pixels may carry any flag."""
     if pixels is None:
         H, Wd = gpu["mask"].shape
         vv, uu = np.mgrid[0:H, 0:Wd]
@@ -49,25 +65,32 @@ def compare_render(gpu: dict, ref, pixels=None, *, W=None, name=""):
     u, v = pixels[:, 0], pixels[:, 1]
     gm = gpu["mask"][v, u].astype(bool)
     om = ref.mask.astype(bool)
-    graze = ref.flags != 0
-    st = dict(n=len(u), hits=int(om.sum()), grazing=int(graze.sum()))
-    mism = (gm != om) & ~graze
+    fl = ref.flags.astype(int)
+    g_mask = (fl & MASK_FLAGS) != 0
+    g_depth = (fl & DEPTH_FLAGS) != 0
+    g_shade = (fl & SHADE_FLAGS) != 0
+    st = dict(n=len(u), hits=int(om.sum()), flagged=int((fl != 0).sum()),
+              flagged_mask=int(g_mask.sum()), flagged_share=float((fl != 0).mean()) if len(u) else 0.0)
+    mism = (gm != om) & ~g_mask
     st["mask_mismatch"] = int(mism.sum())
-    st["mask_mismatch_incl_grazing"] = int((gm != om).sum())
-    both = gm & om & ~graze
+    st["mask_mismatch_incl_flagged"] = int((gm != om).sum())
+    both = gm & om & ~g_depth
     st["compared"] = int(both.sum())
     dz = np.abs(gpu["depth"][v, u][both] - ref.depth[both])
     st["depth_max"] = float(dz.max()) if dz.size else 0.0
+    shade = gm & om & ~g_shade
     if "normal" in gpu:
-        nodir = both & ((ref.flags & O.ROOT_FACE) == 0)
-        gn = np.stack([gpu["normal"][k][v, u] for k in range(3)], 1)[nodir]
-        on = ref.normal[nodir]
+        gn = np.stack([gpu["normal"][k][v, u] for k in range(3)], 1)[shade]
+        on = ref.normal[shade]
         cosang = np.clip((gn * on).sum(1) / np.maximum(np.linalg.norm(gn, axis=1), 1e-30), -1, 1)
         ang = np.degrees(np.arccos(cosang))
         st["normal_max_deg"] = float(ang.max()) if ang.size else 0.0
+    if "vertex" in gpu:
+        gv = np.stack([gpu["vertex"][k][v, u] for k in range(3)], 1)[both]
+        st["vertex_max"] = float(np.abs(gv - ref.vertex[both]).max()) if gv.size else 0.0
     if "rgba" in gpu:
-        gc = gpu["rgba"][v, u][both].astype(int)
-        oc = ref.rgba[both].astype(int)
+        gc = gpu["rgba"][v, u][shade].astype(int)
+        oc = ref.rgba[shade].astype(int)
         st["alpha_mismatch"] = int((gc[:, 3] != oc[:, 3]).sum())
         cb = (gc[:, 3] == 255) & (oc[:, 3] == 255)
         st["color_max"] = int(np.abs(gc[cb, :3] - oc[cb, :3]).max()) if cb.any() else 0
@@ -76,10 +99,14 @@ def compare_render(gpu: dict, ref, pixels=None, *, W=None, name=""):
         problems.append("mask")
     if st["depth_max"] > DEPTH_TOL:
         problems.append("depth")
+    if st.get("vertex_max", 0) > DEPTH_TOL:
+        problems.append("vertex")
     if st.get("normal_max_deg", 0) > NORMAL_TOL_DEG:
         problems.append("normal")
     if st.get("color_max", 0) > COLOR_TOL or st.get("alpha_mismatch", 0):
         problems.append("color")
+    if st["flagged"] > MAX_FLAGGED_SHARE * st["n"]:
+        problems.append("flagged share")
     print(f"[render parity {name}] {st}", flush=True)
     assert not problems, f"{name}: {problems} {st}"
     return st
