@@ -53,7 +53,7 @@ typedef enum {
 
 typedef enum {
   DTSDF_W_F32 = 0, /* float32 weight */
-  DTSDF_W_U8 = 1   /* uint8 code q = round(4 w), weights capped at 63.75 */
+  DTSDF_W_U8 = 1   /* uint8 code q = round(sqrt(1024 w)), w = q^2 / 1024 (at most 63.5) */
 } dtsdf_w_fmt;
 
 typedef struct {

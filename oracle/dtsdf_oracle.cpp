@@ -54,7 +54,7 @@ struct Params {
   int32_t with_color;
   int32_t single_direction;  // control: one direction with w_dir = 1 (a regular TSDF)
   int32_t sdf_fmt;           // 0 float, 1 float16 code, 2 int16 code scaled by the truncation
-  int32_t w_fmt;             // 0 float, 1 uint8 code of 4 w
+  int32_t w_fmt;             // 0 float, 1 uint8 code q, w = q^2 / 1024
 };
 
 struct Key {
@@ -247,10 +247,23 @@ double store_sdf(const Params& p, double d, bool* tie) {
   return d;
 }
 
-// Stored form of a weight: the uint8 code q = round(4 w) (capped at 255 by w_max = 63.75).
+// Stored form of a weight in the uint8 format: the code q = round-half-even(sqrt(1024 w)),
+// at most 255, standing for w = q^2 / 1024 (a square-law code: its step (2 q + 1) / 1024
+// is fine at small weights, so that carving and small fusion weights accumulate).  `tie`
+// is set when 1024 w lies within 1e-3 steps of a rounding boundary (q + 1/2)^2.
 double store_w(const Params& p, double w, bool* tie) {
-  if (p.w_fmt == 1) return std::min(255.0, round_to(4.0 * w, 1.0, 1e-3, tie)) / 4.0;
-  return w;
+  if (p.w_fmt != 1) return w;
+  const double x = 1024.0 * std::max(0.0, w);
+  // nearbyint rounds half to even; the square root of an exact boundary (c + 1/2)^2 is
+  // exact, so ties go to the even code
+  double q = std::nearbyint(std::sqrt(x));
+  for (double c : {q - 1.0, q}) {   // the boundaries below and above q
+    if (c < 0) continue;
+    const double mid = c * c + c + 0.25;
+    if (std::fabs(x - mid) < 1e-3 * (2.0 * c + 1.0)) *tie = true;
+  }
+  q = std::min(255.0, q);
+  return q * q / 1024.0;
 }
 
 }  // namespace

@@ -146,7 +146,7 @@ class MapParams:
     with_color: bool = True
     single_direction: bool = False
     sdf_fmt: int = 0            # 0 float, 1 float16, 2 int16 scaled by the truncation
-    w_fmt: int = 0              # 0 float, 1 uint8 code of 4 w
+    w_fmt: int = 0              # 0 float, 1 uint8 code q, w = q^2 / 1024
 
     def c_struct(self) -> _Params:
         p = _Params()

@@ -15,7 +15,8 @@
 //                                   these.  Plain format: float2 (sdf, w), 8 bytes.  Packed
 //                                   formats: one 32-bit word, sdf code in bits 0-15 (float16,
 //                                   or int16 q with sdf = q / 32767) and the weight code
-//                                   q = round(4 w) in bits 16-23, 4 bytes.
+//                                   q (w = q^2 / 1024, see weight_code) in bits 16-23,
+//                                   4 bytes.
 //   rgb      uint32[capacity*512]   r | g << 8 | b << 16 colour code per voxel; in the packed
 //                                   formats the colour-weight code sits in bits 24-31
 //   wc       float[capacity*512]    colour weight per voxel (plain format only)
@@ -119,8 +120,23 @@ __host__ __device__ inline uint32_t hash_key(uint64_t k) {
 // Read-only view of a map, passed by value to kernels.
 // Storage formats: 0 plain float, 1 float16 distance + uint8 weights, 2 int16 distance
 // (scaled by the truncation) + uint8 weights.  Codes are rounded half to even.
+// Weight code of the packed formats: q in 0 .. 255 stands for w = q^2 / 1024 (0 .. 63.5).
+// The step between codes, (2 q + 1) / 1024, is 0.02 at w = 0.1 and 0.5 at the top, so that
+// carving updates (w_carve = 0.1) and small fusion weights accumulate instead of rounding
+// back to the old code.  q = round-half-even(sqrt(1024 w)), decided exactly: 1024 w and the
+// rounding boundaries (q + 1/2)^2 = q^2 + q + 1/4 are exact float32 values.
 __host__ __device__ inline uint32_t weight_code(float w) {
-  return (uint32_t)fminf(255.f, rintf(4.f * fmaxf(0.f, w)));
+  const float x = 1024.f * fmaxf(0.f, w);
+  int q = (int)fminf(256.f, sqrtf(x));
+  while (q > 0 && (float)(q * q) > x) --q;
+  while (q < 256 && (float)((q + 1) * (q + 1)) <= x) ++q;
+  const float mid = (float)(q * q + q) + 0.25f;
+  if (x > mid || (x == mid && (q & 1))) ++q;
+  return (uint32_t)(q < 255 ? q : 255);
+}
+
+__host__ __device__ inline float weight_decode(uint32_t q) {
+  return (float)(q * q) * (1.f / 1024.f);
 }
 
 template <int F>
@@ -151,12 +167,12 @@ struct Vox<0> {
 
 struct VoxPacked {
   static constexpr int kGeoBytes = 4;
-  __host__ __device__ static float weight(uint32_t v) { return (float)((v >> 16) & 0xFFu) * 0.25f; }
+  __host__ __device__ static float weight(uint32_t v) { return weight_decode((v >> 16) & 0xFFu); }
   __host__ __device__ static void load_color(const uint32_t* rgb, const float*, size_t i,
                                              uint32_t& code, float& w) {
     const uint32_t v = rgb[i];
     code = v & 0xFFFFFFu;
-    w = (float)(v >> 24) * 0.25f;
+    w = weight_decode(v >> 24);
   }
   __host__ __device__ static void store_color(uint32_t* rgb, float*, size_t i, uint32_t code,
                                               float w) {

@@ -578,8 +578,64 @@ def test_quantised_storage_matches_reference_rounding(sdf_fmt):
                   np.float32(1.0 / 32767.0)).astype(np.float64)
         assert np.mean(b["sdf"][band] == expect) > 0.999
     assert np.max(np.abs(b["sdf"][band] - expect)) < 1e-7      # float32 export of the code
-    q = b["w"] * 4
+    q = np.sqrt(b["w"] * 1024.0)
     assert np.all(q == np.round(q)) and q.max() <= 255
-    # weights are the rounded view cosines (one frame)
+    # weights are the coded view cosines of the pixel rays (one frame); the voxel's own
+    # viewing direction differs from its pixel's ray by up to half a pixel, so within one
+    # code step of the code of its cosine
     cosang = x[..., 2] / np.linalg.norm(x, axis=-1)
-    assert np.max(np.abs(b["w"][band] - np.rint(4 * cosang[band]) / 4)) <= 0.25
+    qe = np.minimum(np.rint(np.sqrt(1024.0 * cosang[band])), 255)
+    assert np.all(np.abs(b["w"][band] - qe ** 2 / 1024.0) <= (2 * qe + 1) / 1024.0)
+
+
+def _weight_code(w):
+    """The uint8 weight code written out: q = round-half-even(sqrt(1024 w)), at most 255."""
+    return int(min(255, np.rint(math.sqrt(1024.0 * w))))
+
+
+def test_weight_code_definition():
+    """Values the square-law code fixes: 0 and the top, the exact code points, a tie
+    between two codes going to the even one, and the step at small weights."""
+    m = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04, w_fmt=1))
+    del m
+    assert _weight_code(0.0) == 0 and _weight_code(63.5) == 255 and _weight_code(100.0) == 255
+    for q in (1, 7, 100, 254):
+        assert _weight_code(q * q / 1024.0) == q
+    # (q + 1/2)^2 / 1024 lies halfway between codes q and q + 1 in the square root
+    assert _weight_code((10.5 ** 2) / 1024.0) == 10 and _weight_code((11.5 ** 2) / 1024.0) == 12
+    # a carving weight of 0.1 is representable to within 1 %
+    assert abs(_weight_code(0.1) ** 2 / 1024.0 - 0.1) < 0.003
+
+
+@pytest.mark.parametrize("sdf_fmt", [1, 2])
+def test_quantised_weights_accumulate(sdf_fmt):
+    """Repeated carving (w_carve = 0.1) and repeated small fusion weights raise the stored
+    uint8 weight frame after frame, as the float32 weights do, instead of rounding back
+    to the old code: the cumulative weighted average of Sec. 3 is kept."""
+    cam = TINY
+    T = np.eye(4)
+    # a frontal plane at 0.5 m seen through a thin slab of voxels: voxels in front of the
+    # band are carved, voxels in the band are fused with the view cosine as weight
+    depth = np.full((cam.height, cam.width), 0.5, np.float32)
+    plain = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04))
+    packed = O.OracleMap(O.MapParams(voxel=0.01, tau=0.04, sdf_fmt=sdf_fmt, w_fmt=1))
+    wp, wq = [], []
+    for _ in range(6):
+        plain.integrate(depth, None, cam, T)
+        packed.integrate(depth, None, cam, T)
+        bp, bq = plain.export(), packed.export()
+        assert np.array_equal(bp["keys"], bq["keys"])
+        wp.append(bp["w"].copy())
+        wq.append(bq["w"].copy())
+    x = _voxel_positions(bp, 0.01)
+    d = (0.5 - x[..., 2]) / O.f32(0.04)
+    carved = (d > 1.2) & (wp[-1] > 0)
+    band = (np.abs(d) < 0.8) & (wp[-1] > 0)
+    assert carved.sum() > 1000 and band.sum() > 1000
+    for sel in (carved, band):
+        for k in range(1, 6):
+            # every frame raises every stored weight ...
+            assert np.all(wq[k][sel] > wq[k - 1][sel])
+            # ... and each of the k + 1 updates so far rounded by at most half a code step
+            step = (2.0 * np.sqrt(wq[k][sel] * 1024.0) + 1.0) / 1024.0
+            assert np.all(np.abs(wq[k][sel] - wp[k][sel]) <= (k + 1) * step / 2)
