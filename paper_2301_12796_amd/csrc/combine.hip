@@ -335,9 +335,8 @@ dtsdf_status mirror_blocks(const dtsdf_map* src, dtsdf_map* vol, hipStream_t st)
   if (gs != DTSDF_OK) return gs;
   int64_t handed = c[0];
   if (handed > (int64_t)vol->p.brick_capacity) {
-    int32_t cap = (int32_t)vol->p.brick_capacity;
-    DTSDF_HIP(hipMemcpyAsync(vol->counters, &cap, sizeof(cap), hipMemcpyHostToDevice, st));
-    handed = cap;
+    launch_clamp_handed(vol, st);
+    handed = vol->p.brick_capacity;
   }
   const bool dropped = c[1] > vol->dropped;
   vol->dropped = c[1];

@@ -363,6 +363,25 @@ struct dtsdf_map {
 namespace dtsdf {
 MapView make_view(const dtsdf_map* m);
 
+// Slot of the per-device descriptor staging ring (staging.hip): pinned host memory, device
+// memory and an event recorded behind the last work that read the slot.
+struct Stage {
+  uint8_t* host = nullptr;
+  uint8_t* dev = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  bool recorded = false;
+};
+constexpr size_t kStageHostBytes = size_t(2) << 20;
+constexpr size_t kStageDevBytes = size_t(8) << 20;
+// Hands out a free slot of the current device once the work that last used it has
+// finished (DTSDF_E_BUSY if every slot is held by a call that has not released it).
+dtsdf_status stage_acquire(Stage** out);
+// Records the slot's event on `st` behind the work enqueued so far and frees the slot.
+dtsdf_status stage_release(Stage* s, hipStream_t st);
+// Enqueues the clamp of the bricks-handed-out counter (counters[0]) at the pool capacity.
+void launch_clamp_handed(dtsdf_map* m, hipStream_t st);
+
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Minima of the eight 4^3 sub-blocks of brick `b` over voxels with w > 0 (+inf if none),

@@ -17,6 +17,7 @@
 //                  (eq. ICP_solution), exp(xi) in closed form and T <- exp(xi) T
 //                  (eq. deltaT_update), all on the device.
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -700,6 +701,41 @@ __global__ __launch_bounds__(256) void mean2x2_k(const float* __restrict__ in, i
   out[(size_t)v * Wo + u] = 0.25f * ((r0[0] + r0[1]) + (r1[0] + r1[1]));
 }
 
+// Batches whose descriptors exceed a staging slot: a pinned block of their own, released
+// once the stream has run the batch (the call waits for it).
+dtsdf_status icp_batch_large(int32_t n, const dtsdf_icp_req* reqs, int32_t iterations,
+                             hipStream_t hs) {
+  const size_t jb = (sizeof(IcpJob) * n + 255) & ~(size_t)255;
+  const size_t pb = sizeof(float) * 2 * kChunks * kNSMax * (size_t)n;
+  IcpJob* jobs = nullptr;
+  uint8_t* dev = nullptr;
+  if (hipHostMalloc((void**)&jobs, sizeof(IcpJob) * n, hipHostMallocDefault) != hipSuccess)
+    return DTSDF_E_NOMEM;
+  dtsdf_status rs = DTSDF_OK;
+  for (int r = 0; r < n; ++r)
+    make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params,
+             reqs[r].pose, reqs[r].active, reqs[r].min_step, reqs[r].result, jobs[r]);
+  if (hipMallocAsync((void**)&dev, jb + pb, hs) != hipSuccess) {
+    rs = DTSDF_E_NOMEM;
+  } else {
+    if (hipMemcpyAsync(dev, jobs, sizeof(IcpJob) * n, hipMemcpyHostToDevice, hs) != hipSuccess) {
+      rs = DTSDF_E_HIP;
+    } else {
+      const IcpJob* dj = reinterpret_cast<const IcpJob*>(dev);
+      float* part = reinterpret_cast<float*>(dev + jb);
+      for (int it = 0; it < iterations; ++it) {
+        hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
+        hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+      }
+      if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
+    }
+    if (hipFreeAsync(dev, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
+  }
+  if (hipStreamSynchronize(hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
+  (void)hipHostFree(jobs);
+  return rs;
+}
+
 }  // namespace
 
 extern "C" dtsdf_status dtsdf_intensity(const uint8_t* rgb, int32_t width, int32_t height,
@@ -813,30 +849,49 @@ extern "C" dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* req
   if (n < 0 || (n > 0 && !reqs) || n > 65535 || iterations < 1 || iterations > 1000)
     return DTSDF_E_INVAL;
   if (n == 0) return DTSDF_OK;
-  std::vector<IcpJob> jobs((size_t)n);
+  IcpJob probe;
   for (int r = 0; r < n; ++r)
-    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params, reqs[r].pose,
-                  reqs[r].active, reqs[r].min_step, reqs[r].result, jobs[r]))
+    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params,
+                  reqs[r].pose, reqs[r].active, reqs[r].min_step, reqs[r].result, probe))
       return DTSDF_E_INVAL;
   hipStream_t hs = (hipStream_t)stream;
   const size_t jb = (sizeof(IcpJob) * n + 255) & ~(size_t)255;
-  const size_t bytes = jb + sizeof(float) * 2 * kChunks * kNSMax * (size_t)n;
-  uint8_t* dev = nullptr;
-  DTSDF_HIP(hipMallocAsync((void**)&dev, bytes, hs));
-  dtsdf_status rs = DTSDF_OK;
-  if (hipMemcpyAsync(dev, jobs.data(), sizeof(IcpJob) * n, hipMemcpyHostToDevice, hs) != hipSuccess) {
-    rs = DTSDF_E_HIP;
+  const size_t pb = sizeof(float) * 2 * kChunks * kNSMax * (size_t)n;
+  // descriptors through a staging slot (pinned host memory that outlives the copy); the
+  // partial sums in the slot's device block when they fit, else stream-ordered memory
+  Stage* sg = nullptr;
+  if (jb > kStageHostBytes) return icp_batch_large(n, reqs, iterations, hs);
+  dtsdf_status rs = stage_acquire(&sg);
+  if (rs != DTSDF_OK) return rs;
+  IcpJob* jobs = reinterpret_cast<IcpJob*>(sg->host);
+  for (int r = 0; r < n; ++r)
+    make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params,
+             reqs[r].pose, reqs[r].active, reqs[r].min_step, reqs[r].result, jobs[r]);
+  float* part = nullptr;
+  bool own_part = false;
+  if (jb + pb <= kStageDevBytes) {
+    part = reinterpret_cast<float*>(sg->dev + jb);
+  } else if (hipMallocAsync((void**)&part, pb, hs) == hipSuccess) {
+    own_part = true;
   } else {
-    const IcpJob* dj = reinterpret_cast<const IcpJob*>(dev);
-    float* part = reinterpret_cast<float*>(dev + jb);
-    // the descriptors hold device pointers to each request's pose and flag, so the same
-    // launches repeated continue from the poses the previous ones wrote
-    for (int it = 0; it < iterations; ++it) {
-      hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
-      hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
-    }
-    if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
+    rs = DTSDF_E_NOMEM;
   }
-  if (hipFreeAsync(dev, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
-  return rs;
+  if (rs == DTSDF_OK) {
+    if (hipMemcpyAsync(sg->dev, sg->host, sizeof(IcpJob) * n, hipMemcpyHostToDevice, hs) !=
+        hipSuccess) {
+      rs = DTSDF_E_HIP;
+    } else {
+      const IcpJob* dj = reinterpret_cast<const IcpJob*>(sg->dev);
+      // the descriptors hold device pointers to each request's pose and flag, so the same
+      // launches repeated continue from the poses the previous ones wrote
+      for (int it = 0; it < iterations; ++it) {
+        hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
+        hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+      }
+      if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
+    }
+  }
+  if (own_part && hipFreeAsync(part, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
+  const dtsdf_status rr = stage_release(sg, hs);
+  return rs != DTSDF_OK ? rs : rr;
 }

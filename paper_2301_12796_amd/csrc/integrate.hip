@@ -359,7 +359,22 @@ bool valid_intr(const dtsdf_intrinsics* i) {
 
 }  // namespace
 
+namespace {
+
+// The bricks-handed-out counter may overshoot the pool while a frame allocates; it is
+// brought back to the capacity on the device (no host word travels to the device).
+__global__ void clamp_handed_k(int32_t* counters, int32_t cap) {
+  if (threadIdx.x == 0 && counters[0] > cap) counters[0] = cap;
+}
+
+}  // namespace
+
 namespace dtsdf {
+
+void launch_clamp_handed(dtsdf_map* m, hipStream_t st) {
+  hipLaunchKernelGGL(clamp_handed_k, dim3(1), dim3(64), 0, st, m->counters,
+                     (int32_t)m->p.brick_capacity);
+}
 
 // Every caller runs launch_bbox next, which clamps the free-list count.
 void launch_assign(dtsdf_map* m, hipStream_t st) {
@@ -445,9 +460,8 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
     if (gs != DTSDF_OK) return gs;
     int64_t handed = c[0];
     if (handed > (int64_t)m->p.brick_capacity) {
-      int32_t cap = (int32_t)m->p.brick_capacity;
-      DTSDF_HIP(hipMemcpyAsync(m->counters, &cap, sizeof(cap), hipMemcpyHostToDevice, st));
-      handed = cap;
+      launch_clamp_handed(m, st);
+      handed = m->p.brick_capacity;
     }
     dropped_now = (int64_t)c[1] - m->dropped;
     m->dropped = c[1];

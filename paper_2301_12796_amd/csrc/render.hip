@@ -26,7 +26,7 @@
 //     surface.
 #include <algorithm>
 #include <cmath>
-#include <vector>
+#include <cstring>
 
 #include "dtsdf_internal.hpp"
 
@@ -502,9 +502,9 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
 // Directions per group of the march's evaluations (see eval_cell).
 constexpr int march_group(int) { return 1; }
 
-// Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step a
-// bisection, until the bracket is shorter than kRefineTol (metres along the ray) or after
-// kRefineMaxIter evaluations.
+// Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step and every
+// step after one that shrank the bracket by less than a tenth a bisection, until the bracket
+// is shorter than kRefineTol (metres along the ray) or after kRefineMaxIter evaluations.
 constexpr double kRefineTol = 1e-6;
 constexpr double kRefinePair = 0.45 * kRefineTol;
 constexpr int kRefineMaxIter = 24;
@@ -562,6 +562,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   double ta = 0.0, tb = 0.0;
   int k = 0;
   int it = 0, side = 0;
+  bool bisect = false;    // refinement: the next step is a bisection
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
   double te2 = 0.0;       // second point evaluated with it (refinement pair, or lattice k + 1)
@@ -577,7 +578,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
           break;
         }
         double q = 0.5;
-        if ((it & 3) != 3) q = (double)__fdividef(fa, fa - fb);
+        if ((it & 3) != 3 && !bisect) q = (double)__fdividef(fa, fa - fb);
         double tc = ta + (tb - ta) * q;
         if (!(tc > ta && tc < tb)) tc = 0.5 * (ta + tb);
         // the estimate is evaluated as a pair straddling it by kRefinePair: when the estimate
@@ -730,6 +731,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     if (refining) {
       if (TRACE) ++n_refine;
       ++it;
+      const double w0 = tb - ta;
       const bool pos1 = !e.defined || e.f > 0.f;
       const bool pos2 = !ev[1].defined || ev[1].f > 0.f;
       if (pos1 && pair && !pos2) {
@@ -750,6 +752,10 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
         if (side == -1) fa *= 0.5f;
         side = -1;
       }
+      // a false-position step that shrank the bracket by less than a tenth (one end keeps
+      // a value far from the root, e.g. behind a jump of f at a cell face) is followed by
+      // a bisection
+      bisect = (tb - ta) > 0.9 * w0;
       continue;
     }
     if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
@@ -942,26 +948,37 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
   const size_t off_prefix = 16;
   const size_t off_args = (off_prefix + sizeof(int32_t) * (n + 1) + 63) & ~(size_t)63;
   const size_t bytes = off_args + sizeof(RenderArgs) * n;
-  std::vector<uint8_t> host(bytes, 0);
-  int32_t* prefix = reinterpret_cast<int32_t*>(host.data() + off_prefix);
-  RenderArgs* args = reinterpret_cast<RenderArgs*>(host.data() + off_args);
+  static_assert((16 + 4 * 4097 + 63 + sizeof(RenderArgs) * 4096) <= kStageHostBytes,
+                "the largest batch fits one staging slot");
+  RenderArgs args1;
   int64_t total = 0;
   bool trace = false;
   for (int r = 0; r < n; ++r) {
     if (!fill_args(&reqs[r].intr, reqs[r].T_world_cam, reqs[r].z_near, reqs[r].z_far,
-                   &reqs[r].out, args[r]))
+                   &reqs[r].out, args1))
       return DTSDF_E_INVAL;
-    const RenderArgs& q = args[r];
-    trace = trace || q.trace_bricks || q.trace_color || q.trace_slots || q.trace_counts;
-    prefix[r] = (int32_t)total;
-    total += args[r].tiles;
+    trace = trace || args1.trace_bricks || args1.trace_color || args1.trace_slots ||
+            args1.trace_counts;
+    total += args1.tiles;
     if (total > (int64_t)1 << 30) return DTSDF_E_INVAL;
   }
+  Stage* sg = nullptr;
+  dtsdf_status rs = stage_acquire(&sg);
+  if (rs != DTSDF_OK) return rs;
+  uint8_t* host = sg->host;
+  std::memset(host, 0, off_args);
+  int32_t* prefix = reinterpret_cast<int32_t*>(host + off_prefix);
+  RenderArgs* args = reinterpret_cast<RenderArgs*>(host + off_args);
+  total = 0;
+  for (int r = 0; r < n; ++r) {
+    fill_args(&reqs[r].intr, reqs[r].T_world_cam, reqs[r].z_near, reqs[r].z_far, &reqs[r].out,
+              args[r]);
+    prefix[r] = (int32_t)total;
+    total += args[r].tiles;
+  }
   prefix[n] = (int32_t)total;
-  uint8_t* dev = nullptr;
-  DTSDF_HIP(hipMallocAsync((void**)&dev, bytes, st));
-  dtsdf_status rs = DTSDF_OK;
-  if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+  uint8_t* dev = sg->dev;
+  if (hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
     rs = DTSDF_E_HIP;
   } else {
     // persistent waves: three per SIMD (the kernel's occupancy), four SIMDs per CU
@@ -996,6 +1013,6 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
     }
     if (hipGetLastError() != hipSuccess) rs = DTSDF_E_HIP;
   }
-  if (hipFreeAsync(dev, st) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
-  return rs;
+  const dtsdf_status rr = stage_release(sg, st);
+  return rs != DTSDF_OK ? rs : rr;
 }

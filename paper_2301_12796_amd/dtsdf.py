@@ -167,6 +167,7 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 _lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), ctypes.c_int32, _V]
+
 _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                               ctypes.POINTER(_Photo), ctypes.c_int32,
                               ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
@@ -757,6 +758,16 @@ def icp_step_batch_structs(structs, stream=None) -> None:
 
 def icp_step_batch(requests, stream=None) -> None:
     icp_step_batch_structs([icp_request_struct(q) for q in requests], stream)
+
+
+def icp_step_batch_iters(requests, iterations: int, stream=None) -> None:
+    """`iterations` steps of icp_step_batch from one upload of the requests."""
+    structs = [icp_request_struct(q) for q in requests]
+    n = len(structs)
+    reqs = (_IcpReq * n)(*structs)
+    _check(_lib.icp_step_batch_iters(n, reqs, int(iterations), _stream(stream)),
+           "icp_step_batch_iters")
+
 
 
 def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:
