@@ -355,6 +355,19 @@ dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream);
 dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* reqs, int32_t iterations,
                                   void* stream);
 
+/* icp_step_batch_iters for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops and harnesses that forbid allocation.  Same arguments,
+ * semantics and results as icp_step_batch_iters, for at most DTSDF_NOALLOC_MAX_REQUESTS
+ * requests (more: DTSDF_E_INVAL).  The request descriptors reach the device as kernel
+ * arguments and the partial sums use a fixed device array of the library (under 1 MB per
+ * GPU, held until the process ends); the call allocates no host or device memory and keeps
+ * no pointer to `reqs`.  Every call on one GPU uses that same array: calls that overlap on
+ * one GPU (different streams, or host threads without ordering) race, so the caller
+ * serialises them on that GPU. */
+#define DTSDF_NOALLOC_MAX_REQUESTS 16
+dtsdf_status icp_step_batch_iters_noalloc(int32_t n, const dtsdf_icp_req* reqs,
+                                          int32_t iterations, void* stream);
+
 /* ---- View-dependent combined ("rendering") TSDF (Sec. 4) -------------------------------
  * For a fixed camera position the six directional TSDFs can be merged into one conflict-free
  * regular TSDF (Sec. 4, Lemma positional_unambiguity); ray casting that volume from (near)

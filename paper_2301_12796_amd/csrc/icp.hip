@@ -701,6 +701,51 @@ __global__ __launch_bounds__(256) void mean2x2_k(const float* __restrict__ in, i
   out[(size_t)v * Wo + u] = 0.25f * ((r0[0] + r0[1]) + (r1[0] + r1[1]));
 }
 
+// ---- allocation-free batched step -----------------------------------------------------
+// Requests of icp_step_batch_iters_noalloc: their descriptors and partial sums live in one
+// fixed device array of the library (each GPU holds its own copy until the process ends);
+// the descriptors reach it as kernel arguments, so no host or device memory is allocated and
+// no host buffer has to outlive the call.
+constexpr int kNoAllocMaxRequests = 16;
+constexpr size_t kNoAllocJobBytes = (sizeof(IcpJob) * kNoAllocMaxRequests + 255) & ~(size_t)255;
+constexpr size_t kNoAllocBytes =
+    kNoAllocJobBytes + sizeof(float) * 2 * kChunks * kNSMax * kNoAllocMaxRequests;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kJobsPerPut = 8;
+struct JobPack {
+  IcpJob job[kJobsPerPut];
+};
+static_assert(sizeof(JobPack) <= 3072, "a pack of descriptors fits the kernel arguments");
+static_assert(sizeof(IcpJob) % 4 == 0, "descriptors are copied as 32-bit words");
+
+// Writes `count` descriptors of the pack (a kernel argument) to dst.
+__global__ __launch_bounds__(256) void put_jobs_k(IcpJob* dst, JobPack pack, int count) {
+  const int words = count * (int)(sizeof(IcpJob) / 4);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&pack);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < words; i += blockDim.x) d[i] = src[i];
+}
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64] = {};
+
+// Device address of `scratch` on the current device, taken once per device (in host code
+// the array's name is not a device address).
+dtsdf_status noalloc_scratch(uint8_t** out) {
+  int dev = 0;
+  DTSDF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return DTSDF_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DTSDF_E_HIP;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = static_cast<uint8_t*>(g_noalloc_ptr[dev]);
+  return DTSDF_OK;
+}
+
 // Batches whose descriptors exceed a staging slot: a pinned block of their own, released
 // once the stream has run the batch (the call waits for it).
 dtsdf_status icp_batch_large(int32_t n, const dtsdf_icp_req* reqs, int32_t iterations,
@@ -894,4 +939,35 @@ extern "C" dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* req
   if (own_part && hipFreeAsync(part, hs) != hipSuccess && rs == DTSDF_OK) rs = DTSDF_E_HIP;
   const dtsdf_status rr = stage_release(sg, hs);
   return rs != DTSDF_OK ? rs : rr;
+}
+
+extern "C" dtsdf_status icp_step_batch_iters_noalloc(int32_t n, const dtsdf_icp_req* reqs,
+                                                     int32_t iterations, void* stream) {
+  if (n < 0 || (n > 0 && !reqs) || n > kNoAllocMaxRequests || iterations < 1 ||
+      iterations > 1000)
+    return DTSDF_E_INVAL;
+  if (n == 0) return DTSDF_OK;
+  JobPack packs[(kNoAllocMaxRequests + kJobsPerPut - 1) / kJobsPerPut];
+  for (int r = 0; r < n; ++r)
+    if (!make_job(&reqs[r].live, &reqs[r].model, reqs[r].photo, reqs[r].dim, &reqs[r].params,
+                  reqs[r].pose, reqs[r].active, reqs[r].min_step, reqs[r].result,
+                  packs[r / kJobsPerPut].job[r % kJobsPerPut]))
+      return DTSDF_E_INVAL;
+  uint8_t* base = nullptr;
+  const dtsdf_status s0 = noalloc_scratch(&base);
+  if (s0 != DTSDF_OK) return s0;
+  hipStream_t hs = (hipStream_t)stream;
+  IcpJob* dj = reinterpret_cast<IcpJob*>(base);
+  float* part = reinterpret_cast<float*>(base + kNoAllocJobBytes);
+  for (int b = 0; b < n; b += kJobsPerPut)
+    hipLaunchKernelGGL(put_jobs_k, dim3(1), dim3(256), 0, hs, dj + b, packs[b / kJobsPerPut],
+                       std::min(kJobsPerPut, n - b));
+  // every partial sum a solve reads is written by the reduce before it, so nothing of the
+  // previous call's contents is used
+  for (int it = 0; it < iterations; ++it) {
+    hipLaunchKernelGGL(reduce_batch_k, dim3(kChunks, n), dim3(kReduceThreads), 0, hs, dj, part);
+    hipLaunchKernelGGL(solve_batch_k, dim3(n), dim3(64), 0, hs, dj, part);
+  }
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
 }

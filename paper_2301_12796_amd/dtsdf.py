@@ -147,7 +147,7 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
             "dtsdf_integrate_normals", "icp_step_batch_iters",
-            "dtsdf_status_string"]
+            "icp_step_batch_iters_noalloc", "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
 _lib.dtsdf_status_string.argtypes = [ctypes.c_int]
@@ -167,7 +167,9 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 _lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), ctypes.c_int32, _V]
-
+_lib.icp_step_batch_iters_noalloc.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq),
+                                              ctypes.c_int32, _V]
+NOALLOC_MAX_REQUESTS = 16
 _lib.icp_step_rgb.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image),
                               ctypes.POINTER(_Photo), ctypes.c_int32,
                               ctypes.POINTER(_IcpParams), _D16, ctypes.POINTER(_IcpResult), _V]
@@ -768,6 +770,15 @@ def icp_step_batch_iters(requests, iterations: int, stream=None) -> None:
     _check(_lib.icp_step_batch_iters(n, reqs, int(iterations), _stream(stream)),
            "icp_step_batch_iters")
 
+
+def icp_step_batch_iters_noalloc(requests, iterations: int, stream=None) -> None:
+    """icp_step_batch_iters without any allocation (at most NOALLOC_MAX_REQUESTS requests;
+    calls on one GPU must not overlap)."""
+    structs = [icp_request_struct(q) for q in requests]
+    n = len(structs)
+    reqs = (_IcpReq * max(n, 1))(*structs)
+    _check(_lib.icp_step_batch_iters_noalloc(n, reqs, int(iterations), _stream(stream)),
+           "icp_step_batch_iters_noalloc")
 
 
 def decode_result(raw: torch.Tensor, dim: int = 7) -> dict:
