@@ -500,6 +500,9 @@ void orc_integrate(void* h, const float* depth, const uint8_t* rgb, int W, int H
         double dist = std::sqrt((pw[0] - x[0]) * (pw[0] - x[0]) + (pw[1] - x[1]) * (pw[1] - x[1]) +
                                 (pw[2] - x[2]) * (pw[2] - x[2]));
         double wc = wd * (1.0 - std::min(1.0, dist / p.tau));  // eq. color_weight
+        // the colour weight vanishes at |p - x| = tau; within 1e-6 of it a float32
+        // implementation may round it to zero (no colour update) or keep a tiny weight
+        if (std::fabs(1.0 - dist / p.tau) < 1e-6) bl = true;
         if (wc > 0.0) {
           for (int c = 0; c < 3; ++c) {
             double val = ((double)B.rgb[l][c] * B.wc[l] + (double)rgb[3 * pi + c] * wc) /
@@ -801,6 +804,58 @@ double face_distance(const Map& m, const double x[3]) {
   return best;
 }
 
+// Shading outputs of a sample on the ray r (Sec. 4): the normal, normalised weighted sum of
+// the per-direction gradient normals, or of the axis vectors on the fallback branch (the
+// paper does not specify it), world frame, has_n false where the weights sum to zero; the
+// colour, per direction the trilinear colour over corners with w_c > 0, blended with
+// w_dir(n^D) max(0, <n^D, -r>) W_c^D(x), and where those sum to zero with the geometric
+// combination weights (the paper does not specify how colours are combined), unrounded,
+// has_c false where no weight is positive.
+struct Shade {
+  double n[3], rgb[3];
+  bool has_n, has_c;
+};
+
+Shade shade(const Params& p, const Sample& S, const double r[3]) {
+  Shade o{{0, 0, 0}, {0, 0, 0}, false, false};
+  double nw[3] = {0, 0, 0};
+  for (int d = 0; d < 6; ++d) {
+    const DirSample& ds = S.dir[d];
+    if (!ds.defined || ds.omega <= 0) continue;
+    for (int k = 0; k < 3; ++k) nw[k] += ds.omega * (S.fallback ? kAxis[d][k] : ds.n[k]);
+  }
+  const double nl = std::sqrt(dot3(nw, nw));
+  if (nl > 0) {
+    o.has_n = true;
+    for (int k = 0; k < 3; ++k) o.n[k] = nw[k] / nl;
+  }
+  if (!p.with_color) return o;
+  double so = 0, sc[3] = {0, 0, 0};
+  const double mr[3] = {-r[0], -r[1], -r[2]};
+  for (int d = 0; d < 6; ++d) {
+    const DirSample& ds = S.dir[d];
+    if (!ds.defined || !ds.color_ok || !ds.grad_ok || S.fallback) continue;
+    const double oc = w_dir(p, ds.n, d) * std::max(0.0, dot3(ds.n, mr)) * ds.Wc;
+    so += oc;
+    for (int ch = 0; ch < 3; ++ch) sc[ch] += oc * ds.rgb[ch];
+  }
+  if (!(so > 0)) {
+    so = 0;
+    sc[0] = sc[1] = sc[2] = 0;
+    for (int d = 0; d < 6; ++d) {
+      const DirSample& ds = S.dir[d];
+      if (!ds.defined || !ds.color_ok) continue;
+      so += ds.omega;
+      for (int ch = 0; ch < 3; ++ch) sc[ch] += ds.omega * ds.rgb[ch];
+    }
+  }
+  if (so > 0) {
+    o.has_c = true;
+    for (int ch = 0; ch < 3; ++ch) o.rgb[ch] = sc[ch] / so;
+  }
+  return o;
+}
+
 }  // namespace
 
 extern "C" {
@@ -819,12 +874,22 @@ enum {
   kRootFace = 16,     // the root lies inside a cell but within eps_root metres of one of its
                       // faces: a refinement with that tolerance may take the outputs from
                       // the neighbouring cell (normal, colour)
+  kRootBranch = 32,   // where normal and colour are taken, the combination switches branch
+                      // (gradient weights or fallback) or definedness when the thresholded
+                      // factors move by +/- eps_s, or within eps_root metres along the ray
+  kRootShade = 64,    // the shading outputs are not fixed at the resolution eps_root of the
+                      // root: eps_root metres beyond it along the ray the normal has turned by
+                      // more than eps_n, a colour channel has moved by more than eps_c or the
+                      // colour appears or vanishes (combination weights near zero change
+                      // their ratio that fast)
 };
 
 struct OrcRenderCfg {
   double z_near, z_far;
   double eps_f, eps_x, eps_s, eps_root;
   int32_t classify;   // 0: skip the grazing classification (plain render)
+  double eps_n;       // radians
+  double eps_c;       // colour levels (0 .. 255)
 };
 
 // Renders pixels (us[i], vs[i]) of a camera with intrinsics (fx, fy, cx, cy) and pose T
@@ -914,11 +979,26 @@ void orc_render(void* h, int64_t n, const int32_t* us, const int32_t* vs, double
         // points counting as free space as in the refinement below (an undefined stretch
         // between the positive and the negative end leaves the root unique)
         if (cfg->classify) {
+          // 64 even steps, plus both sides of every cell face the bracket crosses (f may
+          // jump there, and a jump can open a stretch of the other sign narrower than the
+          // steps)
+          std::vector<double> tt;
+          for (int j = 0; j <= 64; ++j) tt.push_back(ta + (tb - ta) * j / 64.0);
+          for (int k = 0; k < 3; ++k) {
+            if (r[k] == 0.0) continue;
+            const double xa_ = (c0[k] + ta * r[k]) / p.voxel, xb_ = (c0[k] + tb * r[k]) / p.voxel;
+            for (double fc = std::ceil(std::min(xa_, xb_)); fc <= std::max(xa_, xb_); fc += 1.0) {
+              const double tf = (fc * p.voxel - c0[k]) / r[k];
+              for (double dlt : {-1e-9, 1e-9})
+                if (tf + dlt > ta && tf + dlt < tb) tt.push_back(tf + dlt);
+            }
+          }
+          std::sort(tt.begin(), tt.end());
           int changes = 0;
           bool lastpos = true;
-          for (int j = 0; j <= 64; ++j) {
+          for (size_t j = 0; j < tt.size(); ++j) {
             bool def;
-            double fv = f_at(ta + (tb - ta) * j / 64.0, &def);
+            double fv = f_at(tt[j], &def);
             bool pos = !def || fv > 0;
             if (j > 0 && pos != lastpos) changes++;
             lastpos = pos;
@@ -942,7 +1022,29 @@ void orc_render(void* h, int64_t n, const int32_t* us, const int32_t* vs, double
         // defined): where f jumps across a cell face this is the cell beyond the face
         double xs[3] = {c0[0] + b * r[0], c0[1] + b * r[1], c0[2] + b * r[2]};
         Sample S = eval(m, xs, r, tl);
+        const Shade sh = shade(p, S, r);
         if (cfg->classify) {
+          // a refinement to eps_root ends inside the surface, between the root and eps_root
+          // beyond it
+          {
+            const double y[3] = {xs[0] + cfg->eps_root * r[0], xs[1] + cfg->eps_root * r[1],
+                                 xs[2] + cfg->eps_root * r[2]};
+            const Shade sy = shade(p, eval(m, y, r, nullptr), r);
+            bool moved = sy.has_n != sh.has_n || sy.has_c != sh.has_c;
+            if (sy.has_n && sh.has_n)
+              moved |= std::acos(std::min(1.0, dot3(sy.n, sh.n))) > cfg->eps_n;
+            if (sy.has_c && sh.has_c)
+              for (int ch = 0; ch < 3; ++ch) moved |= std::fabs(sy.rgb[ch] - sh.rgb[ch]) > cfg->eps_c;
+            if (moved) fl |= kRootShade;
+          }
+          const Sample lo = eval(m, xs, r, nullptr, -cfg->eps_s);
+          const Sample hi = eval(m, xs, r, nullptr, cfg->eps_s);
+          const double xf[3] = {xs[0] + cfg->eps_root * r[0], xs[1] + cfg->eps_root * r[1],
+                                xs[2] + cfg->eps_root * r[2]};
+          const Sample Sf = eval(m, xf, r, nullptr);
+          if (lo.defined != hi.defined || lo.fallback != hi.fallback ||
+              Sf.defined != S.defined || Sf.fallback != S.fallback)
+            fl |= kRootBranch;
           double xa[3] = {c0[0] + a * r[0], c0[1] + a * r[1], c0[2] + a * r[2]};
           bool same_cell = true;
           for (int k = 0; k < 3; ++k)
@@ -961,49 +1063,13 @@ void orc_render(void* h, int64_t n, const int32_t* us, const int32_t* vs, double
         }
         out_depth = ts * rc[2];
         for (int k = 0; k < 3; ++k) out_v[k] = ts * rc[k];
-        // output normal: normalised weighted sum of the per-direction gradient normals, or of
-        // the axis vectors on the fallback branch (the paper does not specify it)
-        double nw[3] = {0, 0, 0};
-        for (int d = 0; d < 6; ++d) {
-          const DirSample& ds = S.dir[d];
-          if (!ds.defined || ds.omega <= 0) continue;
-          for (int k = 0; k < 3; ++k)
-            nw[k] += ds.omega * (S.fallback ? kAxis[d][k] : ds.n[k]);
-        }
-        double nl = std::sqrt(dot3(nw, nw));
-        if (nl > 0)
+        if (sh.has_n)
           for (int k = 0; k < 3; ++k)  // world -> camera: R^T n
-            out_n[k] = (R[k] * nw[0] + R[3 + k] * nw[1] + R[6 + k] * nw[2]) / nl;
-        // colour: per direction trilinear colour over corners with w_c > 0, blended with
-        // w_dir(n^D) max(0, <n^D, -r>) W_c^D(x); if those sum to zero, with the geometric
-        // combination weights; the paper does not specify how colours are combined.
-        if (p.with_color) {
-          double so = 0, sc[3] = {0, 0, 0};
-          double mr[3] = {-r[0], -r[1], -r[2]};
-          for (int d = 0; d < 6; ++d) {
-            const DirSample& ds = S.dir[d];
-            if (!ds.defined || !ds.color_ok || !ds.grad_ok || S.fallback) continue;
-            double oc = w_dir(p, ds.n, d) * std::max(0.0, dot3(ds.n, mr)) * ds.Wc;
-            so += oc;
-            for (int ch = 0; ch < 3; ++ch) sc[ch] += oc * ds.rgb[ch];
-          }
-          if (!(so > 0)) {
-            so = 0;
-            sc[0] = sc[1] = sc[2] = 0;
-            for (int d = 0; d < 6; ++d) {
-              const DirSample& ds = S.dir[d];
-              if (!ds.defined || !ds.color_ok) continue;
-              so += ds.omega;
-              for (int ch = 0; ch < 3; ++ch) sc[ch] += ds.omega * ds.rgb[ch];
-            }
-          }
-          if (so > 0) {
-            for (int ch = 0; ch < 3; ++ch) {
-              double val = std::nearbyint(sc[ch] / so);
-              out_c[ch] = (uint8_t)std::min(255.0, std::max(0.0, val));
-            }
-            out_c[3] = 255;
-          }
+            out_n[k] = R[k] * sh.n[0] + R[3 + k] * sh.n[1] + R[6 + k] * sh.n[2];
+        if (sh.has_c) {
+          for (int ch = 0; ch < 3; ++ch)
+            out_c[ch] = (uint8_t)std::min(255.0, std::max(0.0, std::nearbyint(sh.rgb[ch])));
+          out_c[3] = 255;
         }
       }
       if (depth) depth[i] = out_depth;
@@ -1037,6 +1103,22 @@ void orc_eval(void* h, int64_t n, const double* xs, const double* rs, double* f,
     f[i] = S.f;
     def[i] = S.defined;
     fallback[i] = S.fallback;
+  }
+}
+
+// Shading outputs (see shade) at world points xs (n, 3) for unit rays rs (n, 3): world-frame
+// unit normal (zero where none), unrounded colour, and bit 0 / bit 1 of `has` for the normal
+// / colour being present.
+void orc_shade(void* h, int64_t n, const double* xs, const double* rs, double* normal,
+               double* rgb, uint8_t* has) {
+  const Map& m = *static_cast<Map*>(h);
+  for (int64_t i = 0; i < n; ++i) {
+    const Shade o = shade(m.p, eval(m, xs + 3 * i, rs + 3 * i, nullptr), rs + 3 * i);
+    for (int k = 0; k < 3; ++k) {
+      normal[3 * i + k] = o.n[k];
+      rgb[3 * i + k] = o.rgb[k];
+    }
+    has[i] = (o.has_n ? 1 : 0) | (o.has_c ? 2 : 0);
   }
 }
 

@@ -84,7 +84,8 @@ class _RenderCfg(ctypes.Structure):
     _fields_ = [("z_near", ctypes.c_double), ("z_far", ctypes.c_double),
                 ("eps_f", ctypes.c_double), ("eps_x", ctypes.c_double),
                 ("eps_s", ctypes.c_double), ("eps_root", ctypes.c_double),
-                ("classify", ctypes.c_int32)]
+                ("classify", ctypes.c_int32), ("eps_n", ctypes.c_double),
+                ("eps_c", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -112,6 +113,7 @@ def _declare(L):
                              ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(_RenderCfg),
                              _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_eval.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
+    L.orc_shade.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _P]
     L.orc_brick_key.argtypes = [_P, ctypes.c_int64, _P]
     L.orc_combine.argtypes = [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -193,7 +195,8 @@ class RenderOut:
 
 
 # Grazing flag bits returned by render()
-NEAR_ZERO, NEAR_FACE, BRANCH, AMBIGUOUS, ROOT_FACE = 1, 2, 4, 8, 16
+NEAR_ZERO, NEAR_FACE, BRANCH, AMBIGUOUS, ROOT_FACE, ROOT_BRANCH, ROOT_SHADE = \
+    1, 2, 4, 8, 16, 32, 64
 
 
 class OracleMap:
@@ -272,12 +275,15 @@ class OracleMap:
     def render(self, cam, T_wc: np.ndarray, *, pixels: Optional[np.ndarray] = None,
                z_near: float = 0.2, z_far: float = 10.0, eps_f: float = 1e-5,
                eps_x: float = 1e-6, eps_s: float = 1e-5, eps_root: float = 2e-6,
+               eps_n_deg: float = 0.25, eps_c: float = 0.5,
                classify: bool = True, touched: bool = False) -> RenderOut:
         """Render all pixels (or the (n,2) array of (u, v) ``pixels``).
 
         With ``classify`` the grazing flags are computed (eps_f: |f| near zero; eps_x: voxel
         distance to a cell face; eps_s: margin on thresholded weight factors; eps_root: metres
-        between the root and a cell face); without it only the plain render runs."""
+        along the ray within which the root is taken as known; eps_n_deg, eps_c: the turn of
+        the normal and the change of a colour channel within eps_root of the root above which
+        the shading counts as not fixed by it); without it only the plain render runs."""
         if pixels is None:
             vv, uu = np.mgrid[0:cam.height, 0:cam.width]
             pixels = np.stack([uu.ravel(), vv.ravel()], axis=1)
@@ -291,7 +297,8 @@ class OracleMap:
                       thit=np.zeros(n))
         if touched:
             o.touched = np.zeros(self.num_bricks, np.uint8)
-        cfg = _RenderCfg(f32(z_near), f32(z_far), eps_f, eps_x, eps_s, eps_root, int(classify))
+        cfg = _RenderCfg(f32(z_near), f32(z_far), eps_f, eps_x, eps_s, eps_root, int(classify),
+                         math.radians(eps_n_deg), eps_c)
         T = np.ascontiguousarray(T_wc, np.float64)
         lib().orc_render(self._h, n, _ptr(us), _ptr(vs), cam.fx, cam.fy, cam.cx, cam.cy,
                          _ptr(T), ctypes.byref(cfg), _ptr(o.depth), _ptr(o.vertex),
@@ -309,6 +316,16 @@ class OracleMap:
         fb = np.zeros(n, np.uint8)
         lib().orc_eval(self._h, n, _ptr(xs), _ptr(rs), _ptr(f), _ptr(d), _ptr(fb))
         return f, d.astype(bool), fb.astype(bool)
+
+    def shade(self, xs: np.ndarray, rs: np.ndarray):
+        """Shading outputs at world points xs (n,3) for unit rays rs (n,3): world-frame unit
+        normal (n,3), unrounded colour (n,3), normal present (n,), colour present (n,)."""
+        xs = np.ascontiguousarray(xs, np.float64)
+        rs = np.ascontiguousarray(np.broadcast_to(rs, xs.shape), np.float64)
+        n = xs.shape[0]
+        nrm, rgb, has = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n, np.uint8)
+        lib().orc_shade(self._h, n, _ptr(xs), _ptr(rs), _ptr(nrm), _ptr(rgb), _ptr(has))
+        return nrm, rgb, (has & 1) != 0, (has & 2) != 0
 
     def combine(self, src: "OracleMap", cam, T_center: np.ndarray,
                 T_frustum: Optional[np.ndarray] = None, margin: float = 0.125,

@@ -49,6 +49,7 @@ class Request:
     error: float = math.nan        # residual sum of squares of the last ICP step
     inliers: int = 0               # correspondences of the last ICP step
     H: Optional[np.ndarray] = None # normal matrix of the last ICP step (server only)
+    slot: int = -1                 # slot that served it (server only)
 
 
 @dataclasses.dataclass
@@ -197,7 +198,7 @@ class Server:
             # admission: arrived requests, free slot, memory budget
             new_views = []
             t = now()
-            for s in self._slots:
+            for si, s in enumerate(self._slots):
                 if not queue or (realtime and queue[0].arrival > t):
                     break
                 if s.req is not None:
@@ -208,6 +209,7 @@ class Server:
                     break
                 req = queue.popleft()
                 req.admitted = t
+                req.slot = si
                 s.req, s.level, s.it, s.need = req, self.L - 1, 0, need
                 self.in_use += need
                 self.peak_bytes = max(self.peak_bytes, self.in_use)

@@ -119,7 +119,7 @@ int main() {
   std::vector<double> dep(n), vert(3 * n), nrm(3 * n), thit(n);
   std::vector<uint8_t> rgba(4 * n), mask(n), flags(n), touched((size_t)orc_num_bricks(h));
   std::vector<int64_t> khit(n);
-  OrcRenderCfg cfg{0.2, 3.0, 1e-5, 1e-6, 1e-5, 2e-6, 1};
+  OrcRenderCfg cfg{0.2, 3.0, 1e-5, 1e-6, 1e-5, 2e-6, 1, 0.25 * 3.141592653589793 / 180.0, 0.5};
   orc_render(h, n, us.data(), vs.data(), f, f, cx, cy, T, &cfg, dep.data(), vert.data(),
              nrm.data(), rgba.data(), mask.data(), flags.data(), khit.data(), thit.data(),
              touched.data());

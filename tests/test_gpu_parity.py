@@ -49,7 +49,7 @@ def test_render_tiny_identical_map(dtsdf, tiny_oracle):
     print("case: tiny render phi=0.3, 160x120", flush=True)
     out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
     ref = ref_map.render(P.TINY_CAM, T, z_far=2.5)
-    st = P.compare_render(out, ref, name="tiny")
+    st = P.compare_render(out, ref, name="tiny", roots=(ref_map, P.TINY_CAM, T))
     assert st["compared"] > 5000
 
 
@@ -65,7 +65,7 @@ def test_render_tiny_other_views(dtsdf, tiny_oracle, phi):
     print(f"case: tiny render phi={phi}", flush=True)
     out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
     ref = ref_map.render(P.TINY_CAM, T, z_far=2.5)
-    P.compare_render(out, ref, name=f"tiny phi={phi}")
+    P.compare_render(out, ref, name=f"tiny phi={phi}", roots=(ref_map, P.TINY_CAM, T))
 
 
 def test_render_is_bitwise_deterministic(dtsdf, tiny_oracle):
@@ -101,7 +101,7 @@ def test_end_to_end_tiny(dtsdf, tiny_oracle):
     T = synth.tiny_render_pose()
     out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
     ref = om.render(P.TINY_CAM, T, z_far=2.5)
-    st = P.compare_render(out, ref, name="tiny end-to-end")
+    st = P.compare_render(out, ref, name="tiny end-to-end", roots=(om, P.TINY_CAM, T))
     assert st["compared"] > 5000
 
 
@@ -157,8 +157,67 @@ def test_render_room_full_size_sampled(dtsdf, room_oracle):
         rows = np.stack(np.meshgrid(np.arange(640), [100, 333]), -1).reshape(-1, 2)
         pix = np.concatenate([pix, rows])
         ref = ref_map.render(P.ROOM_CAM, T, pixels=pix)
-        st = P.compare_render(out, ref, pixels=pix, name=f"room pose {k}")
+        st = P.compare_render(out, ref, pixels=pix, name=f"room pose {k}",
+                              roots=(ref_map, P.ROOM_CAM, T))
         assert st["hits"] > 500
+
+
+ROOM30 = list(range(100, 130))     # 30 consecutive frames of the room trajectory
+
+
+@pytest.fixture(scope="module")
+def room30():
+    """Room map fused by the oracle from 30 consecutive 640x480 frames (weights accumulate,
+    reach the cap region of the band and carving repeats), and the frames."""
+    sc = synth.room_scene()
+    frames = synth.room_frames(ROOM30, scene=sc)
+    m = O.OracleMap(P.room_oracle_params())
+    for f in frames:
+        m.integrate(f["depth"], f["rgb"], P.ROOM_CAM, f["T_wc"])
+    return m, frames
+
+
+def test_integrate_room_30_frames_voxelwise(dtsdf, room30):
+    om, frames = room30
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf))
+    print(f"case: room integrate {len(frames)} consecutive frames 640x480", flush=True)
+    for f in frames:
+        st = gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.ROOM_CAM, f["T_wc"], stats=True)
+        assert st["dropped"] == 0
+    gb, ob = gm.export(), om.export()
+    st = P.compare_maps(gb, ob, n_frames=len(frames), name="room 30 frames")
+    assert st["ok"], st
+    # allocation differs only where a block or direction decision sits on its threshold
+    n = len(ob["keys"])
+    assert st["only_gpu"] <= 1e-3 * n and st["only_oracle"] <= 1e-3 * n, st
+
+
+def test_render_room_30_frames_sampled(dtsdf, room30):
+    """640x480 renders of the 30-frame map (imported) at five of its poses: 20,000 sampled
+    pixels plus two full rows per pose, with depth, vertex, normal and colour."""
+    om, _ = room30
+    blob = om.export()
+    gm = dtsdf.Map(P.room_gpu_params(dtsdf))
+    gm.load(blob)
+    ref_map = O.OracleMap(P.room_oracle_params())
+    ref_map.load(blob)                               # the oracle renders the same float32 map
+    total = dict(n=0, flagged=0, flagged_mask=0, ambiguous=0, compared=0)
+    for k in (100, 107, 114, 121, 128):
+        T = synth.room_pose(k)
+        print(f"case: room 30-frame render pose {k}", flush=True)
+        out = P.to_numpy_out(gm.render(P.ROOM_CAM, T, outputs=("depth", "vertex", "normal",
+                                                                 "rgba", "mask")))
+        pix = P.random_pixels(P.ROOM_CAM, 20000, seed=k)
+        rows = np.stack(np.meshgrid(np.arange(640), [150, 400]), -1).reshape(-1, 2)
+        pix = np.concatenate([pix, rows])
+        ref = ref_map.render(P.ROOM_CAM, T, pixels=pix)
+        st = P.compare_render(out, ref, pixels=pix, name=f"room30 pose {k}",
+                              roots=(ref_map, P.ROOM_CAM, T))
+        assert st["hits"] > 15000
+        for key in total:
+            total[key] += st[key]
+    print(f"[room30 render] {total}, flagged share {total['flagged'] / total['n']:.4f}",
+          flush=True)
 
 
 def test_empty_map_renders_nothing(dtsdf):

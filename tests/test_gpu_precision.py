@@ -79,7 +79,8 @@ def test_precision_render_identical_map(dtsdf, fmt, name):
         T = synth.tiny_render_pose(phi)
         out = P.to_numpy_out(gm.render(P.TINY_CAM, T, z_far=2.5))
         ref = ref_map.render(P.TINY_CAM, T, z_far=2.5)
-        P.compare_render(out, ref, name=f"precision {name} phi={phi}")
+        P.compare_render(out, ref, name=f"precision {name} phi={phi}",
+                         roots=(ref_map, P.TINY_CAM, T))
 
 
 @pytest.mark.parametrize("fmt,name", FORMATS)

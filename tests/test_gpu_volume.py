@@ -159,7 +159,8 @@ def test_render_volume_tiny_identical(dtsdf, tiny_blobs):
         rr.load(rb)
         print(f"case: tiny volume render phi={phi}", flush=True)
         out = P.to_numpy_out(vol.render(P.TINY_CAM, T, z_far=2.5))
-        st = P.compare_render(out, rr.render(P.TINY_CAM, T, z_far=2.5), name=f"volume phi={phi}")
+        st = P.compare_render(out, rr.render(P.TINY_CAM, T, z_far=2.5), name=f"volume phi={phi}",
+                              roots=(rr, P.TINY_CAM, T))
         assert st["compared"] > 3000
 
 
@@ -184,7 +185,7 @@ def test_render_volume_room_sampled(dtsdf, room_blob):
     rows = np.stack(np.meshgrid(np.arange(640), [100, 333]), -1).reshape(-1, 2)
     pix = np.concatenate([pix, rows])
     st = P.compare_render(out, rr.render(P.ROOM_CAM, T, pixels=pix), pixels=pix,
-                          name="room volume")
+                          name="room volume", roots=(rr, P.ROOM_CAM, T))
     assert st["hits"] > 1000
 
 
@@ -213,7 +214,7 @@ def test_combine_and_render_room(dtsdf, room_blob):
     rows = np.stack(np.meshgrid(np.arange(640), [100, 333]), -1).reshape(-1, 2)
     pix = np.concatenate([pix, rows])
     st = P.compare_render(out, rr.render(P.ROOM_CAM, T, pixels=pix), pixels=pix,
-                          name="room volume")
+                          name="room volume", roots=(rr, P.ROOM_CAM, T))
     assert st["hits"] > 1000
 
 
