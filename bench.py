@@ -42,10 +42,16 @@ if ROOT not in sys.path:
 
 METRIC = "DTSDF render rays/s at 640x480 (% HBM roofline); served p50/p99 render+ICP ms"
 HBM_PEAK_GBS = 8000.0
+# vector issue: each CU's four SIMDs have 16 lanes, so a wave64 VALU instruction occupies
+# its SIMD for 4 cycles: 256 CUs x 4 SIMDs / 4 cycles x 2.4 GHz wave instructions per second
+# (x 64 lanes x 2 flops per FMA x 2 for packed fp32 = the 157.3 TFLOP/s fp32 vector peak)
+VALU_ISSUE_PEAK = 256 * 2.4e9
 OUT_BYTES_PER_RAY = 4 + 12 + 4 + 1          # depth + normal + rgba + mask
 BRICK_MARCH_BYTES = 512 * 8                 # (sdf, w) float32 per voxel
 BRICK_COLOR_BYTES = 512 * 8                 # rgb code + colour weight per voxel
-BUCKET_BYTES = 32
+# per block a ray enters: its grid record (six brick indices, info word, hash slot: 32 B),
+# its positive-cell words (64 B) and its direction-group bytes (64 B)
+RECORD_BYTES = 32 + 64 + 64
 
 
 def log(msg):
@@ -56,10 +62,10 @@ def source_hash(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(kernel_src):
-    """HBM traffic per launch from the committed rocprofv3 summary, if it was taken on the
-    current kernel source."""
-    p = os.path.join(ROOT, "profiles", "render_room_640x480_traffic.txt")
+def read_profile(name, kernel_src):
+    """The `key = value` lines of a committed rocprofv3 summary under profiles/, if it was
+    taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     kv = {}
@@ -69,10 +75,36 @@ def read_traffic(kernel_src):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != source_hash(kernel_src):
         return None
+    return kv
+
+
+def read_float(kv, key):
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key]) if kv is not None else None
     except (KeyError, ValueError):
         return None
+
+
+def roofline_block(achieved, traffic, valu_per_launch, valu_frac, mean_launch_s, ctr):
+    """Roofline of the render kernel on two axes: HBM (algorithmic bytes per launch over the
+    launch time, against 8 TB/s) and vector issue (VALU wave instructions per launch, from
+    the committed counter summary of the same source, over the launch time, against
+    VALU_ISSUE_PEAK).  `bound` names the axis with the larger fraction, whose figures fill
+    achieved / peak / unit / frac; both are given under `hbm` and `alu`."""
+    hbm = dict(achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS)
+    alu = None
+    if valu_frac is not None:
+        alu = dict(achieved=valu_per_launch / mean_launch_s / 1e9, peak=VALU_ISSUE_PEAK / 1e9,
+                   unit="G VALU wave-instructions/s", frac=valu_frac)
+    bound = "alu" if alu is not None and alu["frac"] > hbm["frac"] else "hbm"
+    top = alu if bound == "alu" else hbm
+    return dict(bound=bound, achieved=top["achieved"], peak=top["peak"], unit=top["unit"],
+                frac=top["frac"], traffic=traffic, hbm=hbm, alu=alu,
+                valu_insts_per_launch=valu_per_launch,
+                salu_insts_per_launch=read_float(ctr, "salu_insts_per_launch"),
+                l2_hit_rate=read_float(ctr, "l2_hit_rate"),
+                traffic_over_algorithmic=(traffic / (achieved * mean_launch_s * 1e9)
+                                          if traffic is not None else None))
 
 
 def main():
@@ -92,7 +124,7 @@ def main():
                     help="skip fusing the frames a second time through the preprocessing")
     ap.add_argument("--batch", type=int, default=32,
                     help="views per launch of the batched render block (1: skip it)")
-    ap.add_argument("--serve-requests", type=int, default=600,
+    ap.add_argument("--serve-requests", type=int, default=3600,
                     help="leading requests of the 120/s Poisson stream that are served")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -122,6 +154,7 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     integ_ms = 0.0
     frames_dev = []          # kept for the precision-form maps
+    fuse_counts = []         # per frame: bricks visited, voxels updated, colours updated
     for k in range(n):
         t = time.time()
         f = synth.scenes.render_frame(sc, cam, synth.room_pose(k, n), noise="quadratic",
@@ -131,14 +164,40 @@ def main():
         frames_dev.append((depth, rgb))
         t_gen += time.time() - t
         ev0.record(stream)
-        gm.integrate(depth, rgb, cam, synth.room_pose(k, n))
+        ist = gm.integrate(depth, rgb, cam, synth.room_pose(k, n), stats=True)
         ev1.record(stream)
         ev1.synchronize()
         integ_ms += ev0.elapsed_time(ev1)
+        fuse_counts.append((ist["visited_bricks"], ist["updated_voxels"], ist["color_voxels"]))
         if k % 50 == 0:
             log(f"fused frame {k}/{n}: {gm.info()['bricks']} bricks")
     info = gm.info()
     log(f"map: {info['bricks']} bricks, {info['blocks']} blocks, dropped {info['dropped']}")
+    # fusion roofline: per updated voxel (sdf, w) read and written (16 B), per updated colour
+    # (rgb code, colour weight) read and written (16 B), per visited brick its key (16 B),
+    # per pixel the frame's depth, normal, colour and carving flag (20 B)
+    fc = np.array(fuse_counts, np.float64)
+    fuse_bytes = (fc[:, 1] * 16 + fc[:, 2] * 16 + fc[:, 0] * 16).mean() + \
+        cam.width * cam.height * 20
+    fuse_prof = read_profile("integrate_room_640x480_stats.txt",
+                             os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "integrate.hip"))
+    fuse_k_us = read_float(fuse_prof, "fuse_k_average_us")
+    fusion = dict(visited_bricks_per_frame=float(fc[:, 0].mean()),
+                  updated_voxels_per_frame=float(fc[:, 1].mean()),
+                  color_voxels_per_frame=float(fc[:, 2].mean()),
+                  algorithmic_bytes_per_frame=float(fuse_bytes),
+                  integrate_ms_per_frame=integ_ms / n,
+                  achieved_gbs_whole_frame=float(fuse_bytes / (integ_ms / n * 1e-3) / 1e9),
+                  fuse_k_average_us=fuse_k_us,
+                  achieved_gbs_fuse_k=(float(fuse_bytes / (fuse_k_us * 1e-6) / 1e9)
+                                       if fuse_k_us else None),
+                  peak=HBM_PEAK_GBS, unit="GB/s")
+    fusion["frac_whole_frame"] = fusion["achieved_gbs_whole_frame"] / HBM_PEAK_GBS
+    fusion["frac_fuse_k"] = (fusion["achieved_gbs_fuse_k"] / HBM_PEAK_GBS
+                             if fusion["achieved_gbs_fuse_k"] else None)
+    log(f"fusion: {fc[:, 1].mean():.0f} voxels updated per frame ({fc[:, 0].mean():.0f} bricks "
+        f"visited), {fuse_bytes / 1e6:.1f} MB algorithmic, {fusion['achieved_gbs_whole_frame']:.0f}"
+        f" GB/s over the whole integrate call")
 
     poses = [synth.room_pose(k, n) for k in range(n)]
     H, W = cam.height, cam.width
@@ -170,9 +229,9 @@ def main():
         c = tcnt.view(H // 8, 8, W // 8, 8, 4).permute(0, 2, 1, 3, 4).reshape(-1, 64, 4).float()
         counts.append(torch.stack([c.mean((0, 1)), c.amax(1).mean(0)]).cpu().numpy())
         bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +
-                              ns * BUCKET_BYTES + H * W * OUT_BYTES_PER_RAY)
+                              ns * RECORD_BYTES + H * W * OUT_BYTES_PER_RAY)
     bytes_per_launch = float(np.mean(bytes_per_pose))
-    log(f"per pose: bricks {np.mean(n_bd):.0f}, colour bricks {np.mean(n_cd):.0f}, entries "
+    log(f"per pose: bricks {np.mean(n_bd):.0f}, colour bricks {np.mean(n_cd):.0f}, block records "
         f"{np.mean(n_sl):.0f}, hit rate {np.mean(hits) / (H * W):.3f}, "
         f"{bytes_per_launch / 1e6:.2f} MB")
     cnt = np.mean(counts, 0)
@@ -279,7 +338,56 @@ def main():
     value = rays / wall
     mean_launch_s = float(launch_ms.mean()) * 1e-3
     achieved = bytes_per_launch / mean_launch_s / 1e9
-    traffic = read_traffic(os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip"))
+    render_src = os.path.join(ROOT, "paper_2301_12796_amd", "csrc", "render.hip")
+    traffic = read_float(read_profile("render_room_640x480_traffic.txt", render_src),
+                         "hbm_bytes_per_launch")
+    ctr = read_profile("render_room_640x480_counters.txt", render_src)
+    valu_per_launch = read_float(ctr, "valu_insts_per_launch")
+    valu_frac = (valu_per_launch / (mean_launch_s * VALU_ISSUE_PEAK)
+                 if valu_per_launch is not None else None)
+    # no-reuse byte model: every evaluation reads the 8 corners (sdf, w) of each present
+    # direction of its block from HBM, and every hit the 8 corner colours of each
+    d_bar = info["bricks"] / max(info["blocks"], 1)
+    evals_per_launch = float(np.mean([c_[0][0] + c_[0][1] + c_[0][3] for c_ in counts])) * H * W
+    no_reuse = (evals_per_launch * d_bar * 8 * 8 + float(np.mean(hits)) * d_bar * 8 * 8 +
+                H * W * OUT_BYTES_PER_RAY)
+    log(f"render roofline: {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.4f} of "
+        f"HBM peak); VALU issue fraction {valu_frac if valu_frac is None else round(valu_frac, 4)}; "
+        f"no-reuse model {no_reuse / 1e9:.2f} GB per launch")
+
+    # ---- cold and warm passes: a view rendered right after 2 GiB of unrelated writes (the
+    # caches hold none of the map) and the same view rendered again at once -------------
+    flush = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    cold, warm = [], []
+    for k_ in range(0, n, max(1, n // 10)):
+        e_ = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        flush.fill_(float(k_))
+        e_[0].record(stream)
+        gm.render(cam, poses[k_], out=out)
+        e_[1].record(stream)
+        e_[2].record(stream)
+        gm.render(cam, poses[k_], out=out)
+        e_[3].record(stream)
+        torch.cuda.synchronize()
+        cold.append(e_[0].elapsed_time(e_[1]))
+        warm.append(e_[2].elapsed_time(e_[3]))
+    # plain device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB): the HBM rate the box
+    # reaches with a streaming kernel
+    src_ = flush[: 1 << 28]
+    dst_ = torch.empty_like(src_)
+    for _ in range(3):
+        dst_.copy_(src_)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record(stream)
+    for _ in range(10):
+        dst_.copy_(src_)
+    ce1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src_.numel() * 4 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del flush, src_, dst_
+    torch.cuda.empty_cache()
+    log(f"cold pass {np.mean(cold):.3f} ms, warm pass {np.mean(warm):.3f} ms; device copy "
+        f"{copy_gbs:.0f} GB/s")
 
     # ---- the same 300 views rendered several per launch (dtsdf_render_batch, the serving
     # form's persistent launch): the tails of the views overlap.  Algorithmic bytes of a
@@ -300,7 +408,7 @@ def main():
                                                trace_slots=ts)) for j, T in enumerate(g)]
             gm.render_batch(tviews)
             gbytes.append(int(tb.sum()) * BRICK_MARCH_BYTES + int(tc.sum()) * BRICK_COLOR_BYTES +
-                          int(ts.sum()) * BUCKET_BYTES + len(g) * H * W * OUT_BYTES_PER_RAY)
+                          int(ts.sum()) * RECORD_BYTES + len(g) * H * W * OUT_BYTES_PER_RAY)
         views = [[(cam, T, 0.2, 10.0, bouts[j]) for j, T in enumerate(g)] for g in groups]
         for _ in range(args.warmup):
             for vv in views:
@@ -322,8 +430,8 @@ def main():
         batched = dict(views_per_launch=B, launches_per_step=len(groups),
                        rays_per_s=n * H * W * args.steps / bwall,
                        ms_per_view=1e3 * bwall / (n * args.steps),
-                       roofline=dict(bound="hbm", achieved=bach, peak=HBM_PEAK_GBS, unit="GB/s",
-                                     frac=bach / HBM_PEAK_GBS,
+                       roofline=dict(hbm=dict(achieved=bach, peak=HBM_PEAK_GBS, unit="GB/s",
+                                              frac=bach / HBM_PEAK_GBS),
                                      algorithmic_bytes_per_launch=float(np.mean([gbytes[j] for j in full])),
                                      mean_launch_ms=float(bms[:, full].mean())))
         log(f"batched ({B} views per launch): {batched['rays_per_s'] / 1e6:.1f} M rays/s, "
@@ -539,6 +647,11 @@ def main():
                 f"{ms0:.3f} -> {ms1:.3f} ms, post-fusion MAE {mae0 * 1e3:.3f} -> "
                 f"{mae1 * 1e3:.3f} mm")
 
+    # ---- tracking: 640x480 live frames against the tiny map -----------------------------
+    tracking = None
+    if not args.no_icp:
+        tracking = bench_tracking(torch, synth, dtsdf, dev)
+
     # ---- serving: render + Sim(3) ICP requests from four sensors on the tiny map -------
     serving = None
     if not args.no_serve:
@@ -549,12 +662,17 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
         om = orc.OracleMap(orc.MapParams(voxel=0.005, tau=0.02))
-        sample_frames = list(range(0, n, max(1, n // 5)))[:5]
+        # every tenth of the fused frames (the oracle fuses a frame in about a second)
+        sample_frames = list(range(0, n, 10))
+        ta_ = time.perf_counter()
         for k in sample_frames:
             f = synth.scenes.render_frame(sc, cam, synth.room_pose(k, n), noise="quadratic",
                                           sigma=0.0012, seed=2000 + k, z_max=10.0,
                                           device="cuda")
             om.integrate(f["depth"], f["rgb"], cam, synth.room_pose(k, n))
+        t_fuse = time.perf_counter() - ta_
+        log(f"cpu baseline: oracle map fused from {len(sample_frames)} frames in {t_fuse:.1f} s, "
+            f"{om.num_bricks} bricks (GPU map {info['bricks']})")
         # whole frames of consecutive trajectory poses from pose 30 on, 8 rows at a time,
         # until cpu_seconds of oracle time have been spent
         rays_done, t_cpu, pose_k, rows_done = 0, 0.0, 30, 0
@@ -573,7 +691,9 @@ def main():
                    kind="oracle",
                    sample=f"FP64 oracle render (depth+normal+colour) of {frames_txt} "
                           f"({rays_done} rays, {t_cpu:.1f} s) on an oracle map fused from "
-                          f"frames {sample_frames}")
+                          f"every tenth of the {n} frames ({len(sample_frames)} frames, "
+                          f"{om.num_bricks} bricks; the GPU map holds all {n}, "
+                          f"{info['bricks']} bricks)")
         log(f"cpu baseline: {cpu['value']:.0f} rays/s on {cpu['cores']} threads")
 
     line = {
@@ -596,21 +716,22 @@ def main():
             "width": W, "height": H, "poses_per_step": len(poses), "voxel_m": 0.005,
             "truncation_m": 0.02, "bricks": info["bricks"], "blocks": info["blocks"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+        "roofline": roofline_block(achieved, traffic, valu_per_launch, valu_frac,
+                                   mean_launch_s, ctr) | {
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_ms": float(launch_ms.mean()),
             "bricks_per_launch": float(np.mean(n_bd)),
             "color_bricks_per_launch": float(np.mean(n_cd)),
-            "buckets_per_launch": float(np.mean(n_sl)),
+            "block_records_per_launch": float(np.mean(n_sl)),
+            "no_reuse_bytes_per_launch": no_reuse,
+            "cold_pass_ms": float(np.mean(cold)),
+            "warm_pass_ms": float(np.mean(warm)),
+            "device_copy_gbs": copy_gbs,
+            "frac_of_device_copy": achieved / copy_gbs,
         },
         "cpu_baseline": cpu,
         "integrate_ms_per_frame": integ_ms / n,
+        "fusion": fusion,
         "icp_ms_per_frame": icp_ms,
         "icp_device_loop_ms_per_frame": icp_dev_ms,
         "icp_device_loop_same_pose": same,
@@ -627,6 +748,7 @@ def main():
         "samples_per_ray": per_ray,
         "samples_per_wave_max": per_wave_max,
         "input_generation_s": t_gen,
+        "tracking": tracking,
         "serving": serving,
         "precision": precision,
         "volume": volume,
@@ -674,7 +796,7 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
         tb.zero_(); tc.zero_(); ts.zero_()
         vol.render(cam, T, out=dict(out, trace_bricks=tb, trace_color=tc, trace_slots=ts))
         vbytes.append(int(tb.sum()) * BRICK_MARCH_BYTES + int(tc.sum()) * BRICK_COLOR_BYTES +
-                      int(ts.sum()) * BUCKET_BYTES + H * W * OUT_BYTES_PER_RAY)
+                      int(ts.sum()) * RECORD_BYTES + H * W * OUT_BYTES_PER_RAY)
         v = vol.render(cam, T, outputs=("depth", "mask"))
         d = gm.render(cam, T, outputs=("depth", "mask"))
         vd, dd = v["depth"].cpu().numpy(), d["depth"].cpu().numpy()
@@ -761,21 +883,85 @@ def bench_volume(torch, synth, dtsdf, dev, stream, gm, params, cam, poses, out, 
     return res
 
 
-def bench_serving(args, torch, synth, dtsdf, dev):
-    """The serving workload: the tiny-scene map resident (dense 64^3 blocks at 1 cm, fused
-    from its 10 frames), four sensors (320x240 .. 1280x720, seeded intrinsics and depth
-    scale factors), a Poisson stream at 120 requests/s; each request is a three-level model
-    render plus 10/5/4 Sim(3) ICP iterations from a 2 cm / 2 degree / 1 % prior.  Reports
-    arrival -> pose latency for the continuous-batching server (8 slots, memory budget of 8
-    requests of the largest sensor) and for serial unbatched calls, and the capacity of both
-    with every request queued at the start."""
-    from paper_2301_12796_amd import serve
+def tiny_map(torch, synth, dtsdf, dev):
+    """The tiny-scene map: dense 64^3 blocks at 1 cm (tau 4 cm) fused from its ten frames."""
     tm = dtsdf.Map(dtsdf.Params(voxel_size=0.01, truncation=0.04, brick_capacity=4096,
                                 hash_buckets=1 << 12, dense_lo=synth.scenes.TINY_DENSE_LO,
                                 dense_hi=synth.scenes.TINY_DENSE_HI))
     for f in synth.tiny_frames(10):
         tm.integrate(torch.from_numpy(f["depth"]).to(dev), torch.from_numpy(f["rgb"]).to(dev),
                      synth.scenes.TINY_CAMERA, f["T_wc"])
+    return tm
+
+
+def bench_tracking(torch, synth, dtsdf, dev):
+    """The tracking workload: live 640x480 frames (f = 525, depth noise 0.5 mm) of the tiny
+    scene at 30 seeded poses of its circle, registered against the tiny map from 2 cm /
+    2 degree offsets by three-level point-to-plane ICP (10/5/4 iterations).  Per frame: the
+    model pyramid rendered in one batched launch, then the ICP with a host wait per
+    iteration (icp) and with every level's iterations enqueued on the device (icp_device).
+    Reports ms/frame, the pose error against the truth (the live frame is taken at the model
+    pose, so the result should be the identity) and cond(H) of each level's last step."""
+    tm = tiny_map(torch, synth, dtsdf, dev)
+    cam = synth.scenes.Camera(640, 480, 525.0, 525.0, 319.5, 239.5)
+    sc = synth.tiny_scene()
+    cases = synth.tracking_cases(30)
+    lives = [torch.from_numpy(synth.render_frame(sc, cam, T, noise="const", sigma=0.0005,
+                                                 seed=7000 + i, device="cuda")["depth"]).to(dev)
+             for i, (T, _) in enumerate(cases)]
+    for (T, dT0), live in list(zip(cases, lives))[:3]:                  # warm-up
+        dtsdf.icp(live, cam, dtsdf.render_levels(tm, cam, T, z_far=2.5), dT0)
+    torch.cuda.synchronize()
+    rot, trans, conds, t_host, t_dev, same = [], [], [], 0.0, 0.0, True
+    for (T, dT0), live in zip(cases, lives):
+        ta = time.perf_counter()
+        levels = dtsdf.render_levels(tm, cam, T, z_far=2.5)
+        T_est, lg = dtsdf.icp(live, cam, levels, dT0)
+        torch.cuda.synchronize()
+        t_host += time.perf_counter() - ta
+        ta = time.perf_counter()
+        levels = dtsdf.render_levels(tm, cam, T, z_far=2.5)
+        T_dev = dtsdf.icp_device(live, cam, levels, dT0)
+        torch.cuda.synchronize()
+        t_dev += time.perf_counter() - ta
+        same = same and bool(np.array_equal(T_dev, T_est))
+        c = np.clip((np.trace(T_est[:3, :3]) - 1.0) / 2.0, -1.0, 1.0)
+        rot.append(float(np.arccos(c)))
+        trans.append(float(np.linalg.norm(T_est[:3, 3])))
+        last = {}
+        for e in lg:
+            if "H" in e:
+                last[e["level"]] = e["H"]
+        conds.append([float(np.linalg.cond(last[l])) if l in last else float("nan")
+                      for l in range(3)])
+    conds = np.array(conds)
+    out = dict(cases=len(cases), ms_per_frame=1e3 * t_host / len(cases),
+               device_loop_ms_per_frame=1e3 * t_dev / len(cases), device_loop_same_pose=same,
+               rot_error_median_rad=float(np.median(rot)), rot_error_max_rad=float(np.max(rot)),
+               trans_error_median_m=float(np.median(trans)),
+               trans_error_max_m=float(np.max(trans)),
+               cond_H_median_per_level=[float(np.nanmedian(conds[:, l])) for l in range(3)],
+               cond_H_max_per_level=[float(np.nanmax(conds[:, l])) for l in range(3)])
+    log(f"tracking (tiny scene, 30 cases): {out['ms_per_frame']:.2f} ms/frame "
+        f"({out['device_loop_ms_per_frame']:.2f} device loop, same pose {same}); error vs truth "
+        f"rot median {out['rot_error_median_rad']:.2e} rad, trans median "
+        f"{out['trans_error_median_m']:.2e} m; cond(H) median per level "
+        f"{[round(c_, 0) for c_ in out['cond_H_median_per_level']]}")
+    return out
+
+
+def bench_serving(args, torch, synth, dtsdf, dev):
+    """The serving workload: the tiny-scene map resident (dense 64^3 blocks at 1 cm, fused
+    from its 10 frames), four sensors (320x240 .. 1280x720, seeded intrinsics and depth
+    scale factors), a Poisson stream of 3600 requests at 120 requests/s; each request is a
+    three-level model render plus 10/5/4 Sim(3) ICP iterations from a 2 cm / 2 degree / 1 %
+    prior.  Reports arrival -> pose latency of the continuous-batching server (32 slots,
+    request buffers carved from an arena of 1 % of the device memory free at start-up) and
+    of serial unbatched calls, at 120 req/s and, with the same requests on a compressed
+    timeline, at 480 and 1000 req/s (the serial baseline on the first 600 requests there);
+    and the capacity of both with every request queued at the start."""
+    from paper_2301_12796_amd import serve
+    tm = tiny_map(torch, synth, dtsdf, dev)
     sensors = synth.serving_sensors()
     t = time.time()
     work = synth.serving_workload(args.serve_requests, device="cuda")
@@ -783,49 +969,64 @@ def bench_serving(args, torch, synth, dtsdf, dev):
     torch.cuda.synchronize()
     log(f"serving: {len(work)} requests generated in {time.time() - t:.1f} s, last arrival "
         f"{work[-1]['arrival']:.2f} s")
-    rays = sum(sum((sensors[w["sensor"]][0].width >> l) * (sensors[w["sensor"]][0].height >> l)
-                   for l in range(3)) for w in work)
+    px = [sum((sensors[w["sensor"]][0].width >> l) * (sensors[w["sensor"]][0].height >> l)
+              for l in range(3)) for w in work]
 
-    def reqs():
-        return [serve.Request(k, w["arrival"], w["sensor"], depths[k], w["T_model"], w["dT0"])
-                for k, w in enumerate(work)]
+    def reqs(rate=120.0, n=None):
+        k_ = len(work) if n is None else min(n, len(work))
+        return [serve.Request(k, w["arrival"] * 120.0 / rate, w["sensor"], depths[k],
+                              w["T_model"], w["dT0"]) for k, w in enumerate(work[:k_])]
 
-    def server():
-        return serve.Server(tm, sensors, slots=8)
-
-    server().run(reqs()[:16], realtime=False)                     # warm-up
+    serve.Server(tm, sensors).run(reqs()[:16], realtime=False)        # warm-up
     serve.serve_serial(tm, sensors, reqs()[:4], realtime=False)
     torch.cuda.synchronize()
-    srv = server()
-    t0 = time.perf_counter()
-    done = srv.run(reqs(), realtime=True)
-    wall = time.perf_counter() - t0
-    lat = serve.latency_stats(done)
-    log(f"served (continuous batching): p50 {lat['p50_ms']:.2f} ms, p99 {lat['p99_ms']:.2f} ms, "
-        f"mean batch {np.mean(srv.batch_sizes):.2f}, {rays / wall / 1e6:.2f} M rays/s")
-    ser = serve.serve_serial(tm, sensors, reqs(), realtime=True)
-    lat_s = serve.latency_stats(ser)
-    log(f"served (serial calls): p50 {lat_s['p50_ms']:.2f} ms, p99 {lat_s['p99_ms']:.2f} ms")
+    sweep = []
+    done120 = ser120 = None
+    for rate in (120.0, 480.0, 1000.0):
+        srv = serve.Server(tm, sensors)
+        t0 = time.perf_counter()
+        done = srv.run(reqs(rate), realtime=True)
+        wall = time.perf_counter() - t0
+        lat = serve.latency_stats(done)
+        n_ser = len(work) if rate == 120.0 else min(600, len(work))
+        ser = serve.serve_serial(tm, sensors, reqs(rate, n_ser), realtime=True)
+        lat_s = serve.latency_stats(ser)
+        row = dict(rate_per_s=rate, requests=len(done), p50_ms=lat["p50_ms"],
+                   p99_ms=lat["p99_ms"], mean_batch=float(np.mean(srv.batch_sizes)),
+                   max_batch=int(max(srv.batch_sizes)), rays_per_s=sum(px) / wall,
+                   peak_arena_bytes=int(srv.peak_bytes), arena_bytes=int(srv.budget),
+                   admissions_deferred=int(srv.deferred), serial_requests=n_ser,
+                   serial_p50_ms=lat_s["p50_ms"], serial_p99_ms=lat_s["p99_ms"])
+        sweep.append(row)
+        log(f"served at {rate:.0f} req/s: p50 {lat['p50_ms']:.2f} ms, p99 {lat['p99_ms']:.2f} ms, "
+            f"mean batch {row['mean_batch']:.2f} (max {row['max_batch']}); serial ({n_ser}): "
+            f"p50 {lat_s['p50_ms']:.2f} ms, p99 {lat_s['p99_ms']:.2f} ms")
+        if rate == 120.0:
+            done120, ser120 = done, ser
     bitwise = all(np.array_equal(a.pose, b.pose) for a, b in
-                  zip(sorted(done, key=lambda r: r.rid), sorted(ser, key=lambda r: r.rid)))
-    srv2 = server()
+                  zip(sorted(done120, key=lambda r: r.rid), sorted(ser120, key=lambda r: r.rid)))
+    srv2 = serve.Server(tm, sensors)
     t0 = time.perf_counter()
     srv2.run(reqs(), realtime=False)
     cap = len(work) / (time.perf_counter() - t0)
+    n_cap = min(600, len(work))
     t0 = time.perf_counter()
-    serve.serve_serial(tm, sensors, reqs(), realtime=False)
-    cap_s = len(work) / (time.perf_counter() - t0)
+    serve.serve_serial(tm, sensors, reqs(120.0, n_cap), realtime=False)
+    cap_s = n_cap / (time.perf_counter() - t0)
     log(f"capacity: batched {cap:.0f} req/s, serial {cap_s:.0f} req/s; alone == mix: {bitwise}")
     scale_err = [abs(np.cbrt(np.linalg.det(r.pose[:3, :3])) * work[r.rid]["scale"] - 1.0)
-                 for r in done]
-    return dict(requests=len(work), rate_per_s=120.0, slots=8,
-                p50_ms=lat["p50_ms"], p99_ms=lat["p99_ms"],
-                serial_p50_ms=lat_s["p50_ms"], serial_p99_ms=lat_s["p99_ms"],
-                rays_per_s=rays / wall, mean_batch=float(np.mean(srv.batch_sizes)),
+                 for r in done120]
+    base = sweep[0]
+    return dict(requests=len(work), rate_per_s=120.0, slots=srv2.slots_count,
+                p50_ms=base["p50_ms"], p99_ms=base["p99_ms"],
+                serial_p50_ms=base["serial_p50_ms"], serial_p99_ms=base["serial_p99_ms"],
+                rays_per_s=base["rays_per_s"], mean_batch=base["mean_batch"],
                 capacity_req_per_s=cap, serial_capacity_req_per_s=cap_s,
+                serial_capacity_sample=f"first {n_cap} requests",
                 alone_vs_mix_bitwise=bool(bitwise),
                 scale_error_median=float(np.median(scale_err)),
-                sample=f"first {len(work)} requests of the 3600-request stream")
+                arena_bytes=int(srv2.budget), rate_sweep=sweep,
+                sample=f"all {len(work)} requests of the stream")
 
 
 if __name__ == "__main__":

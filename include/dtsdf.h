@@ -98,7 +98,13 @@ typedef struct {
  * and every hash entry whose brick indices a lookup read (trace_slots, hash_buckets bytes);
  * trace_counts (4 int32 per pixel) receives the number of evaluations at lattice points that
  * may end a crossing, evaluations of a skipped positive point that precedes such a point,
- * jumps over absent space, and refinement evaluations. */
+ * jumps over absent space, and refinement evaluations.  A traced render marches every ray
+ * alone (as with DTSDF_RENDER_ALONE), so that the counts and sets are those of the ray.
+ * flags: DTSDF_RENDER_ALONE marches every ray alone; by default lanes of a wave whose ray
+ * has finished evaluate lattice points of the rays still marching.  The images are the same
+ * either way (the values at lattice points, hence the hit, do not depend on who evaluates
+ * them); the flag serves tests and comparisons. */
+#define DTSDF_RENDER_ALONE 1
 typedef struct {
   float* depth;   /* H*W camera-frame z of the hit, 0 where nothing was hit */
   float* vertex;  /* 3*H*W planes, camera-frame hit point */
@@ -109,6 +115,7 @@ typedef struct {
   uint8_t* trace_color;
   uint8_t* trace_slots;
   int32_t* trace_counts;
+  int32_t flags;  /* 0 or DTSDF_RENDER_ALONE */
 } dtsdf_render_out;
 
 /* Host-side map image used for checkpoints and exact map transfer.  Bricks are listed in
@@ -134,9 +141,12 @@ dtsdf_status dtsdf_destroy(dtsdf_map* map);
 dtsdf_status dtsdf_get_info(const dtsdf_map* map, dtsdf_info* out);
 
 typedef struct {
-  int64_t new_bricks;  /* brick-directions allocated by this call */
-  int64_t dropped;     /* requests refused for lack of capacity by this call */
-  int64_t bricks;      /* brick-directions in use after the call */
+  int64_t new_bricks;      /* brick-directions allocated by this call */
+  int64_t dropped;         /* requests refused for lack of capacity by this call */
+  int64_t bricks;          /* brick-directions in use after the call */
+  int64_t visited_bricks;  /* bricks the fusion visited (frustum test passed) */
+  int64_t updated_voxels;  /* voxels whose distance and weight were updated */
+  int64_t color_voxels;    /* voxels whose colour was updated */
 } dtsdf_integrate_stats;
 
 /* Fuse one depth (+ colour) frame with known pose (Sec. 3).

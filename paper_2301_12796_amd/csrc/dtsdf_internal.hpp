@@ -350,6 +350,9 @@ struct dtsdf_map {
   int64_t n_free;
   // bricks whose voxels may project into the frame being fused (counters[11] of them)
   int32_t* vis_list;
+  // per listed brick of the frame: voxels whose distance / colour were updated (allocated
+  // on the first integration that asks for statistics)
+  int2* fuse_cnt;
   // per pixel of the frame being fused: 1 if no valid depth within two pixels differs from
   // the pixel's by more than tau (the carving guard of Sec. 3)
   uint8_t* carve_ok;

@@ -196,10 +196,43 @@ struct FuseArgs {
   Intr in;
   double scale;
   Pose T;
+  int2* counts;    // per listed brick: updated distances / colours, or null
 };
 
 __global__ void vis_reset_k(int32_t* counters) {
   if (threadIdx.x == 0) counters[11] = 0;
+}
+
+// Sums the per-brick update counts of the frame into counters[12] (distances) and
+// counters[13] (colours); one workgroup.
+__global__ __launch_bounds__(1024) void fuse_count_k(const int2* __restrict__ counts,
+                                                     int32_t* counters) {
+  __shared__ int sg[16], sc[16];
+  const int n = counters[11];
+  int g = 0, c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    g += counts[i].x;
+    c += counts[i].y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    g += __shfl_xor(g, o);
+    c += __shfl_xor(c, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sg[threadIdx.x >> 6] = g;
+    sc[threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tg = 0, tc = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      tg += sg[w];
+      tc += sc[w];
+    }
+    counters[12] = tg;
+    counters[13] = tc;
+  }
 }
 
 // Conservative frustum test of every brick in the pool, one thread per brick: a brick is
@@ -245,6 +278,8 @@ __global__ __launch_bounds__(256) void cull_k(const int4* __restrict__ bkey, int
 
 // Voxel-projection fusion (Sec. 3) of one brick per workgroup.  A brick with any updated
 // voxel refreshes its sub-block minima (sdf over voxels with w > 0) for the render index.
+// With a.counts the brick's numbers of updated distances and colours are stored at its
+// list position (integration statistics).
 template <int F>
 __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_min,
                                               uint64_t* brick_neg,
@@ -254,10 +289,14 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
   const int b = __builtin_amdgcn_readfirstlane(list[blockIdx.x]);
   const int4 key = m.bkey[b];
   const int D = key.w;
-  if (D < 0) return;                      // a recycled brick on the free list
+  if (D < 0) {                            // a recycled brick on the free list
+    if (a.counts && threadIdx.x == 0) a.counts[blockIdx.x] = make_int2(0, 0);
+    return;
+  }
   const size_t HW = (size_t)a.in.W * a.in.H;
   const double tau = (double)m.tau;
   bool upd = false;
+  int n_geo = 0, n_col = 0;    // voxels of this thread updated (at most two each)
   for (int l = threadIdx.x; l < kVox; l += blockDim.x) {
     const int lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
     double x[3] = {(double)(key.x * kB + lx) * m.voxel, (double)(key.y * kB + ly) * m.voxel,
@@ -291,6 +330,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
         const float nw = w + m.w_carve;
         Vox<F>::store(m.geo, vi, (sd * w + 1.0f * m.w_carve) / nw, fminf(nw, m.w_max));
         upd = true;
+        ++n_geo;
       }
       continue;
     }
@@ -313,6 +353,7 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
       Vox<F>::store(m.geo, vi, (sd * w + (float)dd * wd) / nw, fminf(nw, m.w_max));
     }
     upd = true;
+    ++n_geo;
     if (m.with_color && a.rgb) {
       // colour weight w_c = w_d (1 - min(1, |p - x| / tau)) (eq. color_weight)
       const double dist = sqrt((pc[0] - xc[0]) * (pc[0] - xc[0]) + (pc[1] - xc[1]) * (pc[1] - xc[1]) +
@@ -332,7 +373,21 @@ __global__ __launch_bounds__(256) void fuse_k(MapView m, FuseArgs a, float* sub_
           outc |= (uint32_t)val << (8 * ch);
         }
         Vox<F>::store_color(m.rgb, m.wc, vi, outc, fminf(Wc + wc, m.w_max));
+        ++n_col;
       }
+    }
+  }
+  if (a.counts) {
+    // both counts packed in one word (at most 512 each): wave sums, then the workgroup's
+    __shared__ int wsum[4];
+    int cnt = n_geo | (n_col << 16);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+      a.counts[blockIdx.x] = make_int2(t & 0xFFFF, t >> 16);
     }
   }
   if (__syncthreads_or(upd))
@@ -486,7 +541,13 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
     const int n = (int)m->n_bricks;
     hipLaunchKernelGGL(cull_k, dim3((n + 255) / 256), dim3(256), 0, st, m->bkey, n, T, in,
                        (double)m->p.voxel_size, m->vis_list, m->counters);
-    FuseArgs fa{depth, rgb, nmap, m->carve_ok, in, (double)depth_scale, T};
+    if (stats && !m->fuse_cnt &&
+        hipMalloc(&m->fuse_cnt, sizeof(int2) * (size_t)m->p.brick_capacity) != hipSuccess) {
+      m->fuse_cnt = nullptr;
+      return DTSDF_E_NOMEM;
+    }
+    FuseArgs fa{depth, rgb, nmap, m->carve_ok, in, (double)depth_scale, T,
+                stats ? m->fuse_cnt : nullptr};
     const dim3 grd_b((uint32_t)n);
     if (m->fmt == 0)
       hipLaunchKernelGGL(fuse_k<0>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
@@ -498,6 +559,8 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
       hipLaunchKernelGGL(fuse_k<2>, grd_b, dim3(256), 0, st, make_view(m), fa, m->sub_min,
                          m->brick_neg, m->vis_list, m->counters);
   }
+  if (stats && m->n_bricks > 0)
+    hipLaunchKernelGGL(fuse_count_k, dim3(1), dim3(1024), 0, st, m->fuse_cnt, m->counters);
   DTSDF_HIP(hipGetLastError());
   dtsdf_status is = launch_index_update(m, st);
   if (is != DTSDF_OK) return is;
@@ -505,7 +568,13 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
     stats->new_bricks = m->n_bricks - m->n_free - before;
     stats->dropped = dropped_now;
     stats->bricks = m->n_bricks - m->n_free;
+    int32_t fc[3] = {0, 0, 0};
+    if (m->n_bricks > 0)
+      DTSDF_HIP(hipMemcpyAsync(fc, m->counters + 11, sizeof(fc), hipMemcpyDeviceToHost, st));
     DTSDF_HIP(hipStreamSynchronize(st));
+    stats->visited_bricks = fc[0];
+    stats->updated_voxels = fc[1];
+    stats->color_voxels = fc[2];
   }
   return dropped_now > 0 ? DTSDF_E_CAPACITY : DTSDF_OK;
 }

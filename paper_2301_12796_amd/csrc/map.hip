@@ -115,6 +115,7 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->counters);
   (void)hipFree(m->free_list);
   (void)hipFree(m->vis_list);
+  (void)hipFree(m->fuse_cnt);
   (void)hipFree(m->carve_ok);
   (void)hipFree(m->vmap);
   (void)hipFree(m->nmap);

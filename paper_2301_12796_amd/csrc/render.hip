@@ -49,6 +49,7 @@ struct RenderArgs {
   uint8_t* trace_color;
   uint8_t* trace_slots;
   int32_t* trace_counts;
+  int help;       // lanes whose ray has finished evaluate points of the marching rays
 };
 
 struct Trace {
@@ -502,6 +503,49 @@ __device__ void eval_cell(const MapView& m, const CellPos& cp, uint32_t pm, cons
 // Directions per group of the march's evaluations (see eval_cell).
 constexpr int march_group(int) { return 1; }
 
+// World-frame unit ray of pixel (u, v) of view `a` and its parameter range [t0, tmax] (depth
+// z_near .. z_far).
+__device__ inline void pixel_ray(const RenderArgs& a, int u, int v, double r[3], double& t0,
+                                 double& tmax) {
+  const double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
+  const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
+  const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    r[k] = a.R[3 * k] * rc[0] + a.R[3 * k + 1] * rc[1] + a.R[3 * k + 2] * rc[2];
+  t0 = a.z_near / rc[2];
+  tmax = a.z_far / rc[2];
+}
+
+// Lane number of the n-th set bit (n counted from 0) of a 64-bit lane mask.
+__device__ inline int nth_lane(uint64_t mask, int n) {
+  int base = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t lo = mask & ((1ull << w) - 1ull);
+    const int c = __popcll(lo);
+    if (n >= c) {
+      n -= c;
+      mask >>= w;
+      base += w;
+    } else {
+      mask = lo;
+    }
+  }
+  return base;
+}
+
+__device__ inline double shfl_d(double x, int src) {
+  const int64_t b = __double_as_longlong(x);
+  const int lo = __shfl((int)(b & 0xffffffff), src, 64);
+  const int hi = __shfl((int)(b >> 32), src, 64);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Lattice points a marching ray may be helped with per pass (lanes whose own ray has finished
+// evaluate them).
+constexpr int kMaxHelpers = 7;
+
 // Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step and every
 // step after one that shrank the bracket by less than a tenth a bisection, until the bracket
 // is shorter than kRefineTol (metres along the ray) or after kRefineMaxIter evaluations.
@@ -526,16 +570,8 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   const float inv_band = 1.0f / (2.0f * m.theta - 1.5707963267948966f);
   double r[3];
   double t0, tmax;
-  {
-    const double dc[3] = {((double)u - a.cx) / a.fx, ((double)v - a.cy) / a.fy, 1.0};
-    const double len = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
-    const double rc[3] = {dc[0] / len, dc[1] / len, dc[2] / len};
-    for (int k = 0; k < 3; ++k)
-      r[k] = a.R[3 * k] * rc[0] + a.R[3 * k + 1] * rc[1] + a.R[3 * k + 2] * rc[2];
-    t0 = a.z_near / rc[2];
-    tmax = a.z_far / rc[2];
-  }
-  const float rf[3] = {(float)r[0], (float)r[1], (float)r[2]};
+  pixel_ray(a, u, v, r, t0, tmax);
+  float rf[3] = {(float)r[0], (float)r[1], (float)r[2]};
   const double o[3] = {a.t[0], a.t[1], a.t[2]};
   const double step = m.step;
   const Trace tr{a.trace_bricks, a.trace_color, a.trace_slots};
@@ -569,6 +605,8 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   bool lattice = false;   // the pending point is lattice point k, not a deferred one
   bool lpair = false;     // lattice: k + 1 is evaluated together with k
   int next_k = 0;         // lattice index after the pending point
+  bool h_def = false;     // value of the point this lane evaluated in the current pass
+  float h_f = 0.f;
   for (;;) {
     // ---- advance to the next evaluation point ---------------------------------------
     for (; !pending && !done;) {
@@ -697,99 +735,182 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
     }
     // ---- evaluate -----------------------------------------------------------------
     if (!__any(pending)) break;
-    if (!pending) continue;
-    pending = false;
-    const double x[3] = {o[0] + te * r[0], o[1] + te * r[1], o[2] + te * r[2]};
-    CellPos cp;
-    locate(m, x, cp);
-    if (cp.bl[0] != cb0 || cp.bl[1] != cb1 || cp.bl[2] != cb2) {
-      cb0 = cp.bl[0];
-      cb1 = cp.bl[1];
-      cb2 = cp.bl[2];
-      cinfo = enter_block<TRACE>(m, grid_index(m, cb0, cb1, cb2), brow, cwl, gwl, cpm, tr);
-    }
-    // a second point is evaluated with the first when both share the cell: the refinement
-    // pair, or lattice point k + 1
-    bool pair = lattice && lpair;
-    float pa1[1][3] = {{cp.a[0], cp.a[1], cp.a[2]}};
-    if (refining || pair) {
-      const double x2[3] = {o[0] + te2 * r[0], o[1] + te2 * r[1], o[2] + te2 * r[2]};
-      CellPos cp2;
-      locate(m, x2, cp2);
-      pair = cp2.bl[0] == cp.bl[0] && cp2.bl[1] == cp.bl[1] && cp2.bl[2] == cp.bl[2] &&
-             cp2.lo[0] == cp.lo[0] && cp2.lo[1] == cp.lo[1] && cp2.lo[2] == cp.lo[2];
-      pa1[0][0] = cp2.a[0];
-      pa1[0][1] = cp2.a[1];
-      pa1[0][2] = cp2.a[2];
-    }
-    Eval ev[2];
-    // only the directions defined somewhere in the cell's 2x2x2 group can contribute
-    const int grp = (cp.lo[0] >> 1) + 4 * (cp.lo[1] >> 1) + 16 * (cp.lo[2] >> 1);
-    const uint32_t gdef = (uint32_t)(gwl[(grp >> 3) * 64] >> (8 * (grp & 7))) & 0x3Fu;
-    eval_cell<F, false, TRACE, 2, G>(m, cp, cpm & gdef, brow, rf, inv_band, ev, tr, pa1);
-    const Eval& e = ev[0];
-    if (refining) {
-      if (TRACE) ++n_refine;
-      ++it;
-      const double w0 = tb - ta;
-      const bool pos1 = !e.defined || e.f > 0.f;
-      const bool pos2 = !ev[1].defined || ev[1].f > 0.f;
-      if (pos1 && pair && !pos2) {
-        // the pair straddles the root: final bracket
-        ta = te;
-        tb = te2;
-        if (e.defined) fa = e.f;
-        fb = ev[1].f;
-      } else if (pos1) {
-        ta = pair ? te2 : te;
-        const Eval& ea = pair ? ev[1] : e;
-        if (ea.defined) fa = ea.f;
-        if (side == 1) fb *= 0.5f;
-        side = 1;
-      } else {
-        tb = te;
-        fb = e.f;
-        if (side == -1) fa *= 0.5f;
-        side = -1;
+    // Lanes whose ray has finished help the marching rays: each takes one lattice point after
+    // the ones its ray evaluates itself this pass.  The ray receives the values in order and
+    // runs the crossing test over them as if it had evaluated them itself (f at a lattice
+    // point does not depend on who evaluates it, and the points a march skips cannot end a
+    // crossing), so the hit, and everything after it, is the same.  Owner and helper
+    // exchange data by shuffles only; a helper's own ray keeps its bracket, and its
+    // direction is recomputed for the outputs.
+    const bool owner = pending && !refining;
+    const uint64_t own_m = __ballot(owner);
+    const uint64_t idle_m = __ballot(!pending);
+    const int n_own = __popcll(own_m), n_idle = __popcll(idle_m);
+    const int nh = (!TRACE && a.help && n_own > 0) ? min(kMaxHelpers, n_idle / n_own) : 0;
+    const uint64_t below = (1ull << (threadIdx.x & 63)) - 1ull;
+    // lattice index after the owner's own points: k (+ 1 with the pair), or k after a
+    // deferred k - 1
+    const int base = lattice ? (lpair ? k + 2 : k + 1) : next_k;
+    int h_src = (int)(threadIdx.x & 63);
+    bool helper = false;
+    int h_k = 0;
+    double h_tmax = 0.0;
+    if (nh > 0) {
+      int slot = -1;
+      if (!pending) {
+        const int hr = __popcll(idle_m & below);
+        if (hr < nh * n_own) {
+          slot = hr / n_own;
+          h_src = nth_lane(own_m, hr % n_own);
+        }
       }
-      // a false-position step that shrank the bracket by less than a tenth (one end keeps
-      // a value far from the root, e.g. behind a jump of f at a cell face) is followed by
-      // a bisection
-      bisect = (tb - ta) > 0.9 * w0;
-      continue;
-    }
-    if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
-      hit = true;
-      refining = true;
-      ta = t0 + (double)(k - 1) * step;
-      tb = te;
-      fa = prev_f;
-      fb = e.f;
-      continue;
-    }
-    if (pair) {
-      // lattice point k + 1, with f(k) from the first point
-      if (ev[1].defined && e.defined && e.f > 0.f && ev[1].f <= 0.f) {
-        hit = true;
-        refining = true;
-        ta = te;
-        tb = te2;
-        fa = e.f;
-        fb = ev[1].f;
-        continue;
+      // every lane takes part in the shuffles (a lane that is no helper reads itself)
+      double hr3[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) hr3[q] = shfl_d(r[q], h_src);
+      const double h_t0 = shfl_d(t0, h_src);
+      h_tmax = shfl_d(tmax, h_src);
+      const int h_base = __shfl(base, h_src, 64);
+      if (slot >= 0) {
+        h_k = h_base + slot;
+        const double th = h_t0 + (double)h_k * step;
+        helper = th <= h_tmax;
+        if (helper) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            r[q] = hr3[q];
+            rf[q] = (float)hr3[q];
+          }
+          te = th;
+        }
       }
-      prev_def = ev[1].defined;
-      prev_f = ev[1].f;
-      k = next_k + 1;
-      continue;
     }
-    prev_def = e.defined;
-    prev_f = e.f;
-    k = next_k;
+    if (pending || helper) {
+      const double x[3] = {o[0] + te * r[0], o[1] + te * r[1], o[2] + te * r[2]};
+      CellPos cp;
+      locate(m, x, cp);
+      if (cp.bl[0] != cb0 || cp.bl[1] != cb1 || cp.bl[2] != cb2) {
+        cb0 = cp.bl[0];
+        cb1 = cp.bl[1];
+        cb2 = cp.bl[2];
+        cinfo = enter_block<TRACE>(m, grid_index(m, cb0, cb1, cb2), brow, cwl, gwl, cpm, tr);
+      }
+      // a second point is evaluated with the first when both share the cell: the refinement
+      // pair, or lattice point k + 1
+      bool pair = pending && lattice && lpair;
+      float pa1[1][3] = {{cp.a[0], cp.a[1], cp.a[2]}};
+      if (pending && (refining || pair)) {
+        const double x2[3] = {o[0] + te2 * r[0], o[1] + te2 * r[1], o[2] + te2 * r[2]};
+        CellPos cp2;
+        locate(m, x2, cp2);
+        pair = cp2.bl[0] == cp.bl[0] && cp2.bl[1] == cp.bl[1] && cp2.bl[2] == cp.bl[2] &&
+               cp2.lo[0] == cp.lo[0] && cp2.lo[1] == cp.lo[1] && cp2.lo[2] == cp.lo[2];
+        pa1[0][0] = cp2.a[0];
+        pa1[0][1] = cp2.a[1];
+        pa1[0][2] = cp2.a[2];
+      }
+      Eval ev[2];
+      // only the directions defined somewhere in the cell's 2x2x2 group can contribute
+      const int grp = (cp.lo[0] >> 1) + 4 * (cp.lo[1] >> 1) + 16 * (cp.lo[2] >> 1);
+      const uint32_t gdef = (uint32_t)(gwl[(grp >> 3) * 64] >> (8 * (grp & 7))) & 0x3Fu;
+      eval_cell<F, false, TRACE, 2, G>(m, cp, cpm & gdef, brow, rf, inv_band, ev, tr, pa1);
+      const Eval& e = ev[0];
+      h_def = e.defined;
+      h_f = e.f;
+      if (pending) {
+        pending = false;
+        if (refining) {
+          if (TRACE) ++n_refine;
+          ++it;
+          const double w0 = tb - ta;
+          const bool pos1 = !e.defined || e.f > 0.f;
+          const bool pos2 = !ev[1].defined || ev[1].f > 0.f;
+          if (pos1 && pair && !pos2) {
+            // the pair straddles the root: final bracket
+            ta = te;
+            tb = te2;
+            if (e.defined) fa = e.f;
+            fb = ev[1].f;
+          } else if (pos1) {
+            ta = pair ? te2 : te;
+            const Eval& ea = pair ? ev[1] : e;
+            if (ea.defined) fa = ea.f;
+            if (side == 1) fb *= 0.5f;
+            side = 1;
+          } else {
+            tb = te;
+            fb = e.f;
+            if (side == -1) fa *= 0.5f;
+            side = -1;
+          }
+          // a false-position step that shrank the bracket by less than a tenth (one end
+          // keeps a value far from the root, e.g. behind a jump of f at a cell face) is
+          // followed by a bisection
+          bisect = (tb - ta) > 0.9 * w0;
+        } else if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
+          hit = true;
+          refining = true;
+          ta = t0 + (double)(k - 1) * step;
+          tb = te;
+          fa = prev_f;
+          fb = e.f;
+        } else if (pair) {
+          // lattice point k + 1, with f(k) from the first point
+          if (ev[1].defined && e.defined && e.f > 0.f && ev[1].f <= 0.f) {
+            hit = true;
+            refining = true;
+            ta = te;
+            tb = te2;
+            fa = e.f;
+            fb = ev[1].f;
+          } else {
+            prev_def = ev[1].defined;
+            prev_f = ev[1].f;
+            k = next_k + 1;
+          }
+        } else {
+          prev_def = e.defined;
+          prev_f = e.f;
+          k = next_k;
+        }
+      }
+    }
+    // the helpers' values, in lattice order, for each marching ray that has not hit
+    if (nh > 0) {
+      const int my_rank = __popcll(own_m & below);
+      bool take = owner && !refining && k == base;
+      for (int sl = 0; sl < nh; ++sl) {
+        const int hr = my_rank + sl * n_own;
+        const int src = (owner && hr < n_idle) ? nth_lane(idle_m, hr) : (int)(threadIdx.x & 63);
+        const int hv = __shfl(helper ? 1 : 0, src, 64);
+        const int hd = __shfl(h_def ? 1 : 0, src, 64);
+        const float hfv = __shfl(h_f, src, 64);
+        take = take && owner && hr < n_idle && hv != 0;
+        if (take) {
+          pos_last = -1;
+          if (k >= 1 && hd && prev_def && prev_f > 0.f && hfv <= 0.f) {
+            hit = true;
+            refining = true;
+            ta = t0 + (double)(k - 1) * step;
+            tb = t0 + (double)k * step;
+            fa = prev_f;
+            fb = hfv;
+            take = false;
+          } else {
+            prev_def = hd != 0;
+            prev_f = hfv;
+            ++k;
+          }
+        }
+      }
+    }
   }
   float out_depth = 0.f, out_v[3] = {0.f, 0.f, 0.f}, out_n[3] = {0.f, 0.f, 0.f};
   uint32_t out_c = 0;
   if (hit) {
+    pixel_ray(a, u, v, r, t0, tmax);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rf[q] = (float)r[q];
     const double ts = 0.5 * (ta + tb);
     const double x[3] = {o[0] + tb * r[0], o[1] + tb * r[1], o[2] + tb * r[2]};
     CellPos cp;
@@ -885,6 +1006,7 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
       !(z_far > z_near))
     return false;
   if (out->rgba && ((uintptr_t)out->rgba & 3u)) return false;
+  if (out->flags & ~DTSDF_RENDER_ALONE) return false;
   a.W = intr->width;
   a.H = intr->height;
   a.tiles_x = (a.W + 7) / 8;
@@ -908,6 +1030,7 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
   a.trace_color = out->trace_color;
   a.trace_slots = out->trace_slots;
   a.trace_counts = out->trace_counts;
+  a.help = (out->flags & DTSDF_RENDER_ALONE) ? 0 : 1;
   return true;
 }
 

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_INVAL, E_NOMEM, E_CAPACITY, E_HIP, E_DEGENERATE, E_BUSY = range(7)
 SDF_F32, SDF_F16, SDF_I16 = 0, 1, 2
+RENDER_ALONE = 1
 W_F32, W_U8 = 0, 1
 ICP_W_CONST, ICP_W_DEPTH = 0, 1
 
@@ -63,7 +64,7 @@ class _RenderOut(ctypes.Structure):
                 ("normal", ctypes.c_void_p), ("rgba", ctypes.c_void_p),
                 ("mask", ctypes.c_void_p), ("trace_bricks", ctypes.c_void_p),
                 ("trace_color", ctypes.c_void_p), ("trace_slots", ctypes.c_void_p),
-                ("trace_counts", ctypes.c_void_p)]
+                ("trace_counts", ctypes.c_void_p), ("flags", ctypes.c_int32)]
 
 
 class _Blob(ctypes.Structure):
@@ -73,7 +74,8 @@ class _Blob(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("new_bricks", ctypes.c_int64), ("dropped", ctypes.c_int64),
-                ("bricks", ctypes.c_int64)]
+                ("bricks", ctypes.c_int64), ("visited_bricks", ctypes.c_int64),
+                ("updated_voxels", ctypes.c_int64), ("color_voxels", ctypes.c_int64)]
 
 
 class _Image(ctypes.Structure):
@@ -318,7 +320,8 @@ class Map:
         _check(status, "dtsdf_integrate", allow=(E_CAPACITY,))
         if stats:
             return dict(status=status, new_bricks=st.new_bricks, dropped=st.dropped,
-                        bricks=st.bricks)
+                        bricks=st.bricks, visited_bricks=st.visited_bricks,
+                        updated_voxels=st.updated_voxels, color_voxels=st.color_voxels)
         return status
 
     def _render_out(self, cam, out: dict) -> _RenderOut:
@@ -332,7 +335,8 @@ class Map:
                           _dev_ptr(out.get("trace_bricks"), torch.uint8, cap),
                           _dev_ptr(out.get("trace_color"), torch.uint8, cap),
                           _dev_ptr(out.get("trace_slots"), torch.uint8, nb),
-                          _dev_ptr(out.get("trace_counts"), torch.int32, 4 * H * W))
+                          _dev_ptr(out.get("trace_counts"), torch.int32, 4 * H * W),
+                          RENDER_ALONE if out.get("alone", False) else 0)
 
     def render_batch(self, views, stream=None) -> None:
         """views: list of (cam, T_wc, z_near, z_far, out dict of preallocated tensors)."""
@@ -348,7 +352,9 @@ class Map:
 
     def render(self, cam, T_wc, z_near: float = 0.2, z_far: float = 10.0,
                out: Optional[dict] = None, outputs=("depth", "vertex", "normal", "rgba", "mask"),
-               stream=None) -> dict:
+               stream=None, alone: bool = False) -> dict:
+        """Renders a view into `out` (preallocated tensors) or new tensors of `outputs`;
+        alone: every ray marches alone (DTSDF_RENDER_ALONE)."""
         H, W = int(cam.height), int(cam.width)
         dev = torch.device("cuda", torch.cuda.current_device())
         if out is None:
@@ -359,7 +365,7 @@ class Map:
             for k in outputs:
                 shp, dt = shapes[k]
                 out[k] = torch.empty(shp, dtype=dt, device=dev)
-        ro = self._render_out(cam, out)
+        ro = self._render_out(cam, dict(out, alone=alone))
         _check(_lib.dtsdf_render(self._h, ctypes.byref(_intr(cam)), _pose(T_wc), z_near, z_far,
                                  ctypes.byref(ro), _stream(stream)), "dtsdf_render")
         return out
@@ -826,7 +832,7 @@ def icp(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 6,
                 break
             T = T_new
             log.append(dict(level=l, inliers=res["inliers"], err=res["error"],
-                            step=res["step_norm"], photometric=res["photometric"]))
+                            step=res["step_norm"], photometric=res["photometric"], H=res["H"]))
             if res["step_norm"] < min_step:
                 break
     return T, log

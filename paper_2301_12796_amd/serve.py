@@ -6,12 +6,14 @@ render (one view per pyramid level) and coarse-to-fine point-to-plane ICP in Sim
 (or SE(3)) with the live frame, the scale factor of the sensor being part of the estimate.
 
 The server runs in rounds.  At the start of a round every request whose arrival time has
-passed is admitted while a slot is free and the device memory it needs fits the budget; the
+passed is admitted while a slot is free and its buffers, sized for its own sensor, can be
+carved out of the server's device arena (one allocation whose size is a budget taken from
+the device's free memory at start-up); the
 model pyramids of all newly admitted requests are rendered in one `dtsdf_render_batch`
 launch, and every admitted request then advances by one ICP iteration in one
 `icp_step_batch` (poses, convergence flags and results stay in device memory).  A request
-leaves after its last iteration of the finest level; its slot and memory are freed for the
-next round.  Requests that arrive while others are on the device therefore join the running
+leaves after its last iteration of the finest level; its slot and its part of the arena are
+freed for the next round.  Requests that arrive while others are on the device therefore join the running
 batch (continuous batching, not a queue in front of a serial worker), and each request's
 result is bitwise the same as when it is served alone.
 
@@ -54,31 +56,105 @@ class Request:
 
 @dataclasses.dataclass
 class _Slot:
-    live_levels: list              # per level (vertex, normal, cam)
-    model_levels: list             # per level (vertex, normal, mask, cam)
     pose: torch.Tensor
     active: torch.Tensor
     result: torch.Tensor
+    live_levels: list = dataclasses.field(default_factory=list)   # per level depth, vertex, normal
+    model_levels: list = dataclasses.field(default_factory=list)  # per level vertex, normal, mask
     req: Optional[Request] = None
     level: int = 0
     it: int = 0
-    need: int = 0
+    block: Optional[tuple] = None  # (offset, bytes) of the request's buffers in the arena
     c_req: object = None           # C descriptor of the current level's ICP request
     stage: Optional[torch.Tensor] = None   # pinned initial pose being copied in
 
 
+_ALIGN = 256
+
+
+def _buffers(cam, levels: int):
+    """Buffers of one request, in arena order: per level the live depth, vertex and normal
+    (float32: 1, 3, 3 per pixel) and the model vertex, normal (float32, 3 each) and mask
+    (uint8, 1).  Returns [(level, side, name, dtype, elements)]."""
+    out = []
+    for l in range(levels):
+        n = (cam.width >> l) * (cam.height >> l)
+        out += [(l, "live", "depth", torch.float32, n),
+                (l, "live", "vertex", torch.float32, 3 * n),
+                (l, "live", "normal", torch.float32, 3 * n),
+                (l, "model", "vertex", torch.float32, 3 * n),
+                (l, "model", "normal", torch.float32, 3 * n),
+                (l, "model", "mask", torch.uint8, n)]
+    return out
+
+
+def _aligned(nbytes: int) -> int:
+    return (nbytes + _ALIGN - 1) // _ALIGN * _ALIGN
+
+
+def _nbytes(dtype, count: int) -> int:
+    return count * (4 if dtype == torch.float32 else 1)
+
+
 def request_bytes(cam, levels: int = 3) -> int:
-    """Device memory one request of this sensor holds while admitted: live pyramid depth,
-    vertex and normal (28 B/px) and model vertex, normal and mask (25 B/px) per level."""
-    px = sum((cam.width >> l) * (cam.height >> l) for l in range(levels))
-    return px * (28 + 25) + 1024
+    """Device memory one request of this sensor holds while admitted: per level live depth,
+    vertex and normal (28 B/px) and model vertex, normal and mask (25 B/px), each buffer
+    starting on a 256-byte boundary of the arena."""
+    return sum(_aligned(_nbytes(dt, k)) for _, _, _, dt, k in _buffers(cam, levels))
+
+
+class Arena:
+    """First-fit allocator over one device allocation of `nbytes` (offsets and sizes in
+    multiples of 256 bytes; a freed range merges with its free neighbours).  All work on
+    the memory is issued on one stream, so a range handed out again is only written after
+    the earlier work on it."""
+
+    def __init__(self, nbytes: int, device):
+        self.size = nbytes // _ALIGN * _ALIGN
+        self.mem = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)] if self.size else []   # sorted, disjoint, not adjacent
+        self.in_use = 0
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        nbytes = _aligned(nbytes)
+        for i, (off, size) in enumerate(self.free):
+            if size >= nbytes:
+                if size == nbytes:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + nbytes, size - nbytes)
+                self.in_use += nbytes
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int) -> None:
+        nbytes = _aligned(nbytes)
+        self.in_use -= nbytes
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, (off, nbytes))
+        if i + 1 < len(self.free) and off + nbytes == self.free[i + 1][0]:
+            self.free[i] = (off, nbytes + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def view(self, off: int, dtype, count: int) -> torch.Tensor:
+        return self.mem[off:off + _nbytes(dtype, count)].view(dtype)
 
 
 class Server:
-    def __init__(self, gmap: dtsdf.Map, sensors: Sequence, *, slots: int = 8,
-                 budget_bytes: Optional[int] = None, dim: int = 7, iters=(10, 5, 4),
+    def __init__(self, gmap: dtsdf.Map, sensors: Sequence, *, slots: int = 32,
+                 budget_bytes: Optional[int] = None, memory_fraction: float = 0.01,
+                 dim: int = 7, iters=(10, 5, 4),
                  params: dtsdf.IcpParams = dtsdf.IcpParams(), min_step: float = 1e-6,
                  z_near: float = 0.2, z_far: float = 10.0, stream=None):
+        """`slots`: most requests on the device at once (the largest batch).  The request
+        buffers come out of one device allocation of `budget_bytes`, or of
+        `memory_fraction` of the device memory free at start-up (hipMemGetInfo); a request
+        is admitted only when its own sensor's buffers fit in what is left of it."""
         self.map = gmap
         self.sensors = list(sensors)          # list of (cam, depth_scale)
         self.dim = dim
@@ -88,37 +164,55 @@ class Server:
         self.min_step = min_step
         self.z_near, self.z_far = z_near, z_far
         self.stream = stream
+        dev = torch.device("cuda", torch.cuda.current_device())
+        free, _ = torch.cuda.mem_get_info(dev)
         biggest = max(request_bytes(c, self.L) for c, _ in self.sensors)
-        self.budget = budget_bytes if budget_bytes is not None else 8 * biggest
+        self.budget = int(budget_bytes if budget_bytes is not None else memory_fraction * free)
         if self.budget < biggest:
             raise ValueError(f"memory budget {self.budget} B is below one request of the "
                              f"largest sensor ({biggest} B)")
+        if self.budget > free:
+            raise ValueError(f"memory budget {self.budget} B exceeds the free device memory "
+                             f"({free} B)")
         if slots < 1:
             raise ValueError("at least one slot is needed")
-        self.in_use = 0
+        self.arena = Arena(self.budget, dev)
         self.peak_bytes = 0
-        dev = torch.device("cuda", torch.cuda.current_device())
-        self._slots: List[_Slot] = []
-        # slot buffers are sized for the largest sensor and reused (no allocation per request)
-        Wm = max(c.width for c, _ in self.sensors)
-        Hm = max(c.height for c, _ in self.sensors)
-        for _ in range(slots):
-            live, model = [], []
-            for l in range(self.L):
-                w, h = Wm >> l, Hm >> l
-                live.append(dict(depth=torch.empty(h * w, dtype=torch.float32, device=dev),
-                                 vertex=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
-                                 normal=torch.empty(3 * h * w, dtype=torch.float32, device=dev)))
-                model.append(dict(vertex=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
-                                  normal=torch.empty(3 * h * w, dtype=torch.float32, device=dev),
-                                  mask=torch.empty(h * w, dtype=torch.uint8, device=dev)))
-            self._slots.append(_Slot(
-                live_levels=live, model_levels=model,
-                pose=torch.zeros((4, 4), dtype=torch.float64, device=dev),
-                active=torch.zeros(1, dtype=torch.int32, device=dev),
-                result=torch.zeros(dtsdf.ICP_RESULT_BYTES, dtype=torch.uint8, device=dev)))
+        self._slots: List[_Slot] = [
+            _Slot(pose=torch.zeros((4, 4), dtype=torch.float64, device=dev),
+                  active=torch.zeros(1, dtype=torch.int32, device=dev),
+                  result=torch.zeros(dtsdf.ICP_RESULT_BYTES, dtype=torch.uint8, device=dev))
+            for _ in range(slots)]
         self.rounds = 0
         self.batch_sizes: List[int] = []
+        self.deferred = 0      # rounds whose next admission waited for memory
+
+    @property
+    def in_use(self) -> int:
+        return self.arena.in_use
+
+    @property
+    def slots_count(self) -> int:
+        return len(self._slots)
+
+    def _carve(self, s: _Slot, req: Request) -> bool:
+        """Carves the request's buffers out of the arena into the slot; False if they do
+        not fit."""
+        cam, _ = self.sensors[req.sensor]
+        need = request_bytes(cam, self.L)
+        off = self.arena.alloc(need)
+        if off is None:
+            return False
+        s.block = (off, need)
+        s.live_levels = [dict() for _ in range(self.L)]
+        s.model_levels = [dict() for _ in range(self.L)]
+        o = off
+        for l, side, name, dt, k in _buffers(cam, self.L):
+            (s.live_levels if side == "live" else s.model_levels)[l][name] = \
+                self.arena.view(o, dt, k)
+            o += _aligned(_nbytes(dt, k))
+        self.peak_bytes = max(self.peak_bytes, self.arena.in_use)
+        return True
 
     # -- per-request set-up --------------------------------------------------------------
     def _views(self, s: _Slot, req: Request):
@@ -203,16 +297,13 @@ class Server:
                     break
                 if s.req is not None:
                     continue
-                cam, _ = self.sensors[queue[0].sensor]
-                need = request_bytes(cam, self.L)
-                if self.in_use + need > self.budget:
+                if not self._carve(s, queue[0]):
+                    self.deferred += 1
                     break
                 req = queue.popleft()
                 req.admitted = t
                 req.slot = si
-                s.req, s.level, s.it, s.need = req, self.L - 1, 0, need
-                self.in_use += need
-                self.peak_bytes = max(self.peak_bytes, self.in_use)
+                s.req, s.level, s.it = req, self.L - 1, 0
                 self._prepare_live(s, req)
                 s.stage = torch.from_numpy(np.ascontiguousarray(req.dT0, np.float64)).pin_memory()
                 s.pose.copy_(s.stage, non_blocking=True)
@@ -248,7 +339,10 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 leaving.append((ev, s.req, hp, hr))
-                self.in_use -= s.need
+                # the buffers stay readable through the slot until the memory is handed out
+                # again (later work on it is ordered after this request's on the stream)
+                self.arena.release(*s.block)
+                s.block = None
                 s.req = None
         return done
 
