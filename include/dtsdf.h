@@ -365,6 +365,25 @@ dtsdf_status icp_step_batch(int32_t n, const dtsdf_icp_req* reqs, void* stream);
 dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* reqs, int32_t iterations,
                                   void* stream);
 
+/* Intrinsics of pyramid level `level` of a camera (Sec. 5, the pyramid of registration):
+ * width and height halved `level` times, f / 2^level and c_l = (c + 0.5) / 2^level - 0.5
+ * (pixel centres at integer coordinates, each level pixel the mean of a 2x2 block), computed
+ * in double and rounded to float.  0 <= level <= 15; a level with no pixels is
+ * DTSDF_E_INVAL.  Host function. */
+dtsdf_status dtsdf_level_intrinsics(const dtsdf_intrinsics* in, int32_t level,
+                                    dtsdf_intrinsics* out);
+
+/* Coarse-to-fine registration of one request on the device (Sec. 5: the levels of the
+ * pyramid, coarsest first): reqs[l] describes level l (0 finest; live and model images and
+ * intrinsics of that level) and all levels share one device pose and carry a device
+ * convergence flag.  For l = levels-1 .. 0 the flag is raised and iterations[l] steps of
+ * icp_step_batch_iters run (a converged or degenerate level skips its remaining steps on the
+ * device; 0 skips the level).  Enqueues on `stream` with no host wait; the pose is
+ * T_model_live after the finest level.  DTSDF_E_INVAL if the levels do not share one pose,
+ * a flag is missing, or a count is outside 0..1000. */
+dtsdf_status dtsdf_icp_pyramid(int32_t levels, const dtsdf_icp_req* reqs,
+                               const int32_t* iterations, void* stream);
+
 /* icp_step_batch_iters for callers that cannot allocate memory: code under HIP graph
  * capture, tight serving loops and harnesses that forbid allocation.  Same arguments,
  * semantics and results as icp_step_batch_iters, for at most DTSDF_NOALLOC_MAX_REQUESTS

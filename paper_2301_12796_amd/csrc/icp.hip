@@ -941,6 +941,49 @@ extern "C" dtsdf_status icp_step_batch_iters(int32_t n, const dtsdf_icp_req* req
   return rs != DTSDF_OK ? rs : rr;
 }
 
+namespace {
+__global__ void set_flag_k(int32_t* flag) {
+  if (threadIdx.x == 0) *flag = 1;
+}
+}  // namespace
+
+extern "C" dtsdf_status dtsdf_level_intrinsics(const dtsdf_intrinsics* in, int32_t level,
+                                               dtsdf_intrinsics* out) {
+  if (!in || !out || level < 0 || level > 15 || in->width <= 0 || in->height <= 0)
+    return DTSDF_E_INVAL;
+  const double s = (double)(1 << level);
+  dtsdf_intrinsics o;
+  o.width = in->width >> level;
+  o.height = in->height >> level;
+  if (o.width <= 0 || o.height <= 0) return DTSDF_E_INVAL;
+  o.fx = (float)((double)in->fx / s);
+  o.fy = (float)((double)in->fy / s);
+  o.cx = (float)(((double)in->cx + 0.5) / s - 0.5);
+  o.cy = (float)(((double)in->cy + 0.5) / s - 0.5);
+  *out = o;
+  return DTSDF_OK;
+}
+
+extern "C" dtsdf_status dtsdf_icp_pyramid(int32_t levels, const dtsdf_icp_req* reqs,
+                                          const int32_t* iterations, void* stream) {
+  if (levels < 1 || levels > 16 || !reqs || !iterations) return DTSDF_E_INVAL;
+  for (int l = 0; l < levels; ++l)
+    if (reqs[l].pose != reqs[0].pose || !reqs[l].active || iterations[l] < 0 ||
+        iterations[l] > 1000)
+      return DTSDF_E_INVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  for (int l = levels - 1; l >= 0; --l) {
+    if (iterations[l] == 0) continue;
+    // every level starts afresh: its convergence flag is raised on the device, in stream
+    // order after the previous level's steps
+    hipLaunchKernelGGL(set_flag_k, dim3(1), dim3(64), 0, hs, reqs[l].active);
+    DTSDF_HIP(hipGetLastError());
+    const dtsdf_status st = icp_step_batch_iters(1, &reqs[l], iterations[l], stream);
+    if (st != DTSDF_OK) return st;
+  }
+  return DTSDF_OK;
+}
+
 extern "C" dtsdf_status icp_step_batch_iters_noalloc(int32_t n, const dtsdf_icp_req* reqs,
                                                      int32_t iterations, void* stream) {
   if (n < 0 || (n > 0 && !reqs) || n > kNoAllocMaxRequests || iterations < 1 ||

@@ -149,7 +149,8 @@ EXPORTED = ["dtsdf_create", "dtsdf_destroy", "dtsdf_get_info", "dtsdf_integrate"
             "icp_step_rgb", "icp_step_lm", "dtsdf_intensity", "dtsdf_intensity_downsample",
             "dtsdf_depth_filter", "dtsdf_normal_filter", "dtsdf_depth_error", "dtsdf_recycle",
             "dtsdf_integrate_normals", "icp_step_batch_iters",
-            "icp_step_batch_iters_noalloc", "dtsdf_status_string"]
+            "icp_step_batch_iters_noalloc", "dtsdf_level_intrinsics", "dtsdf_icp_pyramid",
+            "dtsdf_status_string"]
 
 _lib.dtsdf_status_string.restype = ctypes.c_char_p
 _lib.dtsdf_status_string.argtypes = [ctypes.c_int]
@@ -169,6 +170,8 @@ _lib.icp_step.argtypes = [ctypes.POINTER(_Image), ctypes.POINTER(_Image), ctypes
 _lib.dtsdf_render_batch.argtypes = [_V, ctypes.c_int32, ctypes.POINTER(_RenderReq), _V]
 _lib.icp_step_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), _V]
 _lib.icp_step_batch_iters.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq), ctypes.c_int32, _V]
+_lib.dtsdf_icp_pyramid.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq),
+                                   ctypes.POINTER(ctypes.c_int32), _V]
 _lib.icp_step_batch_iters_noalloc.argtypes = [ctypes.c_int32, ctypes.POINTER(_IcpReq),
                                               ctypes.c_int32, _V]
 NOALLOC_MAX_REQUESTS = 16
@@ -193,6 +196,8 @@ _lib.dtsdf_combine.argtypes = [_V, _V, _D16, _D16, ctypes.POINTER(_Intr), ctypes
                                ctypes.c_int32, _V]
 _lib.dtsdf_recombine_decide.argtypes = [ctypes.POINTER(_RecombineState), _D16,
                                         ctypes.POINTER(ctypes.c_int32)]
+_lib.dtsdf_level_intrinsics.argtypes = [ctypes.POINTER(_Intr), ctypes.c_int32,
+                                        ctypes.POINTER(_Intr)]
 for _f in EXPORTED:
     if _f != "dtsdf_status_string":
         getattr(_lib, _f).restype = ctypes.c_int
@@ -878,20 +883,19 @@ def icp_device(live_depth: torch.Tensor, live_cam, model_levels, T0, dim: int = 
     dev = live_depth.device
     pose = torch.tensor(np.asarray(T0, np.float64), dtype=torch.float64, device=dev)
     active = torch.ones(1, dtype=torch.int32, device=dev)
-    for l in reversed(range(L)):
+    reqs = (_IcpReq * L)()
+    photos = []       # kept alive until the call has copied them
+    for l in range(L):
         cam_l, v, n = live[l]
         mv, mn, mm, mcam = model_levels[l]
-        active.fill_(1)
-        st = icp_request_struct(IcpRequest(v, n, cam_l, mv, mn, mm, mcam, pose, active, None,
-                                           dim, params, min_step))
-        ph = None
+        reqs[l] = icp_request_struct(IcpRequest(v, n, cam_l, mv, mn, mm, mcam, pose, active,
+                                                None, dim, params, min_step))
         if ipyr is not None:
             ri, rcam = ref_levels[l]
-            ph = Photo(ipyr[l], ri, rcam, Tref, lam, max_error[l]).c_struct(cam_l)
-            st.photo = ctypes.addressof(ph)
-        reqs = (_IcpReq * 1)(st)
-        _check(_lib.icp_step_batch_iters(1, reqs, int(iters[l]), _stream(stream)),
-               "icp_step_batch_iters")
+            photos.append(Photo(ipyr[l], ri, rcam, Tref, lam, max_error[l]).c_struct(cam_l))
+            reqs[l].photo = ctypes.addressof(photos[-1])
+    its = (ctypes.c_int32 * L)(*[int(i) for i in iters])
+    _check(_lib.dtsdf_icp_pyramid(L, reqs, its, _stream(stream)), "dtsdf_icp_pyramid")
     return pose.cpu().numpy()
 
 
@@ -906,9 +910,10 @@ class LevelCamera:
 
 
 def level_camera(cam, l: int):
-    """Intrinsics of pyramid level l: f / 2^l, c_l = (c + 0.5) / 2^l - 0.5."""
+    """Intrinsics of pyramid level l (dtsdf_level_intrinsics); level 0 is `cam` itself."""
     if l == 0:
         return cam
-    s = float(2 ** l)
-    return LevelCamera(int(cam.width) >> l, int(cam.height) >> l, cam.fx / s, cam.fy / s,
-                       (cam.cx + 0.5) / s - 0.5, (cam.cy + 0.5) / s - 0.5)
+    o = _Intr()
+    _check(_lib.dtsdf_level_intrinsics(ctypes.byref(_intr(cam)), int(l), ctypes.byref(o)),
+           "dtsdf_level_intrinsics")
+    return LevelCamera(o.width, o.height, o.fx, o.fy, o.cx, o.cy)

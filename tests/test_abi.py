@@ -78,3 +78,31 @@ def test_argument_validation_without_device():
     assert lib.dtsdf_integrate_normals(None, a, None, None, None, None, 1.0, None, None) == E_INVAL
     lib.icp_step_lm.argtypes = [V] * 3 + [ctypes.c_int32] + [V] * 4
     assert lib.icp_step_lm(None, None, None, 7, None, None, None, None) == E_INVAL
+
+
+def test_level_intrinsics_without_device():
+    """dtsdf_level_intrinsics (a host function): f / 2^l and c_l = (c + 0.5) / 2^l - 0.5 in
+    double, rounded to float; the image halved l times; bad levels and empty levels refused."""
+    class Intr(ctypes.Structure):
+        _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                    ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                    ("cy", ctypes.c_float)]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2301_12796_amd", "libdtsdf.so"))
+    f32 = lambda x: ctypes.c_float(x).value   # noqa: E731
+    for cam in ((640, 480, 525.0, 525.0, 319.5, 239.5), (848, 480, 601.37, 598.2, 423.5, 239.5),
+                (1279, 719, 1004.9, 1004.9, 638.25, 359.75)):
+        src = Intr(*cam)
+        for l in range(4):
+            out = Intr()
+            assert lib.dtsdf_level_intrinsics(ctypes.byref(src), l, ctypes.byref(out)) == 0
+            s = float(2 ** l)
+            assert (out.width, out.height) == (cam[0] >> l, cam[1] >> l)
+            assert out.fx == f32(f32(cam[2]) / s) and out.fy == f32(f32(cam[3]) / s)
+            assert out.cx == f32((f32(cam[4]) + 0.5) / s - 0.5)
+            assert out.cy == f32((f32(cam[5]) + 0.5) / s - 0.5)
+    out = Intr()
+    assert lib.dtsdf_level_intrinsics(ctypes.byref(Intr(640, 480, 1, 1, 0, 0)), -1,
+                                      ctypes.byref(out)) != 0
+    assert lib.dtsdf_level_intrinsics(ctypes.byref(Intr(4, 4, 1, 1, 0, 0)), 3,
+                                      ctypes.byref(out)) != 0
+    assert lib.dtsdf_level_intrinsics(None, 1, ctypes.byref(out)) != 0
