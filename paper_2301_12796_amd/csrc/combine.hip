@@ -326,7 +326,8 @@ dtsdf_status mirror_blocks(const dtsdf_map* src, dtsdf_map* vol, hipStream_t st)
   hipLaunchKernelGGL(mirror_k, dim3((src->buckets + 255) / 256), dim3(256), 0, st, src->entries,
                      src->buckets, vol->entries, vol->req, vol->buckets - 1, vol->counters,
                      max_entries);
-  launch_assign(vol, st);
+  const dtsdf_status as = launch_assign(vol, st);
+  if (as != DTSDF_OK) return as;
   launch_bbox(vol, st);
   int32_t c[10];
   DTSDF_HIP(hipMemcpyAsync(c, vol->counters, sizeof(c), hipMemcpyDeviceToHost, st));

@@ -348,6 +348,13 @@ struct dtsdf_map {
   // grows; counters[10] holds their number on the device, n_free its host mirror
   int32_t* free_list;
   int64_t n_free;
+  // deterministic allocation: the frame's new (block key << 3 | D) requests and their hash
+  // slots, double buffered for the radix sort, and the sort's scratch (grown on demand)
+  uint64_t* alloc_keys;
+  uint32_t* alloc_vals;
+  int64_t alloc_cap;
+  void* sort_tmp;
+  size_t sort_tmp_bytes;
   // bricks whose voxels may project into the frame being fused (counters[11] of them)
   int32_t* vis_list;
   // per listed brick of the frame: voxels whose distance / colour were updated (allocated
@@ -430,8 +437,13 @@ dtsdf_status ensure_grid(dtsdf_map* m, const int32_t* hb, hipStream_t st);
 dtsdf_status launch_index_update(dtsdf_map* m, hipStream_t st);
 // All of the above (synchronises `st`).
 dtsdf_status rebuild_index(dtsdf_map* m, hipStream_t st);
-// Enqueues the pool-index assignment of requested (block, D) bricks.
-void launch_assign(dtsdf_map* m, hipStream_t st);
+// Pool indices for the requested (block, D) bricks without one, handed out in ascending
+// (block key, D) order (recycled indices first, in ascending order, then the pool's unused
+// end), so the pool layout and the requests dropped at capacity do not depend on thread
+// order.  Synchronises `st` once (the request count sizes the sort).
+dtsdf_status launch_assign(dtsdf_map* m, hipStream_t st);
+// Sorts the free list ascending (after recycling pushed to it in thread order).
+dtsdf_status sort_free_list(dtsdf_map* m, hipStream_t st);
 // rebuild_index with every grid cell cleared first (blocks may have disappeared).
 dtsdf_status rebuild_index_cleared(dtsdf_map* m, hipStream_t st);
 }

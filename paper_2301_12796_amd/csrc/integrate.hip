@@ -5,7 +5,8 @@
 //                        depth image, one thread per pixel, float64 arithmetic
 //   2. request_k         (sparse maps) block requests along p +/- tau r for every direction
 //                        with w_dir > 0, inserted into the spatial hash by CAS
-//   3. assign_k          pool indices for newly requested (block, D) bricks
+//   3. collect_k,        pool indices for newly requested (block, D) bricks, handed out in
+//      assign_sorted_k   sorted (block key, D) order (a radix sort between the two)
 //   4. carve_guard_k     the carving guard of every pixel (depth jumps within two pixels)
 //   5. cull_k            conservative frustum test per brick: the list of bricks to visit
 //   6. fuse_k            voxel-projection fusion of every listed brick, one workgroup per
@@ -13,8 +14,11 @@
 // Geometry (projection, point-to-plane distance) is evaluated in float64 so that the
 // discrete decisions (pixel association, band tests) match an exact evaluation except on
 // measure-zero ties; the running averages are float32, as stored.
+#include <algorithm>
 #include <cmath>
 #include <vector>
+
+#include <hipcub/hipcub.hpp>
 
 #include "dtsdf_internal.hpp"
 
@@ -129,38 +133,77 @@ __global__ __launch_bounds__(256) void request_k(const float* __restrict__ depth
   }
 }
 
-// Pool indices come from the free list of recycled bricks first (counters[10] entries of
-// free_list; a pop below zero falls through to the pool, and the bounding-box reset that
-// follows every allocation clamps the count at zero), then from the unused end of the pool
-// (counters[0]).
-__global__ __launch_bounds__(256) void assign_k(HashEntry* entries, uint32_t* req, int4* bkey,
-                                                const int32_t* __restrict__ free_list,
-                                                uint32_t buckets, uint32_t capacity,
-                                                int32_t* counters) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+// The frame's new brick requests, one entry per (block, direction) still without a brick:
+// sort key (block key << 3 | D) and the block's hash slot, appended in thread order (the
+// sort that follows fixes the order).  counters[14] counts them, also past `cap` (then the
+// host grows the buffers and collects again).
+__global__ __launch_bounds__(256) void collect_k(const HashEntry* __restrict__ entries,
+                                                 uint32_t* req, uint32_t buckets,
+                                                 uint64_t* keys, uint32_t* vals, int64_t cap,
+                                                 int32_t* counters) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= buckets) return;
-  uint32_t r = req[s];
+  const uint32_t r = req[s];
   if (!r) return;
-  req[s] = 0;
-  int bx, by, bz;
-  unpack_key(entries[s].key, bx, by, bz);
   for (int d = 0; d < 6; ++d) {
     if (!((r >> d) & 1u) || entries[s].brick[d] >= 0) continue;
-    int idx = -1;
-    const int f = __atomic_load_n(&counters[10], __ATOMIC_RELAXED) > 0
-                      ? atomicSub(&counters[10], 1) - 1 : -1;
-    if (f >= 0) {
-      idx = free_list[f];
-    } else {
-      const int b = atomicAdd(&counters[0], 1);
-      if (b < (int)capacity) idx = b;
-      else atomicAdd(&counters[1], 1);
-    }
-    if (idx >= 0) {
-      entries[s].brick[d] = idx;
-      bkey[idx] = make_int4(bx, by, bz, d);
+    const int i = atomicAdd(&counters[14], 1);
+    if (i < cap) {
+      keys[i] = (entries[s].key << 3) | (uint64_t)d;
+      vals[i] = s;
     }
   }
+}
+
+// Pool index of the i-th request in (block key, D) order: the free list of recycled bricks
+// first (ascending, popped from its end: counters[10] entries), then the unused end of the
+// pool (counters[0]); beyond the capacity the request is dropped.  Counters are read here
+// and updated by assign_counts_k afterwards.
+__global__ __launch_bounds__(256) void assign_sorted_k(const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ vals, int n,
+                                                       HashEntry* entries, int4* bkey,
+                                                       const int32_t* __restrict__ free_list,
+                                                       uint32_t capacity,
+                                                       const int32_t* __restrict__ counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int free_n = max(counters[10], 0);
+  int idx;
+  if (i < free_n) {
+    idx = free_list[free_n - 1 - i];
+  } else {
+    const int64_t j = (int64_t)counters[0] + (i - free_n);
+    idx = j < (int64_t)capacity ? (int)j : -1;
+  }
+  if (idx < 0) return;
+  const uint64_t kd = keys[i];
+  const int d = (int)(kd & 7u);
+  int bx, by, bz;
+  unpack_key(kd >> 3, bx, by, bz);
+  entries[vals[i]].brick[d] = idx;
+  bkey[idx] = make_int4(bx, by, bz, d);
+}
+
+__global__ __launch_bounds__(256) void clear_req_k(uint32_t* req, uint32_t buckets) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < buckets) req[s] = 0;
+}
+
+__global__ void zero_counter_k(int32_t* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
+__global__ void assign_counts_k(int n, uint32_t capacity, int32_t* counters) {
+  if (threadIdx.x != 0) return;
+  const int free_n = max(counters[10], 0);
+  const int popped = min(free_n, n);
+  counters[10] = free_n - popped;
+  const int rest = n - popped;
+  const int room = max(0, (int)capacity - counters[0]);
+  const int taken = min(rest, room);
+  counters[0] += taken;
+  counters[1] += rest - taken;
+  counters[14] = 0;
 }
 
 // The carving guard of Sec. 3 per pixel: carving through pixel p is allowed unless a valid
@@ -432,10 +475,93 @@ void launch_clamp_handed(dtsdf_map* m, hipStream_t st) {
 }
 
 // Every caller runs launch_bbox next, which clamps the free-list count.
-void launch_assign(dtsdf_map* m, hipStream_t st) {
-  hipLaunchKernelGGL(assign_k, dim3((m->buckets + 255) / 256), dim3(256), 0, st, m->entries,
-                     m->req, m->bkey, m->free_list, m->buckets, m->p.brick_capacity,
+namespace {
+// Grows the request buffers to `n` entries and the sort scratch to what sorting them needs.
+dtsdf_status ensure_alloc_buffers(dtsdf_map* m, int64_t n, hipStream_t st) {
+  if (n > m->alloc_cap) {
+    DTSDF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(m->alloc_keys);
+    (void)hipFree(m->alloc_vals);
+    m->alloc_keys = nullptr;
+    m->alloc_vals = nullptr;
+    m->alloc_cap = 0;
+    const int64_t cap = std::max<int64_t>(n, 1 << 16) * 5 / 4;
+    if (hipMalloc(&m->alloc_keys, sizeof(uint64_t) * 2 * cap) != hipSuccess ||
+        hipMalloc(&m->alloc_vals, sizeof(uint32_t) * 2 * cap) != hipSuccess)
+      return DTSDF_E_NOMEM;
+    m->alloc_cap = cap;
+  }
+  size_t need = 0;
+  DTSDF_HIP(hipcub::DeviceRadixSort::SortPairs(
+      nullptr, need, m->alloc_keys, m->alloc_keys + m->alloc_cap, m->alloc_vals,
+      m->alloc_vals + m->alloc_cap, (int)m->alloc_cap, 0, 63, st));
+  size_t need_free = 0;
+  DTSDF_HIP(hipcub::DeviceRadixSort::SortKeys(
+      nullptr, need_free, m->free_list, m->free_list, (int)m->p.brick_capacity, 0, 32, st));
+  need = std::max(need, need_free);
+  if (need > m->sort_tmp_bytes) {
+    DTSDF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(m->sort_tmp);
+    m->sort_tmp = nullptr;
+    m->sort_tmp_bytes = 0;
+    if (hipMalloc(&m->sort_tmp, need) != hipSuccess) return DTSDF_E_NOMEM;
+    m->sort_tmp_bytes = need;
+  }
+  return DTSDF_OK;
+}
+}  // namespace
+
+dtsdf_status launch_assign(dtsdf_map* m, hipStream_t st) {
+  if (m->alloc_cap == 0) {
+    const dtsdf_status s0 = ensure_alloc_buffers(m, 1 << 16, st);
+    if (s0 != DTSDF_OK) return s0;
+  }
+  const dim3 gb((m->buckets + 255) / 256);
+  int32_t n = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    hipLaunchKernelGGL(zero_counter_k, dim3(1), dim3(64), 0, st, m->counters + 14);
+    hipLaunchKernelGGL(collect_k, gb, dim3(256), 0, st, m->entries, m->req, m->buckets,
+                       m->alloc_keys, m->alloc_vals, m->alloc_cap, m->counters);
+    DTSDF_HIP(hipMemcpyAsync(&n, m->counters + 14, sizeof(n), hipMemcpyDeviceToHost, st));
+    DTSDF_HIP(hipStreamSynchronize(st));
+    if (n <= m->alloc_cap) break;
+    // more requests than the buffers hold: grow them and collect again (the request bits
+    // are still set)
+    const dtsdf_status sg = ensure_alloc_buffers(m, n, st);
+    if (sg != DTSDF_OK) return sg;
+  }
+  if (n > m->alloc_cap) return DTSDF_E_NOMEM;
+  hipLaunchKernelGGL(clear_req_k, gb, dim3(256), 0, st, m->req, m->buckets);
+  if (n > 0) {
+    uint64_t* k_in = m->alloc_keys;
+    uint64_t* k_out = m->alloc_keys + m->alloc_cap;
+    uint32_t* v_in = m->alloc_vals;
+    uint32_t* v_out = m->alloc_vals + m->alloc_cap;
+    size_t bytes = m->sort_tmp_bytes;
+    DTSDF_HIP(hipcub::DeviceRadixSort::SortPairs(m->sort_tmp, bytes, k_in, k_out, v_in, v_out,
+                                                 n, 0, 63, st));
+    hipLaunchKernelGGL(assign_sorted_k, dim3((n + 255) / 256), dim3(256), 0, st, k_out, v_out,
+                       n, m->entries, m->bkey, m->free_list, m->p.brick_capacity,
+                       m->counters);
+  }
+  hipLaunchKernelGGL(assign_counts_k, dim3(1), dim3(64), 0, st, n, m->p.brick_capacity,
                      m->counters);
+  DTSDF_HIP(hipGetLastError());
+  return DTSDF_OK;
+}
+
+dtsdf_status sort_free_list(dtsdf_map* m, hipStream_t st) {
+  if (m->n_free <= 1) return DTSDF_OK;
+  // sorted into the request key buffer (grown to hold the list) and copied back
+  const dtsdf_status s0 = ensure_alloc_buffers(m, std::max<int64_t>(m->n_free / 2 + 1, 1 << 16), st);
+  if (s0 != DTSDF_OK) return s0;
+  int32_t* tmp = reinterpret_cast<int32_t*>(m->alloc_keys);
+  size_t bytes = m->sort_tmp_bytes;
+  DTSDF_HIP(hipcub::DeviceRadixSort::SortKeys(m->sort_tmp, bytes, m->free_list, tmp,
+                                              (int)m->n_free, 0, 32, st));
+  DTSDF_HIP(hipMemcpyAsync(m->free_list, tmp, sizeof(int32_t) * m->n_free,
+                           hipMemcpyDeviceToDevice, st));
+  return DTSDF_OK;
 }
 
 }  // namespace dtsdf
@@ -506,7 +632,8 @@ dtsdf_status integrate_impl(dtsdf_map* m, const float* depth, const float* norma
     hipLaunchKernelGGL(request_k, grd, blk, 0, st, depth, nmap, in, (double)depth_scale, T,
                        voxel, tau, J, m->p.theta, m->entries, m->req, m->buckets - 1,
                        m->counters, max_entries);
-    launch_assign(m, st);
+    const dtsdf_status as = launch_assign(m, st);
+    if (as != DTSDF_OK) return as;
     launch_bbox(m, st);
     int32_t c[11];
     DTSDF_HIP(hipMemcpyAsync(c, m->counters, sizeof(c), hipMemcpyDeviceToHost, st));

@@ -116,6 +116,9 @@ void free_map(dtsdf_map* m) {
   (void)hipFree(m->free_list);
   (void)hipFree(m->vis_list);
   (void)hipFree(m->fuse_cnt);
+  (void)hipFree(m->alloc_keys);
+  (void)hipFree(m->alloc_vals);
+  (void)hipFree(m->sort_tmp);
   (void)hipFree(m->carve_ok);
   (void)hipFree(m->vmap);
   (void)hipFree(m->nmap);

@@ -91,5 +91,9 @@ extern "C" dtsdf_status dtsdf_recycle(dtsdf_map* m, float t_free, int64_t* recyc
   DTSDF_HIP(hipStreamSynchronize(st));
   m->n_free = nf;
   if (recycled) *recycled = nf - before;
+  // the free list was pushed in thread order: sorted, allocation hands its indices out in a
+  // fixed order
+  const dtsdf_status ss = sort_free_list(m, st);
+  if (ss != DTSDF_OK) return ss;
   return rebuild_index_cleared(m, st);
 }

@@ -311,6 +311,28 @@ def test_precision_room30_vs_fp64_oracle(dtsdf, room30):
         assert q["mask_mismatch"] < 1e-2 and q["color_p99"] <= 8, (name, q)
 
 
+def test_allocation_is_deterministic_at_capacity(dtsdf):
+    """New bricks are handed out in (block, direction) order, so which requests a full pool
+    drops, and the whole map, do not depend on thread order: two maps fused from the same
+    room frames into a pool too small for them come out equal.  (The hash table is sized so
+    that it does not fill: a full table refuses new blocks in the order they arrive.)"""
+    frames = synth.room_frames(range(0, 300, 60), device="cuda")
+    blobs, drops = [], []
+    for run in range(2):
+        print(f"case: room 5 frames into a 12000-brick pool, run {run}", flush=True)
+        gm = dtsdf.Map(P.room_gpu_params(dtsdf, capacity=12000, buckets=1 << 20))
+        dropped = 0
+        for f in frames:
+            st = gm.integrate(_dev(f["depth"]), _dev(f["rgb"]), P.ROOM_CAM, f["T_wc"],
+                              stats=True)
+            dropped += st["dropped"]
+        drops.append(dropped)
+        blobs.append(gm.export())
+    assert drops[0] == drops[1] and drops[0] > 0, drops
+    for key in ("keys", "sdf", "w", "rgb", "wc"):
+        assert np.array_equal(blobs[0][key], blobs[1][key]), key
+
+
 def test_empty_map_renders_nothing(dtsdf):
     gm = dtsdf.Map(P.room_gpu_params(dtsdf, capacity=64, buckets=256))
     out = P.to_numpy_out(gm.render(P.ROOM_CAM, synth.room_pose(3)))
