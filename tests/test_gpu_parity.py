@@ -259,14 +259,31 @@ def test_precision_room30_vs_fp64_oracle(dtsdf, room30):
     GPU into plain (float32), f16 and i16 maps (u8 square-law weights for the packed ones),
     rendered at five poses; depth, normal, colour and mask against the oracle's FP64 render
     of its own FP64 map of the same frames at 20,000 sampled pixels per pose, no pixel
-    exempt.  Reported per form; the plain map shows what float32 arithmetic alone does, the
-    packed forms add their quantisation."""
+    exempt; and the Sim(3) registration of a second sensor whose depth is scaled by a seeded
+    factor (three levels, 10/5/4) against each map's renders, against the oracle's on its
+    FP64 renders from the same start.  Reported per form; the plain map shows what float32
+    arithmetic alone does, the packed forms add their quantisation."""
     om, frames = room30
     poses = [synth.room_pose(k) for k in (100, 107, 114, 121, 128)]
     refs = []
     for k, T in zip((100, 107, 114, 121, 128), poses):
         pix = P.random_pixels(P.ROOM_CAM, 20000, seed=1000 + k)
         refs.append((pix, om.render(P.ROOM_CAM, T, pixels=pix, classify=False)))
+    # the oracle's Sim(3) registration of the scaled second sensor on its own renders
+    s_sensor = synth.precision_scale()
+    T_reg = synth.room_pose(110)
+    live_s = synth.scenes.render_frame(synth.room_scene(), P.ROOM_CAM, T_reg, noise="quadratic",
+                                       sigma=0.0012, seed=7110, z_max=10.0,
+                                       depth_scale=s_sensor)["depth"]
+    dT0_s = synth.perturb_pose(0.01, np.radians(1.0), np.random.default_rng(21))
+    dT0_s[:3, :3] *= 1.01 / s_sensor
+    lo = []
+    for l in range(3):
+        c = P.ROOM_CAM.level(l)
+        r_ = om.render(c, T_reg, classify=False)
+        lo.append((r_.vertex.reshape(c.height, c.width, 3), r_.normal.reshape(c.height, c.width, 3),
+                   r_.mask.reshape(c.height, c.width), c))
+    T_o, _ = O.icp(live_s, P.ROOM_CAM, lo, dT0_s, dim=7)
     stats = {}
     for name, sf, wf in (("plain", dtsdf.SDF_F32, dtsdf.W_F32), ("f16", dtsdf.SDF_F16, dtsdf.W_U8),
                          ("i16", dtsdf.SDF_I16, dtsdf.W_U8)):
@@ -295,6 +312,16 @@ def test_precision_room30_vs_fp64_oracle(dtsdf, room30):
                   normal_p99_deg=float(np.percentile(ang, 99)),
                   color_p99=float(np.percentile(dc, 99)), mask_mismatch=mm / (5 * 20000),
                   hits=n_hit)
+        # Sim(3) registration of a second sensor (depth scaled by s) against this map's
+        # renders, against the oracle's Sim(3) ICP on its FP64 map's renders, same start
+        cam = P.ROOM_CAM
+        levels = [(o["vertex"], o["normal"], o["mask"], c) for o, c in
+                  ((gm.render(c, T_reg, outputs=("vertex", "normal", "mask")), c)
+                   for c in (dtsdf.level_camera(cam, l) for l in range(3)))]
+        T_g, _ = dtsdf.icp(_dev(live_s), cam, levels, dT0_s, dim=7)
+        d = P.twist_between(T_g, T_o, 7)
+        st.update(sim3_rot_rad=float(np.linalg.norm(d[3:6])),
+                  sim3_trans_m=float(np.linalg.norm(d[:3])), sim3_log_scale=float(abs(d[6])))
         stats[name] = st
         print(f"[precision vs FP64 oracle, room 30 frames] {name}: {st}", flush=True)
         del gm
@@ -304,11 +331,15 @@ def test_precision_room30_vs_fp64_oracle(dtsdf, room30):
     plain = stats["plain"]
     assert plain["depth_median_m"] < 1e-6 and plain["depth_p99_m"] < 1e-3
     assert plain["mask_mismatch"] < 2e-3 and plain["color_p99"] <= 1
+    assert plain["sim3_rot_rad"] < 1e-4 and plain["sim3_trans_m"] < 1e-4 and \
+        plain["sim3_log_scale"] < 1e-4, plain
     for name in ("f16", "i16"):
         q = stats[name]
         assert q["depth_median_m"] < 1e-4 and q["depth_p99_m"] < 5e-3, (name, q)
         assert q["depth_over_1cm"] < 5e-3 and q["normal_median_deg"] < 1.0, (name, q)
         assert q["mask_mismatch"] < 1e-2 and q["color_p99"] <= 8, (name, q)
+        assert q["sim3_rot_rad"] < 1e-3 and q["sim3_trans_m"] < 1e-3 and \
+            q["sim3_log_scale"] < 1e-3, (name, q)
 
 
 def test_allocation_is_deterministic_at_capacity(dtsdf):
