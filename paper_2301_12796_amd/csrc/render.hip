@@ -683,18 +683,26 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       }
       const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
       const bool pos_sub = (cinfo >> sub) & 1u;
-      const bool pos_cell =
-          pos_sub || ((cwl[cp.lo[2] * 64] >> (cp.lo[0] + 8 * cp.lo[1])) & 1ull);
+      bool pos_cell = pos_sub;
+      int ext = 4;   // edge of the positive box in cells: 4 (sub-block), 2 (cell pair group), 1
+      if (!pos_sub) {
+        // the cell, and the aligned 2x2x2 group of cells holding it (both slices of the pair)
+        const uint64_t w0 = cwl[(cp.lo[2] & 6) * 64], w1 = cwl[((cp.lo[2] & 6) + 1) * 64];
+        const uint64_t wc = (cp.lo[2] & 1) ? w1 : w0;
+        pos_cell = (wc >> (cp.lo[0] + 8 * cp.lo[1])) & 1ull;
+        const int gs = (cp.lo[0] & 6) + 8 * (cp.lo[1] & 6);
+        ext = (((w0 & w1) >> gs) & 0x303ull) == 0x303ull ? 2 : 1;
+      }
       if (pos_cell) {
-        // positive sub-block or cell: no crossing can end in it; jump to its last lattice
-        // point (evaluated only if the point after it is)
+        // positive sub-block, cell group or cell: no crossing can end in it; jump to its
+        // last lattice point (evaluated only if the point after it is)
         double lo[3], hi[3];
         const int cbv[3] = {cb0, cb1, cb2};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const int v0 = pos_sub ? cbv[ax] * kB + ((sub >> ax) & 1) * 4 : cbv[ax] * kB + cp.lo[ax];
+          const int v0 = cbv[ax] * kB + (cp.lo[ax] & ~(ext - 1));
           lo[ax] = (double)v0 * m.voxel;
-          hi[ax] = (double)(v0 + (pos_sub ? 4 : 1)) * m.voxel;
+          hi[ax] = (double)(v0 + ext) * m.voxel;
         }
         const double texit = box_exit(o, ir, lo, hi);
         const double jn = ceil((texit - 1e-6 - t0) * inv_step);
