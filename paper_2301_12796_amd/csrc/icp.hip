@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kChunks = 128;          // fixed pixel chunks per request (reduction order)
 static_assert(kChunks % 16 == 0, "the solve sums chunks sixteen at a time");
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 512;
 
 template <int DIM>
 struct Sizes {
@@ -256,7 +256,7 @@ __device__ void reduce_chunk(const IcpArgs& a, int chunk, float* __restrict__ ou
       acc[NH + DIM + 2].add(1.f);
     }
   }
-  // fixed-order tree: xor shuffles within the wave, then the four waves in LDS order
+  // fixed-order tree: xor shuffles within the wave, then the waves in LDS order
   __shared__ float lds[kReduceThreads / 64][NS][2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
