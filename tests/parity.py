@@ -297,9 +297,10 @@ def twist_between(Ta, Tb, dim):
 
 
 # change of the RMS point-to-plane residual that a pose difference along the weak directions
-# of an ill-conditioned registration may cause: a hundredth of the live frames' depth noise
-# (0.5 mm), below which two poses fit the frame indistinguishably
-RESID_TOL = 5e-6
+# of an ill-conditioned registration may cause: the translation bar of the pose (1e-5 m), a
+# fiftieth of the live frames' depth noise (0.5 mm), below which two poses fit the frame
+# indistinguishably
+RESID_TOL = 1e-5
 
 
 def pose_parity(live, cam, gpu_levels, oracle_levels, T_g, dT0, dim, *, name=""):

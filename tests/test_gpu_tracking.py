@@ -10,8 +10,8 @@ direction is the amplified difference of the inputs, not an error of the arithme
 is therefore checked as
   * the oracle's ICP on the GPU's own model pyramid (the reduction and solve alone): the pose
     difference within 1e-5 in the well-conditioned eigen-directions of H (eigenvalues above
-    1/100 of the largest) and changing the RMS residual by less than 5e-6 m (a hundredth of
-    the depth noise); the part along the weak directions (float32 sums amplified by cond(H))
+    1/100 of the largest) and changing the RMS residual by less than 1e-5 m (the translation
+    bar of the pose); the part along the weak directions (float32 sums amplified by cond(H))
     is reported;
   * the oracle's ICP on the oracle's renders of the map (render and ICP together, from the
     same start): on this scene the ten, five and four iterations stop part-way along the weak
