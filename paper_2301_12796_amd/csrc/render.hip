@@ -70,6 +70,20 @@ __device__ inline double box_exit(const double o[3], const double ir[3], const d
   return t;
 }
 
+// Parameter of the first voxel face (a plane x = j * voxel on any axis) the ray crosses after t.
+__device__ inline double face_after(const double o[3], const double r[3], const double ir[3],
+                                    double t, double voxel, double inv_voxel) {
+  double best = 1e300;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (r[ax] == 0.0) continue;
+    const double x = (o[ax] + t * r[ax]) * inv_voxel;
+    const double pl = (r[ax] > 0.0 ? floor(x) + 1.0 : ceil(x) - 1.0) * voxel;
+    best = fmin(best, (pl - o[ax]) * ir[ax]);
+  }
+  return best;
+}
+
 __device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
   const int ix = bx - m.gx0, iy = by - m.gy0, iz = bz - m.gz0;
   if (ix < 0 || iy < 0 || iz < 0 || ix >= m.gx || iy >= m.gy || iz >= m.gz) return -1;
@@ -598,7 +612,9 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
   double ta = 0.0, tb = 0.0;
   int k = 0;
   int it = 0, side = 0;
-  bool bisect = false;    // refinement: the next step is a bisection
+  bool bisect = false;    // refinement: the next step is a bisection (or a face probe)
+  bool probe = false;     // refinement: the pending point is a face probe
+  double tn = -1.0;       // refinement: Newton estimate from the last pair (-1: none)
   bool pending = false;   // te holds an evaluation point not evaluated yet
   double te = 0.0;        // parameter of the pending point
   double te2 = 0.0;       // second point evaluated with it (refinement pair, or lattice k + 1)
@@ -615,14 +631,31 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
           done = true;
           break;
         }
-        double q = 0.5;
-        if ((it & 3) != 3 && !bisect) q = (double)__fdividef(fa, fa - fb);
-        double tc = ta + (tb - ta) * q;
-        if (!(tc > ta && tc < tb)) tc = 0.5 * (ta + tb);
-        // the estimate is evaluated as a pair straddling it by kRefinePair: when the estimate
-        // is that close to the root the pair is the final bracket
-        te = fmax(tc - kRefinePair, 0.5 * (ta + tc));
-        te2 = fmin(tc + kRefinePair, 0.5 * (tc + tb));
+        probe = false;
+        if ((it & 3) != 3 && !bisect) {
+          // false position, or the Newton step of the last pair when it stays well inside
+          double tc = ta + (tb - ta) * (double)__fdividef(fa, fa - fb);
+          if (tn > ta && tn < tb) tc = tn;
+          if (!(tc > ta && tc < tb)) tc = 0.5 * (ta + tb);
+          // the estimate is evaluated as a pair straddling it by kRefinePair: when the
+          // estimate is that close to the root the pair is the final bracket
+          te = fmax(tc - kRefinePair, 0.5 * (ta + tc));
+          te2 = fmin(tc + kRefinePair, 0.5 * (tc + tb));
+        } else {
+          // f may jump where the cell changes: probe next to the first voxel face inside the
+          // bracket (just before it, or just after it once the bracket starts there); with
+          // no face inside, bisect
+          const double tf = face_after(o, r, ir, ta, m.voxel, m.inv_voxel);
+          if (tf < tb) {
+            probe = true;
+            te = tf - ta > 2.0 * kRefinePair ? tf - kRefinePair : fmin(tf + kRefinePair, 0.5 * (tf + tb));
+            te2 = te;
+          } else {
+            const double tc = 0.5 * (ta + tb);
+            te = fmax(tc - kRefinePair, 0.5 * (ta + tc));
+            te2 = fmin(tc + kRefinePair, 0.5 * (tc + tb));
+          }
+        }
         pending = true;
         break;
       }
@@ -854,7 +887,18 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
           // a false-position step that shrank the bracket by less than a tenth (one end
           // keeps a value far from the root, e.g. behind a jump of f at a cell face) is
           // followed by a bisection
-          bisect = (tb - ta) > 0.9 * w0;
+          bisect = (tb - ta) > 0.9 * w0 ||
+                   (probe && face_after(o, r, ir, ta, m.voxel, m.inv_voxel) < tb);
+          // Newton step from the pair's slope, kept when it lands within a quarter of the
+          // bracket of the pair
+          tn = -1.0;
+          if (pair && e.defined && ev[1].defined && te2 > te) {
+            const double sl = (double)(ev[1].f - e.f) / (te2 - te);
+            if (sl < 0.0) {
+              const double t_n = te - (double)e.f / sl;
+              if (fabs(t_n - te) < 0.25 * (tb - ta)) tn = t_n;
+            }
+          }
         } else if (lattice && k >= 1 && e.defined && prev_def && prev_f > 0.f && e.f <= 0.f) {
           hit = true;
           refining = true;
