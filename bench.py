@@ -226,7 +226,11 @@ def main():
         nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
         n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
         hits.append(int(out["mask"].sum()))
-        c = tcnt.view(H // 8, 8, W // 8, 8, 4).permute(0, 2, 1, 3, 4).reshape(-1, 64, 4).float()
+        # per wave: a work tile's 64 lanes take pixels interleaved over a 64x32 region
+        # (lane (lx, ly) of tile (tx, ty): u = 64 (tx // 8) + 8 lx + tx % 8, v likewise with
+        # 32, 4), so the image regroups as (gy, ly, sy, gx, lx, sx) -> waves (gy, sy, gx, sx)
+        c = tcnt.view(H // 32, 8, 4, W // 64, 8, 8, 4).permute(0, 2, 3, 5, 1, 4, 6) \
+            .reshape(-1, 64, 4).float()
         counts.append(torch.stack([c.mean((0, 1)), c.amax(1).mean(0)]).cpu().numpy())
         bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +
                               ns * RECORD_BYTES + H * W * OUT_BYTES_PER_RAY)

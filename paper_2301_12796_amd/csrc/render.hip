@@ -1,9 +1,10 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
-// One thread per pixel; a workgroup is one wave covering an 8x8 pixel tile so that its rays
-// traverse the same bricks.  Tiles are numbered so that the workgroups the dispatcher sends to
-// one XCD (workgroup id mod 8) cover one contiguous band of the image, keeping each band's
-// bricks in that XCD's L2.  Per ray:
+// One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels, taken
+// interleaved from a 64x32 pixel region (see tile_pixel) so that slow rays are spread over
+// many waves.  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
+// (workgroup id mod 8) cover one contiguous band of the image, keeping each band's bricks in
+// that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
 //     sample positions are float64 so that the cell a sample falls in is the exact one,
 //     interpolation and combination are float32;
@@ -52,6 +53,14 @@ struct RenderArgs {
   int help;       // lanes whose ray has finished evaluate points of the marching rays
 };
 
+// Work tiles and pixels.  A wave renders 64 pixels of one work tile.  The work tiles of a group
+// of kIlvX x kIlvY take interleaved pixels of the group's (8 kIlvX) x (8 kIlvY) pixel region
+// (lane (lx, ly) of tile (tx, ty) renders pixel (kIlvX (8 gx + lx) + tx mod kIlvX, ...)), so
+// that the rays of a slow image region (grazing a surface, along a silhouette) are spread over
+// many waves instead of holding one wave while its neighbours have long finished.  The tile
+// grid is padded to whole groups; lanes whose pixel lies outside the image start finished.
+constexpr int kIlvX = 8, kIlvY = 4;
+
 struct Trace {
   uint8_t* bricks;
   uint8_t* color;
@@ -82,6 +91,12 @@ __device__ inline double face_after(const double o[3], const double r[3], const 
     best = fmin(best, (pl - o[ax]) * ir[ax]);
   }
   return best;
+}
+
+__device__ inline void tile_pixel(const RenderArgs& a, int tile, int lane, int& u, int& v) {
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  u = (tx / kIlvX) * (8 * kIlvX) + kIlvX * (lane & 7) + tx % kIlvX;
+  v = (ty / kIlvY) * (8 * kIlvY) + kIlvY * (lane >> 3) + ty % kIlvY;
 }
 
 __device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
@@ -1020,8 +1035,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
   const int per = (a.tiles + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (tile >= a.tiles) return;
-  const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
-  const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
+  int u, v;
+  tile_pixel(a, tile, (int)(threadIdx.x & 63), u, v);
   render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
 }
 
@@ -1045,8 +1060,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     }
     const RenderArgs& a = reqs[lo];
     const int tile = item - prefix[lo];
-    const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
-    const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
+    int u, v;
+    tile_pixel(a, tile, (int)(threadIdx.x & 63), u, v);
     render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
   }
 }
@@ -1061,8 +1076,9 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
   if (out->flags & ~DTSDF_RENDER_ALONE) return false;
   a.W = intr->width;
   a.H = intr->height;
-  a.tiles_x = (a.W + 7) / 8;
-  a.tiles = a.tiles_x * ((a.H + 7) / 8);
+  // tile grid padded to whole interleaving groups
+  a.tiles_x = ((a.W + 7) / 8 + kIlvX - 1) / kIlvX * kIlvX;
+  a.tiles = a.tiles_x * (((a.H + 7) / 8 + kIlvY - 1) / kIlvY * kIlvY);
   a.fx = intr->fx;
   a.fy = intr->fy;
   a.cx = intr->cx;
