@@ -226,10 +226,10 @@ def main():
         nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
         n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
         hits.append(int(out["mask"].sum()))
-        # per wave: a work tile's 64 lanes take pixels interleaved over a 64x32 region
-        # (lane (lx, ly) of tile (tx, ty): u = 64 (tx // 8) + 8 lx + tx % 8, v likewise with
-        # 32, 4), so the image regroups as (gy, ly, sy, gx, lx, sx) -> waves (gy, sy, gx, sx)
-        c = tcnt.view(H // 32, 8, 4, W // 64, 8, 8, 4).permute(0, 2, 3, 5, 1, 4, 6) \
+        # per wave: a single view's work tile takes its 64 pixels interleaved over a 32x16
+        # region (lane (lx, ly) of tile (tx, ty): u = 32 (tx // 4) + 4 lx + tx % 4, v = 16 (ty
+        # // 2) + 2 ly + ty % 2), so the image regroups as (gy, ly, sy, gx, lx, sx) -> waves
+        c = tcnt.view(H // 16, 8, 2, W // 32, 8, 4, 4).permute(0, 2, 3, 5, 1, 4, 6) \
             .reshape(-1, 64, 4).float()
         counts.append(torch.stack([c.mean((0, 1)), c.amax(1).mean(0)]).cpu().numpy())
         bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +

@@ -1,8 +1,8 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
-// One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels, taken
-// interleaved from a 64x32 pixel region (see tile_pixel) so that slow rays are spread over
-// many waves.  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
+// One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels (a single
+// view's taken interleaved from a 32x16 pixel region, see tile_pixel; a batched launch's an
+// 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
 // (workgroup id mod 8) cover one contiguous band of the image, keeping each band's bricks in
 // that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
@@ -37,7 +37,8 @@ namespace {
 
 struct RenderArgs {
   int W, H;
-  int tiles_x, tiles;
+  int tiles_x, tiles;     // 8x8 pixel tiles (the batched launch)
+  int itiles_x, itiles;   // interleaved work tiles (the single-view launch, see tile_pixel)
   double fx, fy, cx, cy;
   double R[9], t[3];
   double z_near, z_far;
@@ -53,13 +54,17 @@ struct RenderArgs {
   int help;       // lanes whose ray has finished evaluate points of the marching rays
 };
 
-// Work tiles and pixels.  A wave renders 64 pixels of one work tile.  The work tiles of a group
-// of kIlvX x kIlvY take interleaved pixels of the group's (8 kIlvX) x (8 kIlvY) pixel region
-// (lane (lx, ly) of tile (tx, ty) renders pixel (kIlvX (8 gx + lx) + tx mod kIlvX, ...)), so
-// that the rays of a slow image region (grazing a surface, along a silhouette) are spread over
-// many waves instead of holding one wave while its neighbours have long finished.  The tile
-// grid is padded to whole groups; lanes whose pixel lies outside the image start finished.
-constexpr int kIlvX = 8, kIlvY = 4;
+// Work tiles of the single-view launch.  A wave renders 64 pixels of one work tile.  The work
+// tiles of a group of kIlvX x kIlvY take interleaved pixels of the group's (8 kIlvX) x
+// (8 kIlvY) pixel region (lane (lx, ly) of tile (tx, ty) renders pixel
+// (8 kIlvX gx + kIlvX lx + tx mod kIlvX, ...)), so that the rays of a slow image region
+// (grazing a surface, along a silhouette) are spread over several waves instead of holding
+// one wave while the rest of the chip idles.  Interleaving makes a wave's rays less coherent
+// (more distinct blocks per pass), which costs total work; it pays only where the launch is
+// bound by its slowest waves, so the batched launch, whose views overlap their tails, keeps
+// plain 8x8 tiles.  The tile grid is padded to whole groups; lanes whose pixel lies outside
+// the image start finished.
+constexpr int kIlvX = 4, kIlvY = 2;
 
 struct Trace {
   uint8_t* bricks;
@@ -94,7 +99,7 @@ __device__ inline double face_after(const double o[3], const double r[3], const 
 }
 
 __device__ inline void tile_pixel(const RenderArgs& a, int tile, int lane, int& u, int& v) {
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int tx = tile % a.itiles_x, ty = tile / a.itiles_x;
   u = (tx / kIlvX) * (8 * kIlvX) + kIlvX * (lane & 7) + tx % kIlvX;
   v = (ty / kIlvY) * (8 * kIlvY) + kIlvY * (lane >> 3) + ty % kIlvY;
 }
@@ -1032,9 +1037,9 @@ template <int F, bool TRACE, int G = march_group(F)>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_k(
     MapView m, RenderArgs a) {
   // XCD-aware tile order: workgroup j runs on XCD j % 8; give each XCD a contiguous band
-  const int per = (a.tiles + 7) >> 3;
+  const int per = (a.itiles + 7) >> 3;
   const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (tile >= a.tiles) return;
+  if (tile >= a.itiles) return;
   int u, v;
   tile_pixel(a, tile, (int)(threadIdx.x & 63), u, v);
   render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
@@ -1060,8 +1065,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     }
     const RenderArgs& a = reqs[lo];
     const int tile = item - prefix[lo];
-    int u, v;
-    tile_pixel(a, tile, (int)(threadIdx.x & 63), u, v);
+    const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
+    const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
     render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
   }
 }
@@ -1076,9 +1081,11 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
   if (out->flags & ~DTSDF_RENDER_ALONE) return false;
   a.W = intr->width;
   a.H = intr->height;
-  // tile grid padded to whole interleaving groups
-  a.tiles_x = ((a.W + 7) / 8 + kIlvX - 1) / kIlvX * kIlvX;
-  a.tiles = a.tiles_x * (((a.H + 7) / 8 + kIlvY - 1) / kIlvY * kIlvY);
+  a.tiles_x = (a.W + 7) / 8;
+  a.tiles = a.tiles_x * ((a.H + 7) / 8);
+  // interleaved work tiles, padded to whole groups
+  a.itiles_x = (a.tiles_x + kIlvX - 1) / kIlvX * kIlvX;
+  a.itiles = a.itiles_x * (((a.H + 7) / 8 + kIlvY - 1) / kIlvY * kIlvY);
   a.fx = intr->fx;
   a.fy = intr->fy;
   a.cx = intr->cx;
@@ -1109,7 +1116,7 @@ extern "C" dtsdf_status dtsdf_render(const dtsdf_map* m, const dtsdf_intrinsics*
                                      const dtsdf_render_out* out, void* stream) {
   RenderArgs a;
   if (!m || !fill_args(intr, T, z_near, z_far, out, a)) return DTSDF_E_INVAL;
-  const int per = (a.tiles + 7) / 8;
+  const int per = (a.itiles + 7) / 8;
   const dim3 grd(per * 8);
   const bool trace = a.trace_bricks || a.trace_color || a.trace_slots || a.trace_counts;
   const MapView v = make_view(m);
