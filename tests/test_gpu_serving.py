@@ -65,6 +65,25 @@ def test_render_batch_matches_single_renders(dtsdf, tiny_map):
     assert hits > 10000
 
 
+def test_ragged_views_single_equals_batch(dtsdf, tiny_map):
+    """Views whose sizes are not whole tiles nor whole groups of the single-view launch's
+    interleaved work tiles: every pixel written exactly once (the fill values never survive)
+    and bitwise the batched launch's (plain 8x8 tiles)."""
+    T = synth.tiny_render_pose(0.9)
+    for W, H in ((1, 1), (7, 5), (203, 77), (9, 300), (161, 121)):
+        f = 0.75 * max(W, H)
+        cam = synth.scenes.Camera(W, H, f, f, (W - 1) / 2.0, (H - 1) / 2.0)
+        print(f"case: ragged view {W}x{H}", flush=True)
+        single = _alloc(cam)
+        tiny_map.render(cam, T, 0.2, 10.0, out=single)
+        batch = _alloc(cam)
+        tiny_map.render_batch([(cam, T, 0.2, 10.0, batch)])
+        torch.cuda.synchronize()
+        assert not (single["mask"] == 77).any() and not (single["depth"] == -7.0).any()
+        for key in ("depth", "vertex", "normal", "rgba", "mask"):
+            assert torch.equal(single[key], batch[key]), (W, H, key)
+
+
 def test_render_batch_of_one_and_empty(dtsdf, tiny_map):
     cam, _ = synth.serving_sensors()[1]
     T = synth.tiny_render_pose(1.1)
