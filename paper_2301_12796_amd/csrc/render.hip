@@ -21,10 +21,9 @@
 //     gradient-free fallback W^D max(0, <v^D, -r>) (eq. combine_tsdf_weight), both summed in
 //     one pass over the directions;
 //   * hit: first k >= 1 with f(t_{k-1}) > 0 >= f(t_k), both defined; the bracket is refined
-//     with the Illinois variant of regula falsi (every fourth step a bisection) to 1e-6 m,
-//     undefined
-//     points counting as free space; outputs are evaluated at the bracket end inside the
-//     surface.
+//     to 1e-6 m (Newton or Illinois regula falsi steps, probes next to cell faces where f
+//     may jump, bisections; see kRefineTol), undefined points counting as free space; outputs
+//     are evaluated at the bracket end inside the surface.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -580,9 +579,14 @@ __device__ inline double shfl_d(double x, int src) {
 // evaluate them).
 constexpr int kMaxHelpers = 7;
 
-// Refinement of the bracket of a crossing: Illinois regula falsi, every fourth step and every
-// step after one that shrank the bracket by less than a tenth a bisection, until the bracket
-// is shorter than kRefineTol (metres along the ray) or after kRefineMaxIter evaluations.
+// Refinement of the bracket of a crossing, until it is shorter than kRefineTol (metres along
+// the ray) or after kRefineMaxIter steps.  A step evaluates a pair of points kRefinePair on
+// either side of an estimate (the pair is the final bracket when it straddles the root): the
+// Newton step from the slope of the previous pair when that lands within a quarter of the
+// bracket of it, else Illinois regula falsi.  Every fourth step, and after a step that shrank
+// the bracket by less than a tenth, the step probes next to the first voxel face inside the
+// bracket instead (f may jump where the cell changes: false position then stays pinned to
+// one end), and bisects when no face lies inside.
 constexpr double kRefineTol = 1e-6;
 constexpr double kRefinePair = 0.45 * kRefineTol;
 constexpr int kRefineMaxIter = 24;
