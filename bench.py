@@ -226,11 +226,12 @@ def main():
         nb, nc, ns = int(tb.sum()), int(tc.sum()), int(ts.sum())
         n_bd.append(nb); n_cd.append(nc); n_sl.append(ns)
         hits.append(int(out["mask"].sum()))
-        # per wave: a single view's work tile takes its 64 pixels interleaved over a 32x16
-        # region (lane (lx, ly) of tile (tx, ty): u = 32 (tx // 4) + 4 lx + tx % 4, v = 16 (ty
-        # // 2) + 2 ly + ty % 2), so the image regroups as (gy, ly, sy, gx, lx, sx) -> waves
-        c = tcnt.view(H // 16, 8, 2, W // 32, 8, 4, 4).permute(0, 2, 3, 5, 1, 4, 6) \
-            .reshape(-1, 64, 4).float()
+        # per wave: a single view's work tile takes 16 quads of 2x2 pixels interleaved over a
+        # 128x32 region (lane = 16 qy + 4 qx + 2 dy + dx of tile (tx, ty): u = 128 (tx // 16)
+        # + 32 qx + 2 (tx % 16) + dx, v = 32 (ty // 4) + 8 qy + 2 (ty % 4) + dy), so the image
+        # regroups as (gy, qy, sy, dy, gx, qx, sx, dx) -> waves (gy, sy, gx, sx)
+        c = tcnt.view(H // 32, 4, 4, 2, W // 128, 4, 16, 2, 4) \
+            .permute(0, 2, 4, 6, 1, 5, 3, 7, 8).reshape(-1, 64, 4).float()
         counts.append(torch.stack([c.mean((0, 1)), c.amax(1).mean(0)]).cpu().numpy())
         bytes_per_pose.append(nb * BRICK_MARCH_BYTES + nc * BRICK_COLOR_BYTES +
                               ns * RECORD_BYTES + H * W * OUT_BYTES_PER_RAY)

@@ -1,8 +1,8 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
 // One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels (a single
-// view's taken interleaved from a 32x16 pixel region, see tile_pixel; a batched launch's an
-// 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
+// view's taken as 2x2 quads interleaved over a 128x32 pixel region, see tile_pixel; a batched
+// launch's an 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
 // (workgroup id mod 8) cover one contiguous band of the image, keeping each band's bricks in
 // that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
@@ -53,17 +53,18 @@ struct RenderArgs {
   int help;       // lanes whose ray has finished evaluate points of the marching rays
 };
 
-// Work tiles of the single-view launch.  A wave renders 64 pixels of one work tile.  The work
-// tiles of a group of kIlvX x kIlvY take interleaved pixels of the group's (8 kIlvX) x
-// (8 kIlvY) pixel region (lane (lx, ly) of tile (tx, ty) renders pixel
-// (8 kIlvX gx + kIlvX lx + tx mod kIlvX, ...)), so that the rays of a slow image region
-// (grazing a surface, along a silhouette) are spread over several waves instead of holding
-// one wave while the rest of the chip idles.  Interleaving makes a wave's rays less coherent
-// (more distinct blocks per pass), which costs total work; it pays only where the launch is
-// bound by its slowest waves, so the batched launch, whose views overlap their tails, keeps
-// plain 8x8 tiles.  The tile grid is padded to whole groups; lanes whose pixel lies outside
-// the image start finished.
-constexpr int kIlvX = 4, kIlvY = 2;
+// Work tiles of the single-view launch.  A wave renders 64 pixels of one work tile, as 16
+// quads of 2x2 pixels.  The work tiles of a group of kIlvX x kIlvY take interleaved quads of
+// the group's (8 kIlvX) x (8 kIlvY) pixel region (quad (qx, qy) of tile (tx, ty) is quad
+// column kIlvX qx + tx mod kIlvX and row kIlvY qy + ty mod kIlvY of the region), so that the
+// rays of a slow image region (grazing a surface, along a silhouette) are spread over many
+// waves instead of holding one wave while the rest of the chip idles.  Interleaving makes a
+// wave's rays less coherent (more distinct blocks per pass; the quads keep four neighbouring
+// rays together), which costs total work; it pays only where the launch is bound by its
+// slowest waves, so the batched launch, whose views overlap their tails, keeps plain 8x8
+// tiles.  The tile grid is padded to whole groups; lanes whose pixel lies outside the image
+// start finished.
+constexpr int kIlvX = 16, kIlvY = 4;
 
 struct Trace {
   uint8_t* bricks;
@@ -99,8 +100,9 @@ __device__ inline double face_after(const double o[3], const double r[3], const 
 
 __device__ inline void tile_pixel(const RenderArgs& a, int tile, int lane, int& u, int& v) {
   const int tx = tile % a.itiles_x, ty = tile / a.itiles_x;
-  u = (tx / kIlvX) * (8 * kIlvX) + kIlvX * (lane & 7) + tx % kIlvX;
-  v = (ty / kIlvY) * (8 * kIlvY) + kIlvY * (lane >> 3) + ty % kIlvY;
+  const int dx = lane & 1, dy = (lane >> 1) & 1, qx = (lane >> 2) & 3, qy = lane >> 4;
+  u = (tx / kIlvX) * (8 * kIlvX) + 2 * (kIlvX * qx + tx % kIlvX) + dx;
+  v = (ty / kIlvY) * (8 * kIlvY) + 2 * (kIlvY * qy + ty % kIlvY) + dy;
 }
 
 __device__ inline int64_t grid_index(const MapView& m, int bx, int by, int bz) {
