@@ -1,10 +1,10 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
 // One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels (a single
-// view's taken as 2x2 quads interleaved over a 128x32 pixel region, see tile_pixel; a batched
-// launch's an 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher sends to one XCD
-// (workgroup id mod 8) cover one contiguous band of the image, keeping each band's bricks in
-// that XCD's L2.  Per ray:
+// view's taken as 2x2 quads interleaved over a 128x32 pixel region, see tile_pixel; a
+// batched launch's an 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher
+// sends to one XCD (workgroup id mod 8) cover one contiguous band of the image, keeping each
+// band's bricks in that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
 //     sample positions are float64 so that the cell a sample falls in is the exact one,
 //     interpolation and combination are float32;
@@ -674,7 +674,8 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
           const double tf = face_after(o, r, ir, ta, m.voxel, m.inv_voxel);
           if (tf < tb) {
             probe = true;
-            te = tf - ta > 2.0 * kRefinePair ? tf - kRefinePair : fmin(tf + kRefinePair, 0.5 * (tf + tb));
+            te = tf - ta > 2.0 * kRefinePair ? tf - kRefinePair
+                                             : fmin(tf + kRefinePair, 0.5 * (tf + tb));
             te2 = te;
           } else {
             const double tc = 0.5 * (ta + tb);
@@ -743,7 +744,7 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
       const int sub = (cp.lo[0] >> 2) | ((cp.lo[1] >> 2) << 1) | ((cp.lo[2] >> 2) << 2);
       const bool pos_sub = (cinfo >> sub) & 1u;
       bool pos_cell = pos_sub;
-      int ext = 4;   // edge of the positive box in cells: 4 (sub-block), 2 (cell pair group), 1
+      int ext = 4;   // edge of the positive box in cells: 4 (sub-block), 2 (cell group), 1
       if (!pos_sub) {
         // the cell, and the aligned 2x2x2 group of cells holding it (both slices of the pair)
         const uint64_t w0 = cwl[(cp.lo[2] & 6) * 64], w1 = cwl[((cp.lo[2] & 6) + 1) * 64];
@@ -910,9 +911,9 @@ __device__ void render_pixel(const MapView& m, const RenderArgs& a, int u, int v
             if (side == -1) fa *= 0.5f;
             side = -1;
           }
-          // a false-position step that shrank the bracket by less than a tenth (one end
-          // keeps a value far from the root, e.g. behind a jump of f at a cell face) is
-          // followed by a bisection
+          // a step that shrank the bracket by less than a tenth (one end keeps a value far
+          // from the root, e.g. behind a jump of f at a cell face), or a face probe that
+          // leaves a face inside the bracket, is followed by a face probe or bisection
           bisect = (tb - ta) > 0.9 * w0 ||
                    (probe && face_after(o, r, ir, ta, m.voxel, m.inv_voxel) < tb);
           // Newton step from the pair's slope, kept when it lands within a quarter of the
