@@ -1,8 +1,8 @@
 // Ray-cast rendering of the Directional TSDF (Sec. 4).
 //
 // One thread per pixel; a workgroup is one wave covering a work tile of 64 pixels (a single
-// view's taken as 2x2 quads interleaved over a 128x32 pixel region, see tile_pixel; a
-// batched launch's an 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher
+// view's or a small batch's taken as 2x2 quads interleaved over a 128x32 pixel region, see
+// tile_pixel; a large batch's an 8x8 tile).  Tiles are numbered so that the workgroups the dispatcher
 // sends to one XCD (workgroup id mod 8) cover one contiguous band of the image, keeping each
 // band's bricks in that XCD's L2.  Per ray:
 //   * lattice t_k = t0 + k * step from z_near to z_far (Sec. 4: probing at regular intervals);
@@ -38,6 +38,7 @@ struct RenderArgs {
   int W, H;
   int tiles_x, tiles;     // 8x8 pixel tiles (the batched launch)
   int itiles_x, itiles;   // interleaved work tiles (the single-view launch, see tile_pixel)
+  int ilv;                // batched launch: this view's work tiles are interleaved
   double fx, fy, cx, cy;
   double R[9], t[3];
   double z_near, z_far;
@@ -61,10 +62,13 @@ struct RenderArgs {
 // waves instead of holding one wave while the rest of the chip idles.  Interleaving makes a
 // wave's rays less coherent (more distinct blocks per pass; the quads keep four neighbouring
 // rays together), which costs total work; it pays only where the launch is bound by its
-// slowest waves, so the batched launch, whose views overlap their tails, keeps plain 8x8
-// tiles.  The tile grid is padded to whole groups; lanes whose pixel lies outside the image
-// start finished.
+// slowest waves.  A batched launch therefore interleaves only while its work is small (up to
+// kIlvBatchTiles 8x8 tiles, about three rounds of resident waves: one request's pyramid at up
+// to 848x480) and otherwise, its views overlapping their tails, keeps plain 8x8 tiles.  The
+// tile grid is padded to whole groups; lanes whose pixel lies outside the image start
+// finished.
 constexpr int kIlvX = 16, kIlvY = 4;
+constexpr int64_t kIlvBatchTiles = 9000;
 
 struct Trace {
   uint8_t* bricks;
@@ -1072,8 +1076,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     }
     const RenderArgs& a = reqs[lo];
     const int tile = item - prefix[lo];
-    const int u = (tile % a.tiles_x) * 8 + (threadIdx.x & 7);
-    const int v = (tile / a.tiles_x) * 8 + (threadIdx.x >> 3);
+    int u, v;
+    if (a.ilv) {
+      tile_pixel(a, tile, (int)(threadIdx.x & 63), u, v);
+    } else {
+      u = (tile % a.tiles_x) * 8 + (int)(threadIdx.x & 7);
+      v = (tile / a.tiles_x) * 8 + (int)(threadIdx.x >> 3);
+    }
     render_pixel<F, TRACE, G>(m, a, u, v, u < a.W && v < a.H);
   }
 }
@@ -1113,6 +1122,7 @@ bool fill_args(const dtsdf_intrinsics* intr, const double T[16], float z_near, f
   a.trace_slots = out->trace_slots;
   a.trace_counts = out->trace_counts;
   a.help = (out->flags & DTSDF_RENDER_ALONE) ? 0 : 1;
+  a.ilv = 0;
   return true;
 }
 
@@ -1182,6 +1192,16 @@ extern "C" dtsdf_status dtsdf_render_batch(const dtsdf_map* m, int32_t n,
     total += args[r].tiles;
   }
   prefix[n] = (int32_t)total;
+  if (total <= kIlvBatchTiles) {
+    // small batch: interleaved work tiles (see kIlvX)
+    total = 0;
+    for (int r = 0; r < n; ++r) {
+      args[r].ilv = 1;
+      prefix[r] = (int32_t)total;
+      total += args[r].itiles;
+    }
+    prefix[n] = (int32_t)total;
+  }
   uint8_t* dev = sg->dev;
   if (hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
     rs = DTSDF_E_HIP;
