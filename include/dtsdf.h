@@ -193,8 +193,10 @@ typedef struct {
 } dtsdf_render_req;
 
 /* Render n views (any sizes, any poses) of one map in a single persistent launch that hands
- * (view, 8x8 tile) work items to waves as they free up.  Every pixel is computed exactly as
- * by dtsdf_render, so each view is bitwise identical to rendering it alone.  Serves many
+ * (view, work tile of 64 pixels) items to waves as they free up (8x8 tiles; a batch of at
+ * most 9000 such tiles uses the interleaved work tiles of a single-view launch).  Every pixel
+ * is computed exactly as by dtsdf_render, so each view is bitwise identical to rendering it
+ * alone.  Serves many
  * sensors at once (continuous batching of render requests).  Enqueues on `stream`. */
 dtsdf_status dtsdf_render_batch(const dtsdf_map* map, int32_t n, const dtsdf_render_req* reqs,
                                 void* stream);
